@@ -1,0 +1,794 @@
+/*
+ * CPU ORACLE for the per-timestep vehicle update of the MANTA traffic
+ * microsimulation (Yedavalli, Kumar, Waddell, arXiv 2007.03614).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product imports, links or calls
+ * this file; it is built and used by the test-suite, by the smoke check and by
+ * the CPU-baseline leg of the benchmark.  It shares no code with the HIP path:
+ * both are written separately from the same written step contract.
+ *
+ * It is deliberately plain: per-lane vehicle lists rebuilt by bucket + insertion
+ * sort every phase, brute-force admission, one vehicle at a time in id order.
+ *
+ * Precision.  The paper fixes none.  Compiled with REAL=float (default) it is
+ * the parity oracle: every FP32 operation in the order written below, no
+ * contraction (-ffp-contract=off), so that discrete events can be compared
+ * bit for bit.  Compiled with REAL=double it is the FP64 twin used to report
+ * how far FP32 trajectories drift (same algorithm, same random integers).
+ *
+ * Paper passages followed (sections of the paper):
+ *   Sec. II-D  time step dt = 0.5 s;
+ *   Sec. II-D  lanes are 1-D rows where a vehicle finds its neighbours by
+ *              lookup (the traffic atlas), at most one vehicle per place;
+ *   Eq. (1)    Intelligent Driver Model acceleration; position and speed from
+ *              integrating it twice;
+ *   Table I and Sec. IV-A  parameter bounds and delta = 4;
+ *   Eq. (2)    probability of a mandatory lane change, x0 = 1;
+ *   Eqs. (3)-(4) critical lead and lag gaps with anticipation times
+ *              alpha in [0.05, 0.40] and N(0,1) noise in metres;
+ *   Sec. II-D (intersections, case 2)  all-green nodes, finite edge capacity.
+ * Where the paper is silent the readings are the ones listed in the design
+ * notes (A1..A24); each is named at the place it is used.
+ *
+ * Parity pins: see tests/test_oracle_*.py (closed forms of Eq. (1), the
+ * platoon equilibrium gap, Eq. (2) frequencies, Philox against numpy,
+ * exp against libm, brute-force leader and admission checks, invariants).
+ * Lane-change behaviour and the admission policy are pinned only by the
+ * written contract: parity unpinned by the paper.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef REAL
+#define REAL float
+#endif
+#define RL(c) ((REAL)(c))
+
+#ifdef ORACLE_FP64
+#define ORC_EXP(y) exp(y)
+#else
+#define ORC_EXP(y) orc_expf_c(y)
+#endif
+
+enum { WAITING = 0, ACTIVE = 1, ARRIVED = 2 };
+enum { K_FREE = 0, K_VEH = 1, K_STOP = 2, K_LOOK = 3 };
+enum {
+    C_ACTIVE_SUM, C_DEPARTED, C_ARRIVED, C_LANE_CHANGES, C_TRANSFERS, C_HOLDS,
+    C_INSERT_DENIED, C_MAND_TRIGGERS, C_STOP_BRANCH, C_CLAMP, C_WRONG_LANE_HOLDS,
+    C_WAIVED_EXITS, C_N
+};
+/* event flags of the last step (for brute-force tests) */
+enum {
+    EV_REQ = 1, EV_WIN = 2, EV_ARRIVE = 4, EV_WHOLD = 8, EV_CLAMP = 16, EV_STOPB = 32,
+    EV_ELIG = 64, EV_INSERT_REQ = 128, EV_MOVED = 256, EV_MAND_TRIG = 512
+};
+
+#define PATIENCE 60          /* A19: wrong-lane hold waived after 60 held steps */
+#define X0 1.0               /* Eq. (2): critical distance x0 = 1 (metres, A8) */
+#define Z_CUT 17.0           /* exp(-17) < 5e-8: no trigger beyond this */
+#define INCENTIVE 0.2        /* A9: discretionary incentive threshold, m/s^2 */
+#define V_25MPH 11.176       /* Eqs. (3)-(4) text: 25 mph in m/s */
+#define G_SLOW 3.0           /* A12: midpoint of 1-5 m below 25 mph */
+#define G_FAST 7.5           /* A12: midpoint of 5-10 m above 25 mph */
+#define S_MIN 0.1            /* A4: gap floor in the interaction term */
+
+/* ------------------------------------------------------------------ random numbers
+ * Philox4x64-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers: as easy
+ * as 1, 2, 3", SC'11), counter-based: no state is carried between steps.
+ * key = (seed, 0); counter = (t, vehicle id, stream, block).               */
+static void mulhilo64(uint64_t a, uint64_t b, uint64_t *hi, uint64_t *lo) {
+    unsigned __int128 p = (unsigned __int128)a * (unsigned __int128)b;
+    *hi = (uint64_t)(p >> 64);
+    *lo = (uint64_t)p;
+}
+
+void orc_philox4x64(const uint64_t ctr_in[4], const uint64_t key_in[2], uint64_t out[4]) {
+    uint64_t c0 = ctr_in[0], c1 = ctr_in[1], c2 = ctr_in[2], c3 = ctr_in[3];
+    uint64_t k0 = key_in[0], k1 = key_in[1];
+    for (int r = 0; r < 10; r++) {
+        uint64_t hi0, lo0, hi1, lo1;
+        mulhilo64(0xD2E7470EE14C6C93ULL, c0, &hi0, &lo0);
+        mulhilo64(0xCA5A826395121157ULL, c2, &hi1, &lo1);
+        uint64_t n0 = hi1 ^ c1 ^ k0;
+        uint64_t n1 = lo1;
+        uint64_t n2 = hi0 ^ c3 ^ k1;
+        uint64_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+        k0 += 0x9E3779B97F4A7C15ULL;
+        k1 += 0xBB67AE8584CAA73BULL;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+static void draw_block(uint64_t seed, int64_t t, int64_t id, int s, int blk, uint64_t w[4]) {
+    uint64_t c[4] = {(uint64_t)t, (uint64_t)id, (uint64_t)s, (uint64_t)blk};
+    uint64_t k[2] = {seed, 0};
+    orc_philox4x64(c, k, w);
+}
+
+/* U(t, id, s): top 24 bits of the first word, scaled to [0, 1). */
+REAL orc_uniform(uint64_t seed, int64_t t, int64_t id, int s) {
+    uint64_t w[4];
+    draw_block(seed, t, id, s, 0, w);
+    return (REAL)(w[0] >> 40) * RL(5.9604644775390625e-08); /* 2^-24, exact */
+}
+
+/* N(t, id, s): Irwin-Hall sum of twelve 24-bit uniforms, minus 6 (A14).
+ * Integers: S = sum of (w >> 40) over blocks 0..2 (12 words); the value is
+ * (S - 6*2^24) * 2^-24, converted once to REAL. */
+REAL orc_normal(uint64_t seed, int64_t t, int64_t id, int s) {
+    int64_t S = 0;
+    for (int blk = 0; blk < 3; blk++) {
+        uint64_t w[4];
+        draw_block(seed, t, id, s, blk, w);
+        for (int j = 0; j < 4; j++) S += (int64_t)(w[j] >> 40);
+    }
+    int32_t c = (int32_t)(S - 6 * 16777216LL);
+    return (REAL)c * RL(5.9604644775390625e-08);
+}
+
+/* ------------------------------------------------------------------ exp for Eq. (2)
+ * exp(y) for y in (-17, 0], FP32, every operation in this order:
+ * Cody-Waite reduction y = k ln2 + r with a two-part ln 2, a degree-7 Taylor
+ * polynomial of e^r in Horner form, and an exact scaling by 2^k.          */
+float orc_expf_c(float y) {
+    const float log2e = 1.44269502162933349609375f;       /* nearest float to 1/ln2 */
+    const float ln2_hi = 0.693145751953125f;               /* 0x3F317200, 16 bits */
+    const float ln2_lo = 1.428606765330187045e-06f;        /* ln2 - ln2_hi, rounded */
+    float kf = floorf(y * log2e + 0.5f);
+    float r = (y - kf * ln2_hi) - kf * ln2_lo;
+    float p = 1.0f / 5040.0f;
+    p = p * r + 1.0f / 720.0f;
+    p = p * r + 1.0f / 120.0f;
+    p = p * r + 1.0f / 24.0f;
+    p = p * r + 1.0f / 6.0f;
+    p = p * r + 0.5f;
+    p = p * r + 1.0f;
+    p = p * r + 1.0f;
+    int k = (int)kf;
+    union { uint32_t u; float f; } sc;
+    sc.u = (uint32_t)(k + 127) << 23;   /* 2^k, normal for k >= -126 */
+    return p * sc.f;
+}
+
+void orc_expf_c_batch(const float *in, float *out, int64_t n) {
+    for (int64_t i = 0; i < n; i++) out[i] = orc_expf_c(in[i]);
+}
+
+/* ------------------------------------------------------------------ Eq. (1)
+ * IDM acceleration, the order of operations fixed:
+ *   r = v/v0, r4 = (r*r)*(r*r), phi = a(1 - r4), floored at -b  (A3)
+ *   FREE: acc = phi
+ *   else: s_star = s0 + max(0, vT + v(v - vl)/(2 sqrt(ab)))       (A1)
+ *         acc = phi - a (s_star / max(s, 0.1))^2                  (A4)
+ * den = 2 sqrt(ab) is per class.  flags: bit0 free term floored, bit1 dyn
+ * term clipped at 0, bit2 gap floored. */
+REAL orc_idm(REAL v, REAL v0, REAL vl, REAL s, REAL T, REAL a, REAL b, REAL s0, REAL den,
+             int kind, int *flags) {
+    int fl = 0;
+    REAL r = v / v0;
+    REAL r2 = r * r;
+    REAL r4 = r2 * r2;
+    REAL phi = a * (RL(1.0) - r4);
+    if (phi < -b) { phi = -b; fl |= 1; }
+    REAL acc;
+    if (kind == K_FREE) {
+        acc = phi;
+    } else {
+        REAL dv = v - vl;
+        REAL dyn = (v * T) + ((v * dv) / den);
+        if (dyn < RL(0.0)) { dyn = RL(0.0); fl |= 2; }
+        REAL sst = s0 + dyn;
+        REAL se = s;
+        if (s < RL(S_MIN)) { se = RL(S_MIN); fl |= 4; }
+        REAL q = sst / se;
+        acc = phi - (a * (q * q));
+    }
+    if (flags) *flags = fl;
+    return acc;
+}
+
+/* Eqs. (3)-(4): critical gap before the noise is added, the max taken first,
+ * with g0 the desired gap at the merging vehicle's speed (A12).
+ *   lead: max(g0, (g0 + alpha_a v_i) + alpha_i (v_i - v_a))
+ *   lag:  max(g0, (g0 + alpha_i v_i) + alpha_b (v_i - v_b))              */
+REAL orc_crit_gap(REAL g0, REAL alpha_first, REAL v_i, REAL alpha_second, REAL v_other) {
+    REAL e = (g0 + alpha_first * v_i) + alpha_second * (v_i - v_other);
+    return e > g0 ? e : g0;
+}
+
+REAL orc_desired_gap(REAL v_i) { return v_i < RL(V_25MPH) ? RL(G_SLOW) : RL(G_FAST); }
+
+/* ------------------------------------------------------------------ simulation */
+typedef struct {
+    int *a;
+    int n, cap;
+} ivec;
+
+static int iv_push(ivec *v, int x) {
+    if (v->n == v->cap) {
+        int nc = v->cap ? 2 * v->cap : 8;
+        int *na = (int *)realloc(v->a, (size_t)nc * sizeof(int));
+        if (!na) return -1;
+        v->a = na;
+        v->cap = nc;
+    }
+    v->a[v->n++] = x;
+    return 0;
+}
+
+typedef struct orc_sim {
+    /* network */
+    int n_nodes, n_edges, n_lanes_total;
+    int *efrom, *eto, *lanes, *lane_base;
+    REAL *L, *lim;
+    int *conn_off, *conn_to;
+    uint8_t *conn_mask;
+    /* vehicles (static) */
+    int n;
+    int64_t *roff;
+    int *redges, *dep, *cls, *ins_lane;
+    REAL *alpha;
+    /* classes */
+    int nc;
+    REAL *v0f, *T, *a, *b, *s0, *len, *den;
+    REAL dt;
+    uint64_t seed;
+    /* dynamic state, indexed by vehicle id */
+    int t;
+    uint8_t *status;
+    int *edge, *k, *lane, *mand, *held, *ww;
+    REAL *x, *v;
+    double *tau_in, *t_arr;
+    int64_t cnt[C_N];
+    double *tt_sum;
+    int64_t *tt_cnt;
+    /* per-step scratch */
+    ivec *lst;          /* per global lane: vehicle ids, front first */
+    int *nlane;         /* post-LC lane */
+    REAL *xn, *vn;      /* post-Phase-2 position and speed */
+    int *tgt, *elig;    /* admission target lane (global) and eligibility */
+    uint64_t *key;
+    uint64_t *best;     /* per global lane: smallest eligible key */
+    /* last-step events */
+    int *ev_leader, *ev_kind, *ev_flags;
+} orc_sim;
+
+static int next_edge(const orc_sim *S, int i) {
+    int64_t pos = S->roff[i] + S->k[i] + 1;
+    return pos < S->roff[i + 1] ? S->redges[pos] : -1;
+}
+
+static int conn_mask_of(const orc_sim *S, int e, int f) {
+    for (int c = S->conn_off[e]; c < S->conn_off[e + 1]; c++)
+        if (S->conn_to[c] == f) return S->conn_mask[c];
+    return 0;
+}
+
+/* lane l of e may proceed to f (any lane may, if e is the last route edge) */
+static int allowed_lane(const orc_sim *S, int e, int f, int l) {
+    if (f < 0) return 1;
+    return (conn_mask_of(S, e, f) >> l) & 1;
+}
+
+static int lane_dist(const orc_sim *S, int e, int f, int l) {
+    int m = conn_mask_of(S, e, f), best = 1 << 20;
+    for (int q = 0; q < 8; q++)
+        if ((m >> q) & 1) { int d = q > l ? q - l : l - q; if (d < best) best = d; }
+    return best;
+}
+
+/* (x_j, id_j) > (x_i, id_i): j is ahead of i */
+static int ahead(REAL xj, int j, REAL xi, int i) { return xj > xi || (xj == xi && j > i); }
+
+/* rebuild every lane list from a lane assignment, front first */
+static void build_lanes(orc_sim *S, const int *lane_of, const REAL *pos) {
+    for (int g = 0; g < S->n_lanes_total; g++) S->lst[g].n = 0;
+    for (int i = 0; i < S->n; i++) {
+        if (S->status[i] != ACTIVE) continue;
+        iv_push(&S->lst[S->lane_base[S->edge[i]] + lane_of[i]], i);
+    }
+    for (int g = 0; g < S->n_lanes_total; g++) {
+        int *a = S->lst[g].a, n = S->lst[g].n;
+        for (int p = 1; p < n; p++) {
+            int cur = a[p], q = p - 1;
+            while (q >= 0 && ahead(pos[cur], cur, pos[a[q]], a[q])) { a[q + 1] = a[q]; q--; }
+            a[q + 1] = cur;
+        }
+    }
+}
+
+static void free_sim(orc_sim *S) {
+    if (!S) return;
+    void *ptrs[] = {S->efrom, S->eto, S->lanes, S->lane_base, S->L, S->lim, S->conn_off, S->conn_to,
+                    S->conn_mask, S->roff, S->redges, S->dep, S->cls, S->ins_lane, S->alpha, S->v0f,
+                    S->T, S->a, S->b, S->s0, S->len, S->den, S->status, S->edge, S->k, S->lane,
+                    S->mand, S->held, S->ww, S->x, S->v, S->tau_in, S->t_arr, S->tt_sum, S->tt_cnt,
+                    S->nlane, S->xn, S->vn, S->tgt, S->elig, S->key, S->best, S->ev_leader,
+                    S->ev_kind, S->ev_flags};
+    for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
+    if (S->lst) {
+        for (int g = 0; g < S->n_lanes_total; g++) free(S->lst[g].a);
+        free(S->lst);
+    }
+    free(S);
+}
+
+void orc_destroy(orc_sim *S) { free_sim(S); }
+
+#define ALLOC(p, cnt) do { (p) = calloc((size_t)((cnt) > 0 ? (cnt) : 1), sizeof(*(p))); if (!(p)) { free_sim(S); return NULL; } } while (0)
+
+/* The oracle trusts its inputs (the product validates); tests feed it only
+ * generator output. */
+orc_sim *orc_create(int32_t n_nodes, int32_t n_edges, const int32_t *edge_from, const int32_t *edge_to,
+                    const float *length, const float *limit, const uint8_t *lanes,
+                    const int32_t *conn_off, const int32_t *conn_to, const uint8_t *conn_mask,
+                    int32_t n_veh, const int64_t *route_off, const int32_t *route_edges,
+                    const int32_t *depart_step, const uint8_t *vclass, const float *alpha,
+                    int32_t n_classes, const float *v0f, const float *T, const float *a,
+                    const float *b, const float *s0, const float *vlen, float dt, uint64_t seed) {
+    orc_sim *S = (orc_sim *)calloc(1, sizeof(orc_sim));
+    if (!S) return NULL;
+    S->n_nodes = n_nodes;
+    S->n_edges = n_edges;
+    ALLOC(S->efrom, n_edges); ALLOC(S->eto, n_edges); ALLOC(S->lanes, n_edges);
+    ALLOC(S->lane_base, n_edges + 1); ALLOC(S->L, n_edges); ALLOC(S->lim, n_edges);
+    ALLOC(S->conn_off, n_edges + 1);
+    int n_conn = conn_off[n_edges];
+    ALLOC(S->conn_to, n_conn); ALLOC(S->conn_mask, n_conn);
+    for (int e = 0; e < n_edges; e++) {
+        S->efrom[e] = edge_from[e]; S->eto[e] = edge_to[e]; S->lanes[e] = lanes[e];
+        S->L[e] = (REAL)length[e]; S->lim[e] = (REAL)limit[e];
+        S->lane_base[e + 1] = S->lane_base[e] + lanes[e];
+    }
+    S->n_lanes_total = S->lane_base[n_edges];
+    for (int e = 0; e <= n_edges; e++) S->conn_off[e] = conn_off[e];
+    for (int c = 0; c < n_conn; c++) { S->conn_to[c] = conn_to[c]; S->conn_mask[c] = conn_mask[c]; }
+    S->n = n_veh;
+    ALLOC(S->roff, n_veh + 1);
+    int64_t n_re = route_off[n_veh];
+    ALLOC(S->redges, n_re);
+    for (int i = 0; i <= n_veh; i++) S->roff[i] = route_off[i];
+    for (int64_t q = 0; q < n_re; q++) S->redges[q] = route_edges[q];
+    ALLOC(S->dep, n_veh); ALLOC(S->cls, n_veh); ALLOC(S->alpha, n_veh); ALLOC(S->ins_lane, n_veh);
+    S->nc = n_classes;
+    ALLOC(S->v0f, n_classes); ALLOC(S->T, n_classes); ALLOC(S->a, n_classes); ALLOC(S->b, n_classes);
+    ALLOC(S->s0, n_classes); ALLOC(S->len, n_classes); ALLOC(S->den, n_classes);
+    for (int c = 0; c < n_classes; c++) {
+        S->v0f[c] = (REAL)v0f[c]; S->T[c] = (REAL)T[c]; S->a[c] = (REAL)a[c];
+        S->b[c] = (REAL)b[c]; S->s0[c] = (REAL)s0[c]; S->len[c] = (REAL)vlen[c];
+#ifdef ORACLE_FP64
+        S->den[c] = 2.0 * sqrt(S->a[c] * S->b[c]);
+#else
+        S->den[c] = 2.0f * sqrtf(S->a[c] * S->b[c]);
+#endif
+    }
+    S->dt = (REAL)dt;
+    S->seed = seed;
+    ALLOC(S->status, n_veh); ALLOC(S->edge, n_veh); ALLOC(S->k, n_veh); ALLOC(S->lane, n_veh);
+    ALLOC(S->mand, n_veh); ALLOC(S->held, n_veh); ALLOC(S->ww, n_veh); ALLOC(S->x, n_veh);
+    ALLOC(S->v, n_veh); ALLOC(S->tau_in, n_veh); ALLOC(S->t_arr, n_veh);
+    ALLOC(S->tt_sum, n_edges); ALLOC(S->tt_cnt, n_edges);
+    ALLOC(S->nlane, n_veh); ALLOC(S->xn, n_veh); ALLOC(S->vn, n_veh); ALLOC(S->tgt, n_veh);
+    ALLOC(S->elig, n_veh); ALLOC(S->key, n_veh); ALLOC(S->best, S->n_lanes_total);
+    ALLOC(S->ev_leader, n_veh); ALLOC(S->ev_kind, n_veh); ALLOC(S->ev_flags, n_veh);
+    S->lst = (ivec *)calloc((size_t)(S->n_lanes_total > 0 ? S->n_lanes_total : 1), sizeof(ivec));
+    if (!S->lst) { free_sim(S); return NULL; }
+    for (int i = 0; i < n_veh; i++) {
+        S->dep[i] = depart_step[i];
+        S->cls[i] = vclass[i];
+        S->alpha[i] = (REAL)alpha[i];
+        S->status[i] = WAITING;
+        S->edge[i] = route_edges[route_off[i]];
+        S->k[i] = 0;
+        S->held[i] = -1;
+        S->tau_in[i] = -1.0;
+        S->t_arr[i] = -1.0;
+        /* A18: departures enter the lowest lane that may take the second route
+         * edge (lane 0 for a one-edge route) */
+        int e0 = route_edges[route_off[i]];
+        int il = 0;
+        if (route_off[i + 1] - route_off[i] > 1) {
+            int m = conn_mask_of(S, e0, route_edges[route_off[i] + 1]);
+            while (il < 7 && !((m >> il) & 1)) il++;
+        }
+        S->ins_lane[i] = il;
+        S->lane[i] = il;
+    }
+    return S;
+}
+
+/* ------------------------------------------------------------------ one step
+ * Four phases over the synchronous state S_t (every read below is of S_t
+ * unless it says otherwise); S_{t+1} is written only in Phase 4.          */
+static void step_once(orc_sim *S) {
+    const int t = S->t;
+    const int n = S->n;
+    int n_active = 0;
+    for (int i = 0; i < n; i++) {
+        S->ev_leader[i] = -1; S->ev_kind[i] = -1; S->ev_flags[i] = 0;
+        if (S->status[i] == ACTIVE) n_active++;
+    }
+    S->cnt[C_ACTIVE_SUM] += n_active;
+
+    /* S_t lane lists (front first); M_t rear of a lane = its last entry */
+    build_lanes(S, S->lane, S->x);
+
+    /* ---- Phase 1: lane changes (Eqs. (2)-(4); A8-A15).  All changes in a
+     * step go the same direction (A15), so checking both gaps >= 0 against the
+     * S_t neighbours keeps the post-change lanes free of overlap. */
+    const int dir = (t % 2 == 0) ? -1 : +1;
+    for (int i = 0; i < n; i++) {
+        S->nlane[i] = S->lane[i];
+        if (S->status[i] != ACTIVE || S->held[i] >= 0) continue;
+        const int e = S->edge[i], l = S->lane[i], f = next_edge(S, i), c = S->cls[i];
+        const int allowed_l = allowed_lane(S, e, f, l);
+        /* Eq. (2): mandatory with probability exp(-(d - x0)^2), 1 within x0 */
+        if (!allowed_l && !S->mand[i]) {
+            REAL d = S->L[e] - S->x[i];
+            if (d <= RL(X0)) {
+                S->mand[i] = 1; S->cnt[C_MAND_TRIGGERS]++; S->ev_flags[i] |= EV_MAND_TRIG;
+            } else {
+                REAL dm = d - RL(X0);
+                REAL z = dm * dm;
+                if (z < RL(Z_CUT) && orc_uniform(S->seed, t, i, 1) < (REAL)ORC_EXP(-z)) {
+                    S->mand[i] = 1; S->cnt[C_MAND_TRIGGERS]++; S->ev_flags[i] |= EV_MAND_TRIG;
+                }
+            }
+        }
+        const int lp = l + dir;
+        if (lp < 0 || lp >= S->lanes[e]) continue;
+        const int allowed_lp = allowed_lane(S, e, f, lp);
+        /* S_t neighbours: same-lane leader, and lead a / lag b in lane lp */
+        ivec *own = &S->lst[S->lane_base[e] + l];
+        int lead_cur = -1;
+        for (int p = 0; p < own->n; p++)
+            if (own->a[p] == i) { if (p > 0) lead_cur = own->a[p - 1]; break; }
+        ivec *tl = &S->lst[S->lane_base[e] + lp];
+        int la = -1, lb = -1;
+        for (int p = 0; p < tl->n; p++) {
+            int j = tl->a[p];
+            if (ahead(S->x[j], j, S->x[i], i)) la = j;
+            else { lb = j; break; }
+        }
+        /* desire: route-motivated (towards the allowed lanes) or incentive */
+        int desire = (!allowed_l) && (lane_dist(S, e, f, lp) < lane_dist(S, e, f, l));
+        if (!desire && allowed_lp && !(S->mand[i] && !allowed_l)) {
+            REAL v0 = S->v0f[c] * S->lim[e];
+            REAL acc_cur, acc_new;
+            if (lead_cur >= 0) {
+                REAL s = (S->x[lead_cur] - S->len[S->cls[lead_cur]]) - S->x[i];
+                acc_cur = orc_idm(S->v[i], v0, S->v[lead_cur], s, S->T[c], S->a[c], S->b[c], S->s0[c],
+                                  S->den[c], K_VEH, NULL);
+            } else {
+                acc_cur = orc_idm(S->v[i], v0, RL(0), RL(0), S->T[c], S->a[c], S->b[c], S->s0[c],
+                                  S->den[c], K_FREE, NULL);
+            }
+            if (la >= 0) {
+                REAL s = (S->x[la] - S->len[S->cls[la]]) - S->x[i];
+                acc_new = orc_idm(S->v[i], v0, S->v[la], s, S->T[c], S->a[c], S->b[c], S->s0[c],
+                                  S->den[c], K_VEH, NULL);
+            } else {
+                acc_new = orc_idm(S->v[i], v0, RL(0), RL(0), S->T[c], S->a[c], S->b[c], S->s0[c],
+                                  S->den[c], K_FREE, NULL);
+            }
+            desire = (acc_new - acc_cur) > RL(INCENTIVE);
+        }
+        if (!desire) continue;
+        /* Eqs. (3)-(4): gap acceptance with N(0,1) noise (A11-A14) */
+        const REAL vi = S->v[i];
+        const REAL g0 = orc_desired_gap(vi);
+        int ok = 1;
+        if (la >= 0) {
+            REAL G = (S->x[la] - S->len[S->cls[la]]) - S->x[i];
+            REAL g = orc_crit_gap(g0, S->alpha[la], vi, S->alpha[i], S->v[la]) + orc_normal(S->seed, t, i, 2);
+            REAL need = g > RL(0) ? g : RL(0);
+            ok = ok && (G >= need);
+        }
+        if (lb >= 0) {
+            REAL G = (S->x[i] - S->len[c]) - S->x[lb];
+            REAL g = orc_crit_gap(g0, S->alpha[i], vi, S->alpha[lb], S->v[lb]) + orc_normal(S->seed, t, i, 3);
+            REAL need = g > RL(0) ? g : RL(0);
+            ok = ok && (G >= need);
+        }
+        if (!ok) continue;
+        S->nlane[i] = lp;
+        S->ev_flags[i] |= EV_MOVED;
+        S->cnt[C_LANE_CHANGES]++;
+        if (allowed_lp) { S->mand[i] = 0; S->ww[i] = 0; }
+    }
+
+    /* M_t rears (pre-change lanes) are needed for look-ahead: keep them */
+    int *mrear = (int *)malloc((size_t)(S->n_lanes_total > 0 ? S->n_lanes_total : 1) * sizeof(int));
+    for (int g = 0; g < S->n_lanes_total; g++)
+        mrear[g] = S->lst[g].n ? S->lst[g].a[S->lst[g].n - 1] : -1;
+
+    /* ---- Phase 2: leader on the post-change lane, Eq. (1), integration */
+    build_lanes(S, S->nlane, S->x);
+    for (int i = 0; i < n; i++) {
+        if (S->status[i] != ACTIVE) continue;
+        const int e = S->edge[i], l = S->nlane[i], f = next_edge(S, i), c = S->cls[i];
+        const int allowed_l = allowed_lane(S, e, f, l);
+        ivec *own = &S->lst[S->lane_base[e] + l];
+        int j = -1;
+        for (int p = 0; p < own->n; p++)
+            if (own->a[p] == i) { if (p > 0) j = own->a[p - 1]; break; }
+        int kind;
+        REAL s = RL(0), vl = RL(0);
+        if (j >= 0) {
+            kind = K_VEH;
+            s = (S->x[j] - S->len[S->cls[j]]) - S->x[i];
+            vl = S->v[j];
+        } else if (f < 0) {
+            kind = K_FREE;
+        } else if (S->mand[i] && !allowed_l && S->ww[i] < PATIENCE) {
+            kind = K_STOP;                       /* A8: stop at the stop line */
+            s = S->L[e] - S->x[i];
+            vl = RL(0);
+        } else {
+            /* look ahead into (f, min(l, lanes_f - 1)) of M_t (A17) */
+            int lam = l < S->lanes[f] - 1 ? l : S->lanes[f] - 1;
+            int r = mrear[S->lane_base[f] + lam];
+            if (r >= 0) {
+                kind = K_LOOK;
+                s = (S->L[e] - S->x[i]) + (S->x[r] - S->len[S->cls[r]]);
+                vl = S->v[r];
+            } else {
+                kind = K_FREE;
+            }
+        }
+        S->ev_leader[i] = j;
+        S->ev_kind[i] = kind;
+        REAL v0 = S->v0f[c] * S->lim[e];
+        REAL acc = orc_idm(S->v[i], v0, vl, s, S->T[c], S->a[c], S->b[c], S->s0[c], S->den[c], kind, NULL);
+        /* A5: ballistic update with an exact stop */
+        const REAL dt = S->dt;
+        REAL vnew = S->v[i] + (acc * dt);
+        REAL xnew;
+        if (vnew >= RL(0)) {
+            xnew = (S->x[i] + (S->v[i] * dt)) + ((RL(0.5) * acc) * (dt * dt));
+        } else {
+            xnew = S->x[i] - ((S->v[i] * S->v[i]) / (RL(2.0) * acc));
+            vnew = RL(0);
+            S->cnt[C_STOP_BRANCH]++;
+            S->ev_flags[i] |= EV_STOPB;
+        }
+        /* A7: never past the leader's S_t rear */
+        if (kind == K_VEH) {
+            REAL rear = S->x[j] - S->len[S->cls[j]];
+            if (xnew > rear) { xnew = rear; S->cnt[C_CLAMP]++; S->ev_flags[i] |= EV_CLAMP; }
+        }
+        /* A8/A19: a wrong-lane vehicle waits at the stop line */
+        if (f >= 0 && !allowed_l && S->ww[i] < PATIENCE && xnew >= S->L[e]) {
+            xnew = S->L[e];
+            vnew = RL(0);
+            S->mand[i] = 1;
+            S->ww[i] += 1;
+            S->cnt[C_WRONG_LANE_HOLDS]++;
+            S->ev_flags[i] |= EV_WHOLD;
+        }
+        S->xn[i] = xnew;
+        S->vn[i] = vnew;
+    }
+    free(mrear);
+
+    /* ---- Phase 3: end of edge and admission (case 2 intersections, A16-A18).
+     * rear'(g, lam) = the active vehicle with the smallest (x_new, id) in the
+     * post-change lane; it still counts if it is leaving itself. */
+    for (int g = 0; g < S->n_lanes_total; g++) S->best[g] = UINT64_MAX;
+    int *rearp = (int *)malloc((size_t)(S->n_lanes_total > 0 ? S->n_lanes_total : 1) * sizeof(int));
+    for (int g = 0; g < S->n_lanes_total; g++) {
+        int r = -1;
+        for (int p = 0; p < S->lst[g].n; p++) {
+            int q = S->lst[g].a[p];
+            if (r < 0 || ahead(S->xn[r], r, S->xn[q], q)) r = q;
+        }
+        rearp[g] = r;
+    }
+    for (int i = 0; i < n; i++) {
+        S->tgt[i] = -1;
+        S->elig[i] = 0;
+        if (S->status[i] == ACTIVE) {
+            const int e = S->edge[i], f = next_edge(S, i);
+            if (S->xn[i] >= S->L[e] && !(S->ev_flags[i] & EV_WHOLD)) {
+                if (f < 0) {
+                    S->ev_flags[i] |= EV_ARRIVE;
+                } else {
+                    int lam = S->nlane[i] < S->lanes[f] - 1 ? S->nlane[i] : S->lanes[f] - 1;
+                    int g = S->lane_base[f] + lam;
+                    REAL xp = S->xn[i] - S->L[e];
+                    int r = rearp[g];
+                    int ok = (r < 0) || ((S->xn[r] - S->len[S->cls[r]]) - xp >= RL(0));
+                    uint64_t hs = (uint64_t)(S->held[i] >= 0 ? S->held[i] : t);
+                    S->tgt[i] = g;
+                    S->elig[i] = ok;
+                    S->key[i] = (hs << 32) | (uint64_t)(uint32_t)i;
+                    S->ev_flags[i] |= EV_REQ | (ok ? EV_ELIG : 0);
+                }
+            }
+        } else if (S->status[i] == WAITING && S->dep[i] <= t) {
+            int g0e = S->redges[S->roff[i]];
+            int g = S->lane_base[g0e] + S->ins_lane[i];
+            int r = rearp[g];
+            int ok = (r < 0) || ((S->xn[r] - S->len[S->cls[r]]) >= S->s0[S->cls[i]]);
+            S->tgt[i] = g;
+            S->elig[i] = ok;
+            S->key[i] = (1ULL << 63) | ((uint64_t)(uint32_t)S->dep[i] << 32) | (uint64_t)(uint32_t)i;
+            S->ev_flags[i] |= EV_INSERT_REQ | (ok ? EV_ELIG : 0);
+        }
+        if (S->tgt[i] >= 0 && S->elig[i] && S->key[i] < S->best[S->tgt[i]]) S->best[S->tgt[i]] = S->key[i];
+    }
+    free(rearp);
+
+    /* ---- Phase 4: commit, in ascending vehicle id (this is also the order of
+     * the per-edge travel-time sums, A22). */
+    for (int i = 0; i < n; i++) {
+        if (S->status[i] == ACTIVE) {
+            const int e = S->edge[i];
+            const int won = S->tgt[i] >= 0 && S->elig[i] && S->best[S->tgt[i]] == S->key[i];
+            if ((S->ev_flags[i] & EV_ARRIVE) || won) {
+                /* crossing time interpolated inside the step */
+                REAL phi = (S->xn[i] == S->x[i]) ? RL(0) : (S->L[e] - S->x[i]) / (S->xn[i] - S->x[i]);
+                double tau = ((double)t + (double)phi) * (double)S->dt;
+                S->tt_sum[e] += tau - S->tau_in[i];
+                S->tt_cnt[e] += 1;
+                if (S->ev_flags[i] & EV_ARRIVE) {
+                    S->status[i] = ARRIVED;
+                    S->t_arr[i] = tau;
+                    S->x[i] = S->xn[i];
+                    S->v[i] = S->vn[i];
+                    S->lane[i] = S->nlane[i];
+                    S->cnt[C_ARRIVED]++;
+                } else {
+                    const int f = next_edge(S, i);
+                    if (!allowed_lane(S, e, f, S->nlane[i])) S->cnt[C_WAIVED_EXITS]++;
+                    S->ev_flags[i] |= EV_WIN;
+                    S->x[i] = S->xn[i] - S->L[e];
+                    S->v[i] = S->vn[i];
+                    S->edge[i] = f;
+                    S->k[i] += 1;
+                    S->lane[i] = S->tgt[i] - S->lane_base[f];
+                    S->held[i] = -1;
+                    S->mand[i] = 0;
+                    S->ww[i] = 0;
+                    S->tau_in[i] = tau;
+                    S->cnt[C_TRANSFERS]++;
+                }
+            } else if (S->tgt[i] >= 0) {
+                /* a losing transfer waits at the stop line */
+                S->x[i] = S->L[e];
+                S->v[i] = RL(0);
+                S->lane[i] = S->nlane[i];
+                if (S->held[i] < 0) S->held[i] = t;
+                S->cnt[C_HOLDS]++;
+            } else {
+                S->x[i] = S->xn[i];
+                S->v[i] = S->vn[i];
+                S->lane[i] = S->nlane[i];
+            }
+        } else if (S->status[i] == WAITING && S->tgt[i] >= 0) {
+            if (S->elig[i] && S->best[S->tgt[i]] == S->key[i]) {
+                int e0 = S->redges[S->roff[i]];
+                S->status[i] = ACTIVE;
+                S->edge[i] = e0;
+                S->k[i] = 0;
+                S->lane[i] = S->tgt[i] - S->lane_base[e0];
+                S->x[i] = RL(0);
+                S->v[i] = RL(0);
+                S->held[i] = -1;
+                S->mand[i] = 0;
+                S->ww[i] = 0;
+                S->tau_in[i] = (double)(t + 1) * (double)S->dt;
+                S->ev_flags[i] |= EV_WIN;
+                S->cnt[C_DEPARTED]++;
+            } else {
+                S->cnt[C_INSERT_DENIED]++;
+            }
+        }
+    }
+    S->t = t + 1;
+}
+
+int orc_step(orc_sim *S, int32_t n_steps) {
+    for (int q = 0; q < n_steps; q++) step_once(S);
+    return 0;
+}
+
+int32_t orc_time(const orc_sim *S) { return S->t; }
+
+/* state out, indexed by vehicle id (x, v widened to double exactly) */
+void orc_read_state(const orc_sim *S, uint8_t *status, int32_t *edge, int32_t *lane, int32_t *cursor,
+                    double *x, double *v, int32_t *held_since, uint8_t *mand, int32_t *ww,
+                    double *tau_in, double *t_arr) {
+    for (int i = 0; i < S->n; i++) {
+        status[i] = S->status[i];
+        edge[i] = S->edge[i];
+        lane[i] = S->lane[i];
+        cursor[i] = S->k[i];
+        x[i] = (double)S->x[i];
+        v[i] = (double)S->v[i];
+        held_since[i] = S->held[i];
+        mand[i] = (uint8_t)S->mand[i];
+        ww[i] = S->ww[i];
+        tau_in[i] = S->tau_in[i];
+        t_arr[i] = S->t_arr[i];
+    }
+}
+
+/* overwrite the dynamic state (test scenarios built by hand) */
+void orc_write_state(orc_sim *S, int32_t t, const uint8_t *status, const int32_t *edge,
+                     const int32_t *lane, const int32_t *cursor, const double *x, const double *v,
+                     const int32_t *held_since, const uint8_t *mand, const int32_t *ww,
+                     const double *tau_in) {
+    S->t = t;
+    for (int i = 0; i < S->n; i++) {
+        S->status[i] = status[i];
+        S->edge[i] = edge[i];
+        S->lane[i] = lane[i];
+        S->k[i] = cursor[i];
+        S->x[i] = (REAL)x[i];
+        S->v[i] = (REAL)v[i];
+        S->held[i] = held_since[i];
+        S->mand[i] = mand[i];
+        S->ww[i] = ww[i];
+        S->tau_in[i] = tau_in[i];
+    }
+}
+
+void orc_counters(const orc_sim *S, int64_t *out) {
+    for (int q = 0; q < C_N; q++) out[q] = S->cnt[q];
+}
+
+int32_t orc_n_counters(void) { return C_N; }
+
+void orc_edge_stats(const orc_sim *S, double *tt_sum, int64_t *tt_cnt) {
+    for (int e = 0; e < S->n_edges; e++) { tt_sum[e] = S->tt_sum[e]; tt_cnt[e] = S->tt_cnt[e]; }
+}
+
+/* events of the last step: Phase-2 leader id (-1 none), kind, flags, and the
+ * post-Phase-2 position/speed before commit */
+void orc_last_events(const orc_sim *S, int32_t *leader, int32_t *kind, int32_t *flags, int32_t *post_lane,
+                     double *xnew, double *vnew, int32_t *target_lane) {
+    for (int i = 0; i < S->n; i++) {
+        leader[i] = S->ev_leader[i];
+        kind[i] = S->ev_kind[i];
+        flags[i] = S->ev_flags[i];
+        post_lane[i] = S->nlane[i];
+        xnew[i] = (double)S->xn[i];
+        vnew[i] = (double)S->vn[i];
+        target_lane[i] = S->tgt[i];
+    }
+}
+
+int32_t orc_real_bytes(void) { return (int32_t)sizeof(REAL); }
+
+/* Eq. (2) trigger test hook: does the draw at (t, id) fire at distance d? */
+int32_t orc_mand_trigger(uint64_t seed, int64_t t, int64_t id, double d_in) {
+    REAL d = (REAL)d_in;
+    if (d <= RL(X0)) return 1;
+    REAL dm = d - RL(X0);
+    REAL z = dm * dm;
+    return (z < RL(Z_CUT) && orc_uniform(seed, t, id, 1) < (REAL)ORC_EXP(-z)) ? 1 : 0;
+}
+
+/* scalar wrappers with double arguments, for the tests' ctypes layer */
+double orc_idm_d(double v, double v0, double vl, double s, double T, double a, double b, double s0,
+                 int32_t kind, int32_t *flags) {
+    REAL A = (REAL)a, B = (REAL)b;
+#ifdef ORACLE_FP64
+    REAL den = 2.0 * sqrt(A * B);
+#else
+    REAL den = 2.0f * sqrtf(A * B);
+#endif
+    return (double)orc_idm((REAL)v, (REAL)v0, (REAL)vl, (REAL)s, (REAL)T, A, B, (REAL)s0, den, kind, flags);
+}
+
+double orc_crit_gap_d(double g0, double af, double vi, double as, double vo) {
+    return (double)orc_crit_gap((REAL)g0, (REAL)af, (REAL)vi, (REAL)as, (REAL)vo);
+}
+
+double orc_desired_gap_d(double vi) { return (double)orc_desired_gap((REAL)vi); }
+double orc_uniform_d(uint64_t seed, int64_t t, int64_t id, int32_t s) { return (double)orc_uniform(seed, t, id, s); }
+double orc_normal_d(uint64_t seed, int64_t t, int64_t id, int32_t s) { return (double)orc_normal(seed, t, id, s); }
