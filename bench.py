@@ -1,0 +1,133 @@
+#!/usr/bin/env python3
+"""Benchmark of the per-timestep vehicle update on one MI355X.
+
+A "step" is one simulated time step (dt = 0.5 s) of the whole hot path:
+lane changes, leader search, IDM, integration, intersection admission and the
+rebuild of the sorted vehicle layout.  The default workload is the perturbed
+100x100 grid with a ring highway, 200,000 vehicles, timed over its full
+3-hour horizon (21,600 steps) from t = 0, with inputs already resident in
+device memory when the timed region starts.
+
+value = vehicle-updates/s = sum over the timed steps of the vehicles active at
+each step's start, divided by the device time of those steps (HIP events on
+the simulation's stream).  The roofline object covers the dominant kernel
+(k_tile_step): algorithmic bytes = 48 B per vehicle-update (read and write
+of the 24-byte sorted vehicle record), over its summed event-measured time.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_UPDATE = 48
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_step_traffic.json")
+
+
+def make_workload(name: str):
+    import workloads as W
+    if name == "perturbed_grid_ring":
+        return W.config2()
+    if name == "grid10x10":
+        return W.config1()
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(w, steps: int):
+    """The oracle as it stands, single-threaded, on the first `steps` steps."""
+    import oracle
+    s = oracle.OracleSim(w)
+    t0 = time.perf_counter()
+    s.step(steps)
+    dt = time.perf_counter() - t0
+    upd = s.counters()["active_sum"]
+    return {"value": upd / dt, "unit": "vehicle-updates/s", "cores": 1, "kind": "oracle",
+            "sample": f"steps 0-{steps} of the same workload ({upd} vehicle-updates, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=21600)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--workload", default="perturbed_grid_ring", choices=["perturbed_grid_ring", "grid10x10"])
+    ap.add_argument("--cpu-steps", type=int, default=3600, help="oracle sample length (0: skip)")
+    ap.add_argument("--graph", action="store_true", help="also time the captured-graph path")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation is "
+              "single-device and its multi-GPU sharding is not part of this build.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_2007_03614_amd as M
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = make_workload(args.workload)
+
+    # warm-up on its own handle (kernels, graph, caches), then a fresh handle
+    warm = M.Sim(w, stream=stream)
+    warm.step_timed(args.warmup)
+    warm.close()
+    sim = M.Sim(w, stream=stream)
+    before = sim.counters()["active_sum"]
+    torch.cuda.synchronize()
+    kernel_ms, total_ms = sim.step_timed(args.steps)
+    torch.cuda.synchronize()
+    upd = sim.counters()["active_sum"] - before
+    value = upd / (total_ms / 1e3)
+
+    extra = {}
+    if args.graph:
+        g = M.Sim(w, stream=stream)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        gms = e0.elapsed_time(e1)
+        extra["graph_path"] = {"ms_per_step": gms / args.steps, "value": upd / (gms / 1e3)}
+        g.close()
+
+    k1 = kernel_ms["k_tile_step"]
+    achieved = BYTES_PER_UPDATE * upd / (k1 / 1e3) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("workload") == args.workload:
+            traffic = tr.get("bytes_per_launch")
+    line = {
+        "metric": "vehicle-updates/sec (1 GPU)",
+        "value": value,
+        "unit": "vehicle-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "vehicles": w.n_vehicles, "edges": w.net.n_edges,
+                   "lanes": int(w.net.lanes.sum()), "dt_s": 0.5, "steps": args.steps,
+                   "vehicle_updates": int(upd)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
+        "kernel_ms": {k: round(v, 3) for k, v in kernel_ms.items()},
+    }
+    line.update(extra)
+    if args.cpu_steps > 0:
+        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,202 @@
+/*
+ * libmanta — per-timestep vehicle update of the MANTA traffic microsimulation
+ * (Yedavalli, Kumar, Waddell, arXiv 2007.03614) on AMD Instinct MI355X (gfx950).
+ *
+ * C ABI.  Plain pointers and sizes only.  Unless a comment says "device",
+ * every pointer argument is a HOST pointer: inputs are borrowed for the call
+ * and deep-copied; outputs are caller-owned buffers of the stated length.
+ *
+ * Conventions
+ *   - Every call returns sim_status; nothing throws or aborts across the ABI.
+ *   - On error the handle is left unchanged and sim_last_error() describes it.
+ *   - One handle is not thread-safe; separate handles are independent.
+ *   - Device memory comes from the allocator registered with
+ *     sim_set_allocator() (default: hipMalloc/hipFree).  All device work of a
+ *     handle runs on its stream (sim_set_stream; default: the null stream).
+ *
+ * What one step computes (Sec. II-D of the paper, with dt = 0.5 s):
+ *   for every active vehicle, find its leader on its lane, evaluate the
+ *   Intelligent Driver Model (Eq. (1)), decide lane changes (mandatory-change
+ *   probability Eq. (2), critical lead/lag gaps Eqs. (3)-(4)), advance
+ *   position and speed, and hand vehicles that reach the end of their edge
+ *   to the next edge of their fixed route through intersection admission
+ *   (case 2: every node green, finite lane capacity).
+ */
+#ifndef MANTA_H
+#define MANTA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim_handle sim_handle;   /* opaque; owns all its device memory */
+
+typedef enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,        /* an argument or input array is invalid */
+    SIM_ENOMEM = -2,        /* the allocator returned NULL */
+    SIM_EDEVICE = -3,       /* a HIP runtime call failed */
+    SIM_ESTATE = -4,        /* call not valid in the handle's current state */
+    SIM_EUNSUPPORTED = -5   /* a documented option that is not implemented */
+} sim_status;
+
+/* Road network (Sec. II-A): directed edges with lanes, length and speed limit;
+ * a CSR of allowed moves e -> f with a per-move lane mask (bit l set: lane l
+ * of e, counted from the right, may proceed to f). */
+typedef struct {
+    int32_t n_nodes, n_edges;
+    const int32_t *edge_from, *edge_to;   /* [n_edges] node ids */
+    const float *length_m;                /* [n_edges], >= 20 m */
+    const float *speed_limit_mps;         /* [n_edges], > 0 */
+    const uint8_t *n_lanes;               /* [n_edges], 1..8 */
+    const int32_t *conn_off;              /* [n_edges + 1], non-decreasing, conn_off[0] = 0 */
+    const int32_t *conn_to;               /* [conn_off[n_edges]] edge ids, from(f) == to(e) */
+    const uint8_t *conn_lane_mask;        /* [conn_off[n_edges]], non-zero, < 2^n_lanes[e] */
+} sim_network;
+
+/* Fixed routes computed before the simulation (Sec. II-C) and departures
+ * (Sec. II-D).  Vehicle id == index. */
+typedef struct {
+    int32_t n_vehicles;                   /* >= 0, < 2^31 */
+    const int64_t *route_off;             /* [n_vehicles + 1], route_off[0] = 0, strictly increasing */
+    const int32_t *route_edges;           /* consecutive edges connected by an allowed move */
+    const int32_t *depart_step;           /* [n_vehicles], >= 0: enters at the end of this step */
+    const uint8_t *vclass;                /* [n_vehicles], < n_classes */
+    const float *alpha_s;                 /* [n_vehicles], anticipation time, [0, 0.40] (Eqs. (3)-(4)) */
+} sim_routes;
+
+/* Car-following parameters per vehicle class (Eq. (1), Table I), bounds of
+ * Sec. IV-A: a, b in [1, 10] m/s^2, T in [0.1, 2] s, s0 in [1, 5] m;
+ * v0 = v0_factor * edge speed limit, v0_factor in (0, 2]; length in (0, 20] m. */
+typedef struct {
+    int32_t n_classes;                    /* 1..16 */
+    const float *v0_factor, *T, *a, *b, *s0, *length_m;   /* [n_classes] */
+    float dt;                             /* (0, 1]; the paper uses 0.5 s */
+    uint64_t seed;                        /* Philox key for the lane-change draws */
+    int32_t intersection_mode;            /* 0 = all green (case 2); 1 = flashing red -> SIM_EUNSUPPORTED */
+    int32_t record_every;                 /* reserved for the adjoint; must be 0 */
+} sim_idm_params;
+
+/* Per-vehicle state, all arrays [n_vehicles] indexed by vehicle id; any
+ * pointer may be NULL to skip that field.  status: 0 waiting, 1 active,
+ * 2 arrived.  For a waiting vehicle edge/lane are its first edge and entry
+ * lane and x = v = 0.  counters: [SIM_N_COUNTERS] (cumulative). */
+typedef struct {
+    uint8_t *status;
+    int32_t *edge, *lane, *cursor;
+    float *x, *v;                         /* metres from the edge start (front bumper), m/s */
+    int32_t *held_since;                  /* -1, or the step a held transfer was first refused */
+    uint8_t *mand;                        /* mandatory lane change pending (Eq. (2)) */
+    int32_t *ww;                          /* steps held at the stop line in a wrong lane */
+    double *tau_in;                       /* time the current edge was entered, s (-1 waiting) */
+    double *t_arr;                        /* arrival time, s (-1 not arrived) */
+    int64_t *counters;
+    int32_t t;                            /* out: current step */
+} sim_state;
+
+/* Cumulative counters (sim_state.counters order). */
+enum {
+    SIM_C_ACTIVE_SUM = 0,     /* sum over steps of vehicles active at the step's start */
+    SIM_C_DEPARTED,           /* admitted departures */
+    SIM_C_ARRIVED,
+    SIM_C_LANE_CHANGES,
+    SIM_C_TRANSFERS,          /* admitted edge-to-edge transfers */
+    SIM_C_HOLDS,              /* transfer requests refused (vehicle held at the stop line) */
+    SIM_C_INSERT_DENIED,      /* departure requests refused */
+    SIM_C_MAND_TRIGGERS,      /* mandatory lane-change flags raised by Eq. (2) */
+    SIM_C_STOP_BRANCH,        /* integration steps that ended in a stop */
+    SIM_C_CLAMP,              /* positions clamped to the leader's rear */
+    SIM_C_WRONG_LANE_HOLDS,   /* steps held at the stop line in a wrong lane */
+    SIM_C_WAIVED_EXITS,       /* transfers from a wrong lane after the patience ran out */
+    SIM_N_COUNTERS
+};
+
+/* Process-wide device allocator used by handles created afterwards.
+ * alloc(bytes, ctx) returns a device pointer or NULL; release(ptr, ctx).
+ * Pass NULL, NULL to restore hipMalloc/hipFree.  Both are called only from
+ * the thread calling sim_create or sim_destroy. */
+sim_status sim_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
+                             void (*release)(void *ptr, void *ctx), void *ctx);
+
+/* Validate and deep-copy the inputs, build the device layout, and leave the
+ * simulation at step 0 with every vehicle waiting.  Validation: node ids in
+ * range, lanes 1..8, length >= 20 m, limit > 0 and finite, moves connect
+ * (from(f) == to(e)) with a non-empty lane mask inside the lanes of e, every
+ * route non-empty with consecutive edges joined by a move, depart_step >= 0,
+ * class ids in range, alpha finite in [0, 0.40], parameters finite and in the
+ * bounds above.  Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_EUNSUPPORTED. */
+sim_status sim_create(const sim_network *net, const sim_routes *routes, const sim_idm_params *params,
+                      sim_handle **out);
+
+/* Stream for all later device work of h (a hipStream_t; NULL = null stream).
+ * The captured step graph is launched on this stream. */
+sim_status sim_set_stream(sim_handle *h, void *hip_stream);
+
+/* Enqueue n >= 0 steps on the handle's stream and return (asynchronous). */
+sim_status sim_step(sim_handle *h, int32_t n);
+
+/* Measurement form of sim_step: the n steps are launched kernel by kernel
+ * (not from the captured graph) with a HIP event recorded on the handle's
+ * stream before the first kernel of the run and after every kernel; then the
+ * stream is synchronized.  kernel_ms[SIM_N_KERNELS] (may be NULL) receives
+ * the summed time between consecutive events attributed to each kernel of
+ * the step, total_ms (may be NULL) the time from the first to the last event.
+ * Results are identical to sim_step. */
+enum {
+    SIM_K_TILE_STEP = 0,   /* lane changes, leaders, Eq. (1), integration */
+    SIM_K_ADMIT,           /* intersection admission: eligibility + priority */
+    SIM_K_COMMIT,          /* transfers, arrivals, departures, travel times */
+    SIM_K_EDGE_COUNT,
+    SIM_K_BLOCK_SCAN,
+    SIM_K_EDGE_OFFSET,
+    SIM_K_SCATTER,         /* next sorted layout and look-ahead table */
+    SIM_N_KERNELS
+};
+sim_status sim_step_timed(sim_handle *h, int32_t n, double *kernel_ms, double *total_ms);
+
+/* Synchronize the stream and copy the state out (vehicle-id order). */
+sim_status sim_read_state(sim_handle *h, sim_state *out);
+
+/* Replace the dynamic state (resume from a state read earlier).  Every
+ * non-NULL field is required except counters (kept if NULL).  The edge
+ * travel-time sums are kept.  SIM_EINVAL if the state is inconsistent
+ * (edge not at the cursor of the route, lane out of range, x outside
+ * [0, length], overlapping vehicles in a lane). */
+sim_status sim_write_state(sim_handle *h, const sim_state *in);
+
+/* Per-edge sums of completed traversal times (s, FP64, accumulated each step
+ * in ascending vehicle id) and traversal counts: [n_edges] each. */
+sim_status sim_read_edge_stats(sim_handle *h, double *tt_sum, int64_t *tt_count);
+
+/* Number of vehicles active at the start of the current step (synchronizes). */
+sim_status sim_n_active(sim_handle *h, int32_t *out);
+
+/* Release every device buffer of h.  NULL is a no-op. */
+sim_status sim_destroy(sim_handle *h);
+
+/* Message of the last failed call on h (or of the last failed sim_create when
+ * h is NULL).  Valid until the next call on the same handle. */
+const char *sim_last_error(const sim_handle *h);
+
+/* ------------------------------------------------------------------ diagnostics
+ * Device-side evaluation of the arithmetic building blocks, for checking that
+ * the GPU rounds exactly like IEEE-754 binary32 on the host.  op: 0 a/b,
+ * 1 sqrt(a), 2 a*b, 3 a+b, 4 exp of Eq. (2)'s evaluator on a (a in (-17, 0]).
+ * a, b, out: [n] host arrays. */
+sim_status sim_probe_fp32(int32_t op, const float *a, const float *b, float *out, int64_t n);
+
+/* Device Philox4x64-10 blocks: counters [n][4], key [2] -> out [n][4]. */
+sim_status sim_probe_philox(const uint64_t *counters, const uint64_t *key, uint64_t *out, int64_t n);
+
+/* Device lane-change draws: uniform (stream 1) and normal (streams 2, 3)
+ * for n (t, id) pairs -> u [n], e2 [n], e3 [n]. */
+sim_status sim_probe_draws(uint64_t seed, const int64_t *t, const int64_t *id, float *u, float *e2, float *e3,
+                           int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MANTA_H */

@@ -1,0 +1,300 @@
+"""Python binding of libmanta (the per-timestep vehicle update on MI355X).
+
+Argument marshalling only: every step of the simulation runs in the HIP
+kernels behind the C ABI declared in ``include/manta.h``.  PyTorch provides
+device memory (its caching allocator, registered with ``sim_set_allocator``)
+and streams.  There is no CPU fallback: if ``libmanta.so`` is missing the
+import fails.
+"""
+from __future__ import annotations
+
+import atexit
+import ctypes
+import os
+import weakref
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmanta.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"libmanta.so is not built ({LIB_PATH}); run __graft_entry__.build() first")
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+COUNTERS = ["active_sum", "departed", "arrived", "lane_changes", "transfers", "holds",
+            "insert_denied", "mand_triggers", "stop_branch", "clamp", "wrong_lane_holds",
+            "waived_exits"]
+STATUS = {"SIM_OK": 0, "SIM_EINVAL": -1, "SIM_ENOMEM": -2, "SIM_EDEVICE": -3, "SIM_ESTATE": -4,
+          "SIM_EUNSUPPORTED": -5}
+_STATUS_NAME = {v: k for k, v in STATUS.items()}
+
+P = ctypes.c_void_p
+I32, I64, U64, F32 = ctypes.c_int32, ctypes.c_int64, ctypes.c_uint64, ctypes.c_float
+
+
+class SimNetwork(ctypes.Structure):
+    _fields_ = [("n_nodes", I32), ("n_edges", I32), ("edge_from", P), ("edge_to", P), ("length_m", P),
+                ("speed_limit_mps", P), ("n_lanes", P), ("conn_off", P), ("conn_to", P),
+                ("conn_lane_mask", P)]
+
+
+class SimRoutes(ctypes.Structure):
+    _fields_ = [("n_vehicles", I32), ("route_off", P), ("route_edges", P), ("depart_step", P),
+                ("vclass", P), ("alpha_s", P)]
+
+
+class SimIdmParams(ctypes.Structure):
+    _fields_ = [("n_classes", I32), ("v0_factor", P), ("T", P), ("a", P), ("b", P), ("s0", P),
+                ("length_m", P), ("dt", F32), ("seed", U64), ("intersection_mode", I32),
+                ("record_every", I32)]
+
+
+class SimState(ctypes.Structure):
+    _fields_ = [("status", P), ("edge", P), ("lane", P), ("cursor", P), ("x", P), ("v", P),
+                ("held_since", P), ("mand", P), ("ww", P), ("tau_in", P), ("t_arr", P), ("counters", P),
+                ("t", I32)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(P, ctypes.c_size_t, P)
+_FREE_FN = ctypes.CFUNCTYPE(None, P, P)
+
+_lib.sim_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
+_lib.sim_set_allocator.restype = I32
+_lib.sim_create.argtypes = [ctypes.POINTER(SimNetwork), ctypes.POINTER(SimRoutes),
+                            ctypes.POINTER(SimIdmParams), ctypes.POINTER(P)]
+_lib.sim_create.restype = I32
+_lib.sim_set_stream.argtypes = [P, P]
+_lib.sim_set_stream.restype = I32
+_lib.sim_step.argtypes = [P, I32]
+_lib.sim_step.restype = I32
+_lib.sim_step_timed.argtypes = [P, I32, P, P]
+_lib.sim_step_timed.restype = I32
+_lib.sim_read_state.argtypes = [P, ctypes.POINTER(SimState)]
+_lib.sim_read_state.restype = I32
+_lib.sim_write_state.argtypes = [P, ctypes.POINTER(SimState)]
+_lib.sim_write_state.restype = I32
+_lib.sim_read_edge_stats.argtypes = [P, P, P]
+_lib.sim_read_edge_stats.restype = I32
+_lib.sim_n_active.argtypes = [P, ctypes.POINTER(I32)]
+_lib.sim_n_active.restype = I32
+_lib.sim_destroy.argtypes = [P]
+_lib.sim_destroy.restype = I32
+_lib.sim_last_error.argtypes = [P]
+_lib.sim_last_error.restype = ctypes.c_char_p
+_lib.sim_probe_fp32.argtypes = [I32, P, P, P, I64]
+_lib.sim_probe_fp32.restype = I32
+_lib.sim_probe_philox.argtypes = [P, P, P, I64]
+_lib.sim_probe_philox.restype = I32
+_lib.sim_probe_draws.argtypes = [U64, P, P, P, P, P, I64]
+_lib.sim_probe_draws.restype = I32
+
+KERNELS = ["k_tile_step", "k_admit", "k_commit", "k_edge_count", "k_block_scan", "k_edge_offset", "k_scatter"]
+
+EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
+            "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",
+            "sim_probe_fp32", "sim_probe_philox", "sim_probe_draws"]
+
+
+class SimError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAME.get(status, status)}: {msg}")
+        self.status = status
+        self.name = _STATUS_NAME.get(status, str(status))
+
+
+def _check(st: int, handle=None):
+    if st != 0:
+        raise SimError(st, _lib.sim_last_error(handle).decode(errors="replace"))
+
+
+def _p(a):
+    return ctypes.c_void_p(a.ctypes.data) if a is not None else None
+
+
+def _c(a, dt):
+    return np.ascontiguousarray(a, dtype=dt)
+
+
+# ---------------------------------------------------------------- allocator
+# The callback objects are created once and kept for the life of the process:
+# every handle keeps the function pointers it was created with and calls the
+# release callback when it is destroyed.
+_torch_cb = None
+_null_cb = None
+
+
+def _torch_callbacks():
+    global _torch_cb
+    if _torch_cb is None:
+        import torch
+
+        def _alloc(nbytes, ctx):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            torch.cuda.caching_allocator_delete(int(ptr))
+
+        _torch_cb = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    return _torch_cb
+
+
+def use_torch_allocator() -> None:
+    """Route device allocations of handles created afterwards through torch's
+    caching allocator (current device, current stream)."""
+    cb = _torch_callbacks()
+    _check(_lib.sim_set_allocator(cb[0], cb[1], None))
+
+
+def use_hip_allocator() -> None:
+    global _null_cb
+    if _null_cb is None:
+        _null_cb = (_ALLOC_FN(), _FREE_FN())
+    _check(_lib.sim_set_allocator(_null_cb[0], _null_cb[1], None))
+
+
+# ---------------------------------------------------------------- handle
+_live = weakref.WeakSet()
+
+
+@atexit.register
+def _close_all():
+    # before torch's own teardown: destroying a handle calls the release callback
+    for sim in list(_live):
+        sim.close()
+
+
+class Sim:
+    """One simulation on the current GPU.
+
+    ``Sim(workload)`` takes any object with the generator's attribute names
+    (``net``, ``route_off``, ``route_edges``, ``depart_step``, ``vclass``,
+    ``alpha``, ``params``)."""
+
+    def __init__(self, w, stream=None, allocator: str = "torch"):
+        net, p = w.net, w.params
+        self.n = int(w.depart_step.shape[0])
+        self.n_edges = int(net.edge_from.shape[0])
+        keep = dict(
+            ef=_c(net.edge_from, np.int32), et=_c(net.edge_to, np.int32), ln=_c(net.length, np.float32),
+            li=_c(net.limit, np.float32), la=_c(net.lanes, np.uint8), co=_c(net.conn_off, np.int32),
+            ct=_c(net.conn_to, np.int32), cm=_c(net.conn_mask, np.uint8), ro=_c(w.route_off, np.int64),
+            re=_c(w.route_edges, np.int32), dp=_c(w.depart_step, np.int32), vc=_c(w.vclass, np.uint8),
+            al=_c(w.alpha, np.float32), v0=_c(p.v0_factor, np.float32), T=_c(p.T, np.float32),
+            a=_c(p.a, np.float32), b=_c(p.b, np.float32), s0=_c(p.s0, np.float32),
+            vl=_c(p.veh_len, np.float32))
+        k = keep
+        n_nodes = int(getattr(net, "n_nodes", int(max(k["ef"].max(), k["et"].max())) + 1))
+        self._net = SimNetwork(n_nodes, self.n_edges, _p(k["ef"]), _p(k["et"]), _p(k["ln"]), _p(k["li"]),
+                               _p(k["la"]), _p(k["co"]), _p(k["ct"]), _p(k["cm"]))
+        self._routes = SimRoutes(self.n, _p(k["ro"]), _p(k["re"]), _p(k["dp"]), _p(k["vc"]), _p(k["al"]))
+        self._params = SimIdmParams(int(p.T.shape[0]), _p(k["v0"]), _p(k["T"]), _p(k["a"]), _p(k["b"]),
+                                    _p(k["s0"]), _p(k["vl"]), float(p.dt), int(p.seed),
+                                    int(getattr(p, "intersection_mode", 0)), int(getattr(p, "record_every", 0)))
+        self._keep = keep
+        if allocator == "torch":
+            use_torch_allocator()
+        elif allocator == "hip":
+            use_hip_allocator()
+        h = P()
+        _check(_lib.sim_create(ctypes.byref(self._net), ctypes.byref(self._routes), ctypes.byref(self._params),
+                               ctypes.byref(h)))
+        self._h = h
+        _live.add(self)
+        if stream is not None:
+            self.set_stream(stream)
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _lib.sim_destroy(h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    def set_stream(self, stream) -> None:
+        """stream: a torch.cuda.Stream, a raw hipStream_t (int), or None."""
+        raw = getattr(stream, "cuda_stream", stream)
+        _check(_lib.sim_set_stream(self._h, P(raw) if raw else None), self._h)
+
+    def step(self, n: int = 1) -> None:
+        _check(_lib.sim_step(self._h, int(n)), self._h)
+
+    def step_timed(self, n: int):
+        """Run n steps kernel by kernel with HIP events; returns (per-kernel
+        ms summed over the steps as a dict, total ms)."""
+        ks = np.zeros(len(KERNELS), np.float64)
+        tot = np.zeros(1, np.float64)
+        _check(_lib.sim_step_timed(self._h, int(n), _p(ks), _p(tot)), self._h)
+        return dict(zip(KERNELS, ks.tolist())), float(tot[0])
+
+    @property
+    def n_active(self) -> int:
+        out = I32()
+        _check(_lib.sim_n_active(self._h, ctypes.byref(out)), self._h)
+        return int(out.value)
+
+    def state(self) -> dict:
+        n = self.n
+        s = dict(status=np.empty(n, np.uint8), edge=np.empty(n, np.int32), lane=np.empty(n, np.int32),
+                 cursor=np.empty(n, np.int32), x=np.empty(n, np.float32), v=np.empty(n, np.float32),
+                 held_since=np.empty(n, np.int32), mand=np.empty(n, np.uint8), ww=np.empty(n, np.int32),
+                 tau_in=np.empty(n, np.float64), t_arr=np.empty(n, np.float64),
+                 counters=np.empty(len(COUNTERS), np.int64))
+        st = SimState(*[_p(s[k]) for k in ("status", "edge", "lane", "cursor", "x", "v", "held_since", "mand",
+                                           "ww", "tau_in", "t_arr", "counters")], 0)
+        _check(_lib.sim_read_state(self._h, ctypes.byref(st)), self._h)
+        s["t"] = int(st.t)
+        return s
+
+    def write_state(self, s: dict) -> None:
+        a = dict(status=_c(s["status"], np.uint8), edge=_c(s["edge"], np.int32), lane=_c(s["lane"], np.int32),
+                 cursor=_c(s["cursor"], np.int32), x=_c(s["x"], np.float32), v=_c(s["v"], np.float32),
+                 held_since=_c(s["held_since"], np.int32), mand=_c(s["mand"], np.uint8),
+                 ww=_c(s["ww"], np.int32), tau_in=_c(s["tau_in"], np.float64),
+                 t_arr=_c(s["t_arr"], np.float64))
+        cnt = _c(s["counters"], np.int64) if s.get("counters") is not None else None
+        st = SimState(*[_p(a[k]) for k in ("status", "edge", "lane", "cursor", "x", "v", "held_since", "mand",
+                                           "ww", "tau_in", "t_arr")], _p(cnt), int(s["t"]))
+        _check(_lib.sim_write_state(self._h, ctypes.byref(st)), self._h)
+
+    def counters(self) -> dict:
+        return dict(zip(COUNTERS, self.state()["counters"].tolist()))
+
+    def edge_stats(self):
+        s = np.empty(self.n_edges, np.float64)
+        c = np.empty(self.n_edges, np.int64)
+        _check(_lib.sim_read_edge_stats(self._h, _p(s), _p(c)), self._h)
+        return s, c
+
+
+# ---------------------------------------------------------------- probes
+def probe_fp32(op: int, a: np.ndarray, b: np.ndarray = None) -> np.ndarray:
+    a = _c(a, np.float32)
+    b = _c(b, np.float32) if b is not None else None
+    out = np.empty_like(a)
+    _check(_lib.sim_probe_fp32(int(op), _p(a), _p(b), _p(out), int(a.size)))
+    return out
+
+
+def probe_philox(counters: np.ndarray, key) -> np.ndarray:
+    c = _c(counters, np.uint64).reshape(-1, 4)
+    k = _c(key, np.uint64)
+    out = np.empty_like(c)
+    _check(_lib.sim_probe_philox(_p(c), _p(k), _p(out), int(c.shape[0])))
+    return out
+
+
+def probe_draws(seed: int, t: np.ndarray, vid: np.ndarray):
+    t = _c(t, np.int64)
+    vid = _c(vid, np.int64)
+    u = np.empty(t.size, np.float32)
+    e2 = np.empty(t.size, np.float32)
+    e3 = np.empty(t.size, np.float32)
+    _check(_lib.sim_probe_draws(int(seed), _p(t), _p(vid), _p(u), _p(e2), _p(e3), int(t.size)))
+    return u, e2, e3

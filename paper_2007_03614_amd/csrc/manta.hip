@@ -1,0 +1,809 @@
+// libmanta host side: input validation, device layout, the step launch
+// sequence (replayed from a captured HIP graph), and state I/O.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/manta.h"
+#include "step_kernels.hpp"
+
+using namespace manta;
+
+namespace {
+
+// ---- allocator -----------------------------------------------------------
+void* (*g_alloc)(size_t, void*) = nullptr;
+void (*g_release)(void*, void*) = nullptr;
+void* g_ctx = nullptr;
+thread_local std::string g_create_error;
+
+struct Alloc {
+    void* (*alloc)(size_t, void*);
+    void (*release)(void*, void*);
+    void* ctx;
+    void* get(size_t bytes) {
+        if (bytes == 0) bytes = 16;
+        bytes = (bytes + 255) & ~(size_t)255;
+        if (alloc) return alloc(bytes, ctx);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+        return p;
+    }
+    void put(void* p) {
+        if (!p) return;
+        if (release) release(p, ctx);
+        else (void)hipFree(p);
+    }
+};
+
+struct Fail {
+    sim_status st;
+    std::string msg;
+};
+
+std::string fmt(const char* f, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, f);
+    vsnprintf(buf, sizeof(buf), f, ap);
+    va_end(ap);
+    return buf;
+}
+
+#define HIP_OK(expr)                                                                               \
+    do {                                                                                           \
+        hipError_t e_ = (expr);                                                                    \
+        if (e_ != hipSuccess) throw Fail{SIM_EDEVICE, fmt("%s: %s", #expr, hipGetErrorString(e_))}; \
+    } while (0)
+
+}  // namespace
+
+struct sim_handle {
+    Alloc al{};
+    std::vector<void*> bufs;
+    hipStream_t stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    std::string err;
+    Dev d{};
+    int t = 0;
+    int n_veh = 0, n_edges = 0, n_lanes = 0, n_classes = 0;
+    int g_tile = 1, g_items = 1, g_scatter = 1, n_blk = 1;
+    // host copies of the static inputs needed for state I/O
+    std::vector<int64_t> roff;
+    std::vector<int32_t> redges, dep, lanes, lane_base, conn_off, conn_to, ins_lane;
+    std::vector<uint8_t> conn_mask, cls;
+    std::vector<float> L, len_c, s0_c;
+
+    template <class T>
+    T* dev(size_t count) {
+        void* p = al.get(count * sizeof(T));
+        if (!p) throw Fail{SIM_ENOMEM, fmt("device allocation of %zu bytes failed", count * sizeof(T))};
+        bufs.push_back(p);
+        return (T*)p;
+    }
+    template <class T>
+    T* upload(const T* host, size_t count) {
+        T* p = dev<T>(count);
+        if (count) HIP_OK(hipMemcpy(p, host, count * sizeof(T), hipMemcpyHostToDevice));
+        return p;
+    }
+    void release_all() {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+        exec = nullptr;
+        graph = nullptr;
+        for (void* p : bufs) al.put(p);
+        bufs.clear();
+    }
+    uint32_t mask_of(int e, int f) const {
+        if (f < 0) return 0xFFu;
+        for (int c = conn_off[e]; c < conn_off[e + 1]; ++c)
+            if (conn_to[c] == f) return conn_mask[c];
+        return 0u;
+    }
+};
+
+namespace {
+
+bool finite_in(float v, float lo, float hi) { return std::isfinite(v) && v >= lo && v <= hi; }
+
+void validate(const sim_network* net, const sim_routes* r, const sim_idm_params* p) {
+    auto bad = [](std::string m) { throw Fail{SIM_EINVAL, std::move(m)}; };
+    if (!net || !r || !p) bad("null argument");
+    if (net->n_nodes <= 0 || net->n_edges <= 0) bad("network must have nodes and edges");
+    if (!net->edge_from || !net->edge_to || !net->length_m || !net->speed_limit_mps || !net->n_lanes ||
+        !net->conn_off || !net->conn_to || !net->conn_lane_mask)
+        bad("network array missing");
+    const int E = net->n_edges;
+    if (net->conn_off[0] != 0) bad("conn_off[0] != 0");
+    for (int e = 0; e < E; ++e) {
+        if (net->edge_from[e] < 0 || net->edge_from[e] >= net->n_nodes || net->edge_to[e] < 0 ||
+            net->edge_to[e] >= net->n_nodes)
+            bad(fmt("edge %d: node id out of range", e));
+        if (net->n_lanes[e] < 1 || net->n_lanes[e] > 8) bad(fmt("edge %d: lanes %d not in 1..8", e, net->n_lanes[e]));
+        if (!(std::isfinite(net->length_m[e]) && net->length_m[e] >= 20.0f))
+            bad(fmt("edge %d: length must be >= 20 m", e));
+        if (!(std::isfinite(net->speed_limit_mps[e]) && net->speed_limit_mps[e] > 0.0f))
+            bad(fmt("edge %d: speed limit must be > 0", e));
+        if (net->conn_off[e + 1] < net->conn_off[e]) bad("conn_off must be non-decreasing");
+    }
+    for (int e = 0; e < E; ++e)
+        for (int c = net->conn_off[e]; c < net->conn_off[e + 1]; ++c) {
+            const int f = net->conn_to[c];
+            if (f < 0 || f >= E) bad(fmt("move %d: target edge out of range", c));
+            if (net->edge_from[f] != net->edge_to[e]) bad(fmt("move %d: edges %d -> %d do not meet", c, e, f));
+            const unsigned m = net->conn_lane_mask[c];
+            if (m == 0 || (m >> net->n_lanes[e]) != 0) bad(fmt("move %d: lane mask invalid", c));
+        }
+    if (p->n_classes < 1 || p->n_classes > 16) bad("n_classes must be in 1..16");
+    if (!p->v0_factor || !p->T || !p->a || !p->b || !p->s0 || !p->length_m) bad("parameter array missing");
+    for (int c = 0; c < p->n_classes; ++c) {
+        if (!finite_in(p->a[c], 1.0f, 10.0f)) bad(fmt("class %d: a outside [1, 10]", c));
+        if (!finite_in(p->b[c], 1.0f, 10.0f)) bad(fmt("class %d: b outside [1, 10]", c));
+        if (!finite_in(p->T[c], 0.1f, 2.0f)) bad(fmt("class %d: T outside [0.1, 2]", c));
+        if (!finite_in(p->s0[c], 1.0f, 5.0f)) bad(fmt("class %d: s0 outside [1, 5]", c));
+        if (!(std::isfinite(p->v0_factor[c]) && p->v0_factor[c] > 0.0f && p->v0_factor[c] <= 2.0f))
+            bad(fmt("class %d: v0_factor outside (0, 2]", c));
+        if (!(std::isfinite(p->length_m[c]) && p->length_m[c] > 0.0f && p->length_m[c] <= 20.0f))
+            bad(fmt("class %d: length outside (0, 20]", c));
+    }
+    if (!(std::isfinite(p->dt) && p->dt > 0.0f && p->dt <= 1.0f)) bad("dt outside (0, 1]");
+    if (p->intersection_mode != 0)
+        throw Fail{SIM_EUNSUPPORTED, "intersection_mode 1 (flashing red) is not implemented"};
+    if (p->record_every != 0) throw Fail{SIM_EUNSUPPORTED, "record_every is reserved and must be 0"};
+    // a vehicle entering an edge must land behind everything on it: the
+    // overshoot of one step stays below the shortest edge minus a length
+    float vmax = 0, amax = 0, lmax = 0, lmin = 1e30f, limmax = 0;
+    for (int c = 0; c < p->n_classes; ++c) {
+        vmax = std::max(vmax, p->v0_factor[c]);
+        amax = std::max(amax, p->a[c]);
+        lmax = std::max(lmax, p->length_m[c]);
+    }
+    for (int e = 0; e < E; ++e) {
+        lmin = std::min(lmin, net->length_m[e]);
+        limmax = std::max(limmax, net->speed_limit_mps[e]);
+    }
+    const double reach = ((double)vmax * limmax + (double)amax * p->dt) * p->dt + lmax;
+    if (lmin < reach) bad(fmt("shortest edge %.2f m is below one step's reach %.2f m", lmin, reach));
+
+    if (r->n_vehicles < 0) bad("n_vehicles < 0");
+    if (r->n_vehicles > 0 && (!r->route_off || !r->route_edges || !r->depart_step || !r->vclass || !r->alpha_s))
+        bad("route array missing");
+    if (r->n_vehicles > 0 && r->route_off[0] != 0) bad("route_off[0] != 0");
+    for (int i = 0; i < r->n_vehicles; ++i) {
+        const int64_t a = r->route_off[i], b = r->route_off[i + 1];
+        if (b <= a) bad(fmt("vehicle %d: empty route", i));
+        if (r->depart_step[i] < 0) bad(fmt("vehicle %d: negative departure step", i));
+        if (r->vclass[i] >= p->n_classes) bad(fmt("vehicle %d: class out of range", i));
+        if (!finite_in(r->alpha_s[i], 0.0f, 0.40f)) bad(fmt("vehicle %d: alpha outside [0, 0.40]", i));
+        for (int64_t k = a; k < b; ++k) {
+            const int e = r->route_edges[k];
+            if (e < 0 || e >= E) bad(fmt("vehicle %d: route edge out of range", i));
+            if (k + 1 < b) {
+                const int f = r->route_edges[k + 1];
+                if (f < 0 || f >= E) bad(fmt("vehicle %d: route edge out of range", i));
+                bool ok = false;
+                for (int c = net->conn_off[e]; c < net->conn_off[e + 1]; ++c) ok = ok || net->conn_to[c] == f;
+                if (!ok) bad(fmt("vehicle %d: route is not continuous at edge %d -> %d", i, e, f));
+            }
+        }
+    }
+}
+
+// the kernels of one step, in order; ev (optional) gets an event after each
+void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
+    const Dev& d = h->d;
+    auto mark = [&](int k) {
+        if (ev) HIP_OK(hipEventRecord(ev[k], s));
+    };
+    hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), dim3(kNT), 0, s, d);
+    mark(0);
+    hipLaunchKernelGGL(k_admit, dim3(h->g_items), dim3(kNT), 0, s, d);
+    mark(1);
+    hipLaunchKernelGGL(k_commit, dim3(h->g_items), dim3(kNT), 0, s, d);
+    mark(2);
+    hipLaunchKernelGGL(k_edge_count, dim3(h->n_blk), dim3(kNT), 0, s, d);
+    mark(3);
+    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kNT), 0, s, d);
+    mark(4);
+    hipLaunchKernelGGL(k_edge_offset, dim3(h->n_blk), dim3(kNT), 0, s, d);
+    mark(5);
+    hipLaunchKernelGGL(k_scatter, dim3(h->g_scatter), dim3(kNT), 0, s, d);
+    mark(6);
+}
+
+void capture_graph(sim_handle* h) {
+    if (h->exec) (void)hipGraphExecDestroy(h->exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    h->exec = nullptr;
+    h->graph = nullptr;
+    hipStream_t cs;
+    HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        launch_step(h, cs);
+        e = hipStreamEndCapture(cs, &h->graph);
+    }
+    (void)hipStreamDestroy(cs);
+    HIP_OK(e);
+    HIP_OK(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
+}
+
+template <class F>
+sim_status guarded(sim_handle* h, F&& f) {
+    try {
+        f();
+        if (h) h->err.clear();
+        return SIM_OK;
+    } catch (const Fail& x) {
+        if (h) h->err = x.msg;
+        else g_create_error = x.msg;
+        return x.st;
+    } catch (const std::bad_alloc&) {
+        if (h) h->err = "host allocation failed";
+        else g_create_error = "host allocation failed";
+        return SIM_ENOMEM;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+sim_status sim_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void*, void*), void* ctx) {
+    if ((alloc == nullptr) != (release == nullptr)) return SIM_EINVAL;
+    g_alloc = alloc;
+    g_release = release;
+    g_ctx = ctx;
+    return SIM_OK;
+}
+
+sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm_params* p, sim_handle** out) {
+    if (!out) return SIM_EINVAL;
+    *out = nullptr;
+    sim_handle* h = nullptr;
+    sim_status st = guarded(nullptr, [&] {
+        validate(net, r, p);
+        h = new sim_handle();
+        h->al = Alloc{g_alloc, g_release, g_ctx};
+        try {
+            const int E = net->n_edges, N = r->n_vehicles;
+            h->n_veh = N;
+            h->n_edges = E;
+            h->n_classes = p->n_classes;
+            Dev& d = h->d;
+            // ---- network
+            h->lanes.assign(E, 0);
+            h->lane_base.assign(E + 1, 0);
+            for (int e = 0; e < E; ++e) {
+                h->lanes[e] = net->n_lanes[e];
+                h->lane_base[e + 1] = h->lane_base[e] + net->n_lanes[e];
+            }
+            const int NL = h->lane_base[E];
+            h->n_lanes = NL;
+            const int NC = net->conn_off[E];
+            h->conn_off.assign(net->conn_off, net->conn_off + E + 1);
+            h->conn_to.assign(net->conn_to, net->conn_to + NC);
+            h->conn_mask.assign(net->conn_lane_mask, net->conn_lane_mask + NC);
+            h->L.assign(net->length_m, net->length_m + E);
+            d.n_edges = E;
+            d.n_lanes_total = NL;
+            d.L = h->upload(net->length_m, E);
+            d.lim = h->upload(net->speed_limit_mps, E);
+            d.lanes = h->upload(h->lanes.data(), E);
+            d.lane_base = h->upload(h->lane_base.data(), E + 1);
+            d.conn_off = h->upload(net->conn_off, E + 1);
+            d.conn_to = h->upload(net->conn_to, NC);
+            d.conn_mask = h->upload(net->conn_lane_mask, NC);
+            // ---- classes (den = 2 sqrt(ab), rounded once in binary32)
+            std::vector<ClassParams> cp(16);
+            h->len_c.assign(p->n_classes, 0.f);
+            h->s0_c.assign(p->n_classes, 0.f);
+            float len_min = 1e30f;
+            for (int c = 0; c < p->n_classes; ++c) {
+                ClassParams& q = cp[c];
+                q.v0f = p->v0_factor[c];
+                q.T = p->T[c];
+                q.a = p->a[c];
+                q.b = p->b[c];
+                q.s0 = p->s0[c];
+                q.len = p->length_m[c];
+                const float ab = q.a * q.b;
+                q.den = 2.0f * sqrtf(ab);
+                q.pad = 0.f;
+                h->len_c[c] = q.len;
+                h->s0_c[c] = q.s0;
+                len_min = std::min(len_min, q.len);
+            }
+            d.cp = h->upload(cp.data(), 16);
+            d.dt = p->dt;
+            d.seed = p->seed;
+            // ---- vehicles
+            d.n_veh = N;
+            h->roff.assign(r->route_off, r->route_off + N + 1);
+            const int64_t NR = N ? r->route_off[N] : 0;
+            h->redges.assign(r->route_edges, r->route_edges + NR);
+            h->dep.assign(r->depart_step, r->depart_step + N);
+            h->cls.assign(r->vclass, r->vclass + N);
+            h->ins_lane.assign(N, 0);
+            std::vector<int> ins_gl(N);
+            for (int i = 0; i < N; ++i) {
+                const int e0 = h->redges[h->roff[i]];
+                int il = 0;
+                if (h->roff[i + 1] - h->roff[i] > 1) {
+                    const uint32_t m = h->mask_of(e0, h->redges[h->roff[i] + 1]);
+                    while (il < 7 && !((m >> il) & 1u)) ++il;
+                }
+                h->ins_lane[i] = il;
+                ins_gl[i] = h->lane_base[e0] + il;
+            }
+            std::vector<int> order(N);
+            for (int i = 0; i < N; ++i) order[i] = i;
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return h->dep[a] < h->dep[b]; });
+            int max_dep = -1;
+            for (int i = 0; i < N; ++i) max_dep = std::max(max_dep, h->dep[i]);
+            std::vector<int> due(std::max(1, max_dep + 1), 0);
+            for (int i = 0; i < N; ++i) due[h->dep[i]]++;
+            for (int k = 1; k <= max_dep; ++k) due[k] += due[k - 1];
+            d.roff = h->upload(h->roff.data(), N + 1);
+            d.redges = h->upload(h->redges.data(), (size_t)NR);
+            d.dep = h->upload(h->dep.data(), N);
+            d.cls = h->upload(h->cls.data(), N);
+            d.alpha = h->upload(r->alpha_s, N);
+            d.ins_gl = h->upload(ins_gl.data(), N);
+            d.wait_order = h->upload(order.data(), N);
+            d.due = h->upload(due.data(), due.size());
+            d.max_dep = max_dep;
+            // ---- capacity of the largest edge (vehicles never overlap)
+            long long max_edge = 1;
+            for (int e = 0; e < E; ++e)
+                max_edge = std::max(max_edge, (long long)h->lanes[e] * ((long long)(h->L[e] / len_min) + 1));
+            const long long cap_all = std::min<long long>(std::max(N, 1), (long long)kTileWindow - 1 + max_edge);
+            d.big_cap = (int)std::max<long long>(kTileCapLds + 1, cap_all);
+            h->g_tile = std::max(1, std::min(1024, (N + kTileWindow - 1) / kTileWindow));
+            h->g_items = std::max(1, std::min(1024, (E + N + kNT - 1) / kNT));
+            h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
+            h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
+            d.n_blk = h->n_blk;
+            // ---- dynamic state
+            const size_t NV = std::max(N, 1);
+            for (int b = 0; b < 2; ++b) {
+                d.s[b].x = h->dev<float>(NV);
+                d.s[b].v = h->dev<float>(NV);
+                d.s[b].vid = h->dev<uint32_t>(NV);
+                d.s[b].edge = h->dev<int32_t>(NV);
+                d.s[b].meta = h->dev<uint32_t>(NV);
+                d.s[b].nxt = h->dev<int32_t>(NV);
+                d.req_edges[b] = h->dev<int>(E);
+                d.pend[b] = h->dev<int>(NV);
+            }
+            d.ent = h->dev<EntryRec>(std::min<size_t>(NV, (size_t)NL + 1));
+            d.status = h->dev<uint8_t>(NV);
+            d.cursor = h->dev<int>(NV);
+            d.held_since = h->dev<int>(NV);
+            d.tau_in = h->dev<double>(NV);
+            d.t_arr = h->dev<double>(NV);
+            d.fin_x = h->dev<float>(NV);
+            d.fin_v = h->dev<float>(NV);
+            d.fin_meta = h->dev<uint32_t>(NV);
+            d.rear = h->dev<LaneRear>(NL);
+            d.post = h->dev<LanePost>(NL);
+            d.outbox = h->dev<Outbox>(NL);
+            d.win = h->dev<unsigned long long>(NL);
+            d.exit_stamp = h->dev<int>(NL);
+            d.enter_stamp = h->dev<int>(NL);
+            d.lane_newstart = h->dev<int>(NL);
+            d.lane_newcnt = h->dev<int>(NL);
+            d.cnt = h->dev<int>(E);
+            d.exits = h->dev<int>(E);
+            d.entries = h->dev<int>(E);
+            d.req_stamp = h->dev<int>(E);
+            d.edge_off = h->dev<int>(E);
+            d.blk_sum = h->dev<int>(h->n_blk);
+            d.blk_off = h->dev<int>(h->n_blk);
+            d.tt_sum = h->dev<double>(E);
+            d.tt_cnt = h->dev<unsigned long long>(E);
+            d.ctl = h->dev<Ctl>(1);
+            d.counters = h->dev<unsigned long long>(cNumCounters);
+            d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_tile);
+            // ---- initial values
+            HIP_OK(hipMemset(d.rear, 0xFF, sizeof(LaneRear) * NL));
+            HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * NL));
+            HIP_OK(hipMemset(d.outbox, 0xFF, sizeof(Outbox) * NL));
+            HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * NL));
+            HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * NL));
+            HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
+            HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * E));
+            HIP_OK(hipMemset(d.cnt, 0, sizeof(int) * E));
+            HIP_OK(hipMemset(d.exits, 0, sizeof(int) * E));
+            HIP_OK(hipMemset(d.entries, 0, sizeof(int) * E));
+            HIP_OK(hipMemset(d.tt_sum, 0, sizeof(double) * E));
+            HIP_OK(hipMemset(d.tt_cnt, 0, sizeof(unsigned long long) * E));
+            HIP_OK(hipMemset(d.ctl, 0, sizeof(Ctl)));
+            HIP_OK(hipMemset(d.counters, 0, sizeof(unsigned long long) * cNumCounters));
+            HIP_OK(hipMemset(d.status, 0, NV));
+            HIP_OK(hipMemset(d.cursor, 0, sizeof(int) * NV));
+            HIP_OK(hipMemset(d.held_since, 0xFF, sizeof(int) * NV));
+            std::vector<double> neg1(NV, -1.0);
+            HIP_OK(hipMemcpy(d.tau_in, neg1.data(), sizeof(double) * NV, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.t_arr, neg1.data(), sizeof(double) * NV, hipMemcpyHostToDevice));
+            HIP_OK(hipDeviceSynchronize());
+            capture_graph(h);
+        } catch (...) {
+            h->release_all();
+            delete h;
+            h = nullptr;
+            throw;
+        }
+    });
+    if (st == SIM_OK) *out = h;
+    return st;
+}
+
+sim_status sim_set_stream(sim_handle* h, void* stream) {
+    if (!h) return SIM_EINVAL;
+    return guarded(h, [&] {
+        h->stream = (hipStream_t)stream;
+    });
+}
+
+sim_status sim_step(sim_handle* h, int32_t n) {
+    if (!h) return SIM_EINVAL;
+    if (n < 0) {
+        h->err = "n must be >= 0";
+        return SIM_EINVAL;
+    }
+    return guarded(h, [&] {
+        for (int q = 0; q < n; ++q) HIP_OK(hipGraphLaunch(h->exec, h->stream));
+        HIP_OK(hipGetLastError());
+        h->t += n;
+    });
+}
+
+sim_status sim_step_timed(sim_handle* h, int32_t n, double* kernel_ms, double* total_ms) {
+    if (!h) return SIM_EINVAL;
+    if (n < 0) {
+        h->err = "n must be >= 0";
+        return SIM_EINVAL;
+    }
+    std::vector<hipEvent_t> ev;
+    sim_status st = guarded(h, [&] {
+        ev.resize((size_t)n * SIM_N_KERNELS + 1, nullptr);
+        for (auto& e : ev) HIP_OK(hipEventCreate(&e));
+        HIP_OK(hipEventRecord(ev[0], h->stream));
+        for (int q = 0; q < n; ++q) launch_step(h, h->stream, &ev[1 + (size_t)q * SIM_N_KERNELS]);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipEventSynchronize(ev.back()));
+        h->t += n;
+        double ks[SIM_N_KERNELS] = {0};
+        for (int q = 0; q < n; ++q)
+            for (int k = 0; k < SIM_N_KERNELS; ++k) {
+                const size_t i = 1 + (size_t)q * SIM_N_KERNELS + k;
+                float ms = 0.f;
+                HIP_OK(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
+                ks[k] += ms;
+            }
+        if (kernel_ms)
+            for (int k = 0; k < SIM_N_KERNELS; ++k) kernel_ms[k] = ks[k];
+        if (total_ms) {
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, ev.front(), ev.back()));
+            *total_ms = ms;
+        }
+    });
+    for (auto e : ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
+}
+
+sim_status sim_n_active(sim_handle* h, int32_t* out) {
+    if (!h || !out) return SIM_EINVAL;
+    return guarded(h, [&] {
+        Ctl c;
+        HIP_OK(hipStreamSynchronize(h->stream));
+        HIP_OK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        if (c.err) throw Fail{SIM_EDEVICE, fmt("device layout check failed (code %d)", c.err)};
+        *out = c.n_act[c.t & 1];
+    });
+}
+
+sim_status sim_read_state(sim_handle* h, sim_state* o) {
+    if (!h || !o) return SIM_EINVAL;
+    return guarded(h, [&] {
+        const Dev& d = h->d;
+        const int N = h->n_veh;
+        HIP_OK(hipStreamSynchronize(h->stream));
+        Ctl c;
+        HIP_OK(hipMemcpy(&c, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        if (c.err) throw Fail{SIM_EDEVICE, fmt("device layout check failed (code %d)", c.err)};
+        const int par = c.t & 1, na = c.n_act[par];
+        std::vector<float> sx(na), sv(na), fx(N), fv(N);
+        std::vector<uint32_t> svid(na), smeta(na), fmeta(N);
+        std::vector<int32_t> sedge(na), cur(N), hs(N);
+        std::vector<uint8_t> st(N);
+        std::vector<double> tin(N), tar(N);
+        const Slots S = d.s[par];
+        if (na) {
+            HIP_OK(hipMemcpy(sx.data(), S.x, 4 * (size_t)na, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(sv.data(), S.v, 4 * (size_t)na, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(svid.data(), S.vid, 4 * (size_t)na, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(smeta.data(), S.meta, 4 * (size_t)na, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(sedge.data(), S.edge, 4 * (size_t)na, hipMemcpyDeviceToHost));
+        }
+        if (N) {
+            HIP_OK(hipMemcpy(st.data(), d.status, (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(cur.data(), d.cursor, 4 * (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(hs.data(), d.held_since, 4 * (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(tin.data(), d.tau_in, 8 * (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(tar.data(), d.t_arr, 8 * (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(fx.data(), d.fin_x, 4 * (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(fv.data(), d.fin_v, 4 * (size_t)N, hipMemcpyDeviceToHost));
+            HIP_OK(hipMemcpy(fmeta.data(), d.fin_meta, 4 * (size_t)N, hipMemcpyDeviceToHost));
+        }
+        std::vector<int> slot_of(N, -1);
+        for (int s = 0; s < na; ++s) {
+            if (svid[s] >= (uint32_t)N) throw Fail{SIM_EDEVICE, "corrupt layout: vehicle id out of range"};
+            slot_of[svid[s]] = s;
+        }
+        for (int i = 0; i < N; ++i) {
+            float x = 0.f, v = 0.f;
+            int edge, lane, ww = 0;
+            uint8_t mand = 0;
+            if (st[i] == kActive) {
+                const int s = slot_of[i];
+                if (s < 0) throw Fail{SIM_EDEVICE, fmt("corrupt layout: active vehicle %d has no slot", i)};
+                x = sx[s];
+                v = sv[s];
+                edge = sedge[s];
+                lane = m_lane(smeta[s]);
+                mand = m_mand(smeta[s]);
+                ww = m_ww(smeta[s]);
+            } else if (st[i] == kArrived) {
+                x = fx[i];
+                v = fv[i];
+                edge = h->redges[h->roff[i] + cur[i]];
+                lane = m_lane(fmeta[i]);
+                mand = m_mand(fmeta[i]);
+                ww = m_ww(fmeta[i]);
+            } else {
+                edge = h->redges[h->roff[i]];
+                lane = h->ins_lane[i];
+            }
+            if (o->status) o->status[i] = st[i];
+            if (o->edge) o->edge[i] = edge;
+            if (o->lane) o->lane[i] = lane;
+            if (o->cursor) o->cursor[i] = cur[i];
+            if (o->x) o->x[i] = x;
+            if (o->v) o->v[i] = v;
+            if (o->held_since) o->held_since[i] = hs[i];
+            if (o->mand) o->mand[i] = mand;
+            if (o->ww) o->ww[i] = ww;
+            if (o->tau_in) o->tau_in[i] = tin[i];
+            if (o->t_arr) o->t_arr[i] = tar[i];
+        }
+        if (o->counters) {
+            unsigned long long cc[cNumCounters];
+            HIP_OK(hipMemcpy(cc, d.counters, sizeof(cc), hipMemcpyDeviceToHost));
+            for (int k = 0; k < cNumCounters; ++k) o->counters[k] = (int64_t)cc[k];
+        }
+        o->t = c.t;
+    });
+}
+
+sim_status sim_write_state(sim_handle* h, const sim_state* in) {
+    if (!h || !in) return SIM_EINVAL;
+    return guarded(h, [&] {
+        const int N = h->n_veh;
+        if (!in->status || !in->edge || !in->lane || !in->cursor || !in->x || !in->v || !in->held_since ||
+            !in->mand || !in->ww || !in->tau_in || !in->t_arr)
+            throw Fail{SIM_EINVAL, "every state field is required"};
+        if (in->t < 0) throw Fail{SIM_EINVAL, "t < 0"};
+        const Dev& d = h->d;
+        struct Rec {
+            int edge, lane;
+            float x;
+            int id;
+        };
+        std::vector<Rec> act;
+        for (int i = 0; i < N; ++i) {
+            const uint8_t s = in->status[i];
+            if (s > 2) throw Fail{SIM_EINVAL, fmt("vehicle %d: bad status", i)};
+            const int64_t rl = h->roff[i + 1] - h->roff[i];
+            if (in->cursor[i] < 0 || in->cursor[i] >= rl) throw Fail{SIM_EINVAL, fmt("vehicle %d: bad cursor", i)};
+            if (s == kActive) {
+                const int e = h->redges[h->roff[i] + in->cursor[i]];
+                if (in->edge[i] != e) throw Fail{SIM_EINVAL, fmt("vehicle %d: edge is not the route edge", i)};
+                if (in->lane[i] < 0 || in->lane[i] >= h->lanes[e]) throw Fail{SIM_EINVAL, fmt("vehicle %d: lane", i)};
+                if (!(in->x[i] >= 0.f && in->x[i] <= h->L[e]) || !(in->v[i] >= 0.f) || !std::isfinite(in->v[i]))
+                    throw Fail{SIM_EINVAL, fmt("vehicle %d: x or v out of range", i)};
+                if (in->ww[i] < 0 || in->ww[i] > kPatience) throw Fail{SIM_EINVAL, fmt("vehicle %d: ww", i)};
+                act.push_back(Rec{e, in->lane[i], in->x[i], i});
+            }
+        }
+        std::sort(act.begin(), act.end(), [](const Rec& a, const Rec& b) {
+            if (a.edge != b.edge) return a.edge < b.edge;
+            if (a.lane != b.lane) return a.lane < b.lane;
+            if (a.x != b.x) return a.x > b.x;
+            return a.id > b.id;
+        });
+        for (size_t k = 1; k < act.size(); ++k)
+            if (act[k].edge == act[k - 1].edge && act[k].lane == act[k - 1].lane &&
+                act[k - 1].x - h->len_c[h->cls[act[k - 1].id]] < act[k].x)
+                throw Fail{SIM_EINVAL, fmt("vehicles %d and %d overlap", act[k - 1].id, act[k].id)};
+        const int na = (int)act.size(), t = in->t, par = t & 1;
+        std::vector<float> sx(na), sv(na);
+        std::vector<uint32_t> svid(na), smeta(na);
+        std::vector<int32_t> sedge(na), snxt(na), cnt(h->n_edges, 0);
+        std::vector<LaneRear> rear(h->n_lanes);
+        for (auto& r : rear) r = LaneRear{0.f, 0.f, -1, 0};
+        for (int k = 0; k < na; ++k) {
+            const int i = act[k].id, e = act[k].edge;
+            const int64_t pos = h->roff[i] + in->cursor[i] + 1;
+            const int nx = pos < h->roff[i + 1] ? h->redges[pos] : -1;
+            sx[k] = in->x[i];
+            sv[k] = in->v[i];
+            svid[k] = (uint32_t)i;
+            sedge[k] = e;
+            snxt[k] = nx;
+            smeta[k] = m_make(in->lane[i], in->mand[i] != 0, in->held_since[i] >= 0, in->ww[i], h->cls[i],
+                              h->mask_of(e, nx));
+            cnt[e]++;
+            const bool last = (k + 1 == na) || act[k + 1].edge != e || act[k + 1].lane != act[k].lane;
+            if (last) rear[h->lane_base[e] + act[k].lane] = LaneRear{in->x[i] - h->len_c[h->cls[i]], in->v[i], t, 0};
+        }
+        // vehicles still waiting whose departure step has passed
+        std::vector<int> pend;
+        for (int i = 0; i < N; ++i)
+            if (in->status[i] == kWaiting && h->dep[i] <= t - 1) pend.push_back(i);
+        std::vector<uint8_t> st(in->status, in->status + N);
+        std::vector<float> fx(N, 0.f), fv(N, 0.f);
+        std::vector<uint32_t> fmeta(N, 0);
+        for (int i = 0; i < N; ++i)
+            if (st[i] == kArrived) {
+                fx[i] = in->x[i];
+                fv[i] = in->v[i];
+                fmeta[i] = m_make(in->lane[i], in->mand[i] != 0, false, in->ww[i], h->cls[i], 0);
+            }
+        HIP_OK(hipStreamSynchronize(h->stream));
+        const Slots S = d.s[par];
+        if (na) {
+            HIP_OK(hipMemcpy(S.x, sx.data(), 4 * (size_t)na, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(S.v, sv.data(), 4 * (size_t)na, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(S.vid, svid.data(), 4 * (size_t)na, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(S.meta, smeta.data(), 4 * (size_t)na, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(S.edge, sedge.data(), 4 * (size_t)na, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(S.nxt, snxt.data(), 4 * (size_t)na, hipMemcpyHostToDevice));
+        }
+        if (N) {
+            HIP_OK(hipMemcpy(d.status, st.data(), (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.cursor, in->cursor, 4 * (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.held_since, in->held_since, 4 * (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.tau_in, in->tau_in, 8 * (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.t_arr, in->t_arr, 8 * (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.fin_x, fx.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.fin_v, fv.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d.fin_meta, fmeta.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
+        }
+        if (!pend.empty())
+            HIP_OK(hipMemcpy(d.pend[par], pend.data(), 4 * pend.size(), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d.cnt, cnt.data(), 4 * (size_t)h->n_edges, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d.rear, rear.data(), sizeof(LaneRear) * h->n_lanes, hipMemcpyHostToDevice));
+        HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * h->n_lanes));
+        HIP_OK(hipMemset(d.outbox, 0xFF, sizeof(Outbox) * h->n_lanes));
+        HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * h->n_lanes));
+        HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
+        HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
+        HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * h->n_edges));
+        HIP_OK(hipMemset(d.exits, 0, sizeof(int) * h->n_edges));
+        HIP_OK(hipMemset(d.entries, 0, sizeof(int) * h->n_edges));
+        Ctl c{};
+        c.t = t;
+        c.n_act[par] = na;
+        c.n_pend[par] = (int)pend.size();
+        HIP_OK(hipMemcpy(d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice));
+        if (in->counters) {
+            unsigned long long cc[cNumCounters];
+            for (int k = 0; k < cNumCounters; ++k) cc[k] = (unsigned long long)in->counters[k];
+            HIP_OK(hipMemcpy(d.counters, cc, sizeof(cc), hipMemcpyHostToDevice));
+        }
+        HIP_OK(hipDeviceSynchronize());
+        h->t = t;
+    });
+}
+
+sim_status sim_read_edge_stats(sim_handle* h, double* tt_sum, int64_t* tt_count) {
+    if (!h) return SIM_EINVAL;
+    return guarded(h, [&] {
+        HIP_OK(hipStreamSynchronize(h->stream));
+        if (tt_sum) HIP_OK(hipMemcpy(tt_sum, h->d.tt_sum, 8 * (size_t)h->n_edges, hipMemcpyDeviceToHost));
+        if (tt_count) HIP_OK(hipMemcpy(tt_count, h->d.tt_cnt, 8 * (size_t)h->n_edges, hipMemcpyDeviceToHost));
+    });
+}
+
+sim_status sim_destroy(sim_handle* h) {
+    if (!h) return SIM_OK;
+    (void)hipStreamSynchronize(h->stream);
+    h->release_all();
+    delete h;
+    return SIM_OK;
+}
+
+const char* sim_last_error(const sim_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+// ---- diagnostics ---------------------------------------------------------
+sim_status sim_probe_fp32(int32_t op, const float* a, const float* b, float* out, int64_t n) {
+    if (!a || !out || n < 0 || op < 0 || op > 4 || ((op == 0 || op == 2 || op == 3) && !b)) return SIM_EINVAL;
+    if (n == 0) return SIM_OK;
+    float *da = nullptr, *db = nullptr, *dout = nullptr;
+    sim_status st = guarded(nullptr, [&] {
+        HIP_OK(hipMalloc(&da, 4 * n));
+        HIP_OK(hipMalloc(&dout, 4 * n));
+        HIP_OK(hipMemcpy(da, a, 4 * n, hipMemcpyHostToDevice));
+        if (b) {
+            HIP_OK(hipMalloc(&db, 4 * n));
+            HIP_OK(hipMemcpy(db, b, 4 * n, hipMemcpyHostToDevice));
+        }
+        const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL(k_probe_fp32, dim3(g), dim3(256), 0, 0, op, da, db, dout, n);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpy(out, dout, 4 * n, hipMemcpyDeviceToHost));
+    });
+    (void)hipFree(da);
+    (void)hipFree(db);
+    (void)hipFree(dout);
+    return st;
+}
+
+sim_status sim_probe_philox(const uint64_t* counters, const uint64_t* key, uint64_t* out, int64_t n) {
+    if (!counters || !key || !out || n < 0) return SIM_EINVAL;
+    if (n == 0) return SIM_OK;
+    uint64_t *dc = nullptr, *dout = nullptr;
+    sim_status st = guarded(nullptr, [&] {
+        HIP_OK(hipMalloc(&dc, 32 * n));
+        HIP_OK(hipMalloc(&dout, 32 * n));
+        HIP_OK(hipMemcpy(dc, counters, 32 * n, hipMemcpyHostToDevice));
+        const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL(k_probe_philox, dim3(g), dim3(256), 0, 0, dc, key[0], key[1], dout, n);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpy(out, dout, 32 * n, hipMemcpyDeviceToHost));
+    });
+    (void)hipFree(dc);
+    (void)hipFree(dout);
+    return st;
+}
+
+sim_status sim_probe_draws(uint64_t seed, const int64_t* t, const int64_t* id, float* u, float* e2, float* e3,
+                           int64_t n) {
+    if (!t || !id || !u || !e2 || !e3 || n < 0) return SIM_EINVAL;
+    if (n == 0) return SIM_OK;
+    int64_t *dt = nullptr, *did = nullptr;
+    float* dout = nullptr;
+    sim_status st = guarded(nullptr, [&] {
+        HIP_OK(hipMalloc(&dt, 8 * n));
+        HIP_OK(hipMalloc(&did, 8 * n));
+        HIP_OK(hipMalloc(&dout, 12 * n));
+        HIP_OK(hipMemcpy(dt, t, 8 * n, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(did, id, 8 * n, hipMemcpyHostToDevice));
+        const int g = (int)std::min<int64_t>(4096, (n + 255) / 256);
+        hipLaunchKernelGGL(k_probe_draws, dim3(g), dim3(256), 0, 0, seed, dt, did, dout, dout + n, dout + 2 * n, n);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpy(u, dout, 4 * n, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(e2, dout + n, 4 * n, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(e3, dout + 2 * n, 4 * n, hipMemcpyDeviceToHost));
+    });
+    (void)hipFree(dt);
+    (void)hipFree(did);
+    (void)hipFree(dout);
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,1062 @@
+// Step kernels of the per-timestep vehicle update on gfx950 (wave64).
+//
+// Layout.  Active vehicles live in a structure-of-arrays "slot" buffer sorted
+// by (edge, lane, x descending, id descending), so every lane is a contiguous
+// run with its front first.  The buffer is double-buffered: step t reads
+// slots[t & 1] and the scatter kernel writes slots[(t + 1) & 1].  Per-lane
+// tables carry the rear of each lane at the start of the step (look-ahead,
+// stamped with the step they are valid for), the rear after the move
+// (admission), and the post-lane-change run of each lane (scatter).
+//
+// One step = 7 launches, all reading the step number from device memory, so
+// a captured graph of one step can be replayed for every step:
+//   k_tile_step   Phases 1-2 per tile of whole edges, staged in LDS
+//   k_admit       eligibility + atomicMin of a 64-bit priority key per lane
+//   k_commit      winners, losers, arrivals, per-edge travel-time sums
+//   k_edge_count  new per-edge counts + per-block sums
+//   k_block_scan  scan of the block sums (one workgroup)
+//   k_edge_offset per-edge offsets, per-lane new starts
+//   k_scatter     write the next layout and the next look-ahead table
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "device_math.hpp"
+
+namespace manta {
+
+constexpr int kNT = 256;                 // threads per workgroup (4 waves)
+constexpr int kWaves = kNT / 64;
+constexpr int kTileWindow = 256;         // a tile = the edges whose first slot lies in a 256-slot window
+constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
+constexpr int kEdgeBlock = 1024;         // edges per block in the offset scan
+
+// ---- vehicle meta word ---------------------------------------------------
+// bits 0-3 lane | 4 mandatory | 5 held at stop line | 8-14 wrong-lane wait |
+// 16-19 class | 24-31 lane mask of the move to the next edge
+__host__ __device__ inline int m_lane(uint32_t m) { return (int)(m & 15u); }
+__host__ __device__ inline bool m_mand(uint32_t m) { return (m >> 4) & 1u; }
+__host__ __device__ inline bool m_held(uint32_t m) { return (m >> 5) & 1u; }
+__host__ __device__ inline int m_ww(uint32_t m) { return (int)((m >> 8) & 127u); }
+__host__ __device__ inline int m_cls(uint32_t m) { return (int)((m >> 16) & 15u); }
+__host__ __device__ inline uint32_t m_mask(uint32_t m) { return m >> 24; }
+__host__ __device__ inline uint32_t m_make(int lane, bool mand, bool held, int ww, int cls, uint32_t mask) {
+    return (uint32_t)lane | ((uint32_t)mand << 4) | ((uint32_t)held << 5) | ((uint32_t)ww << 8) |
+           ((uint32_t)cls << 16) | (mask << 24);
+}
+__host__ __device__ inline uint32_t m_set_lane(uint32_t m, int lane) { return (m & ~15u) | (uint32_t)lane; }
+
+enum Status : uint8_t { kWaiting = 0, kActive = 1, kArrived = 2 };
+
+enum Counter {
+    cActiveSum = 0, cDeparted, cArrived, cLaneChanges, cTransfers, cHolds, cInsertDenied,
+    cMandTriggers, cStopBranch, cClamp, cWrongLaneHolds, cWaivedExits, cNumCounters
+};
+
+struct Ctl {
+    int t;
+    int n_act[2];
+    int n_req[2];
+    int n_pend[2];
+    int n_ent[2];
+    unsigned done;
+    int err;          // non-zero: a layout bound check failed (see kErr*)
+    int pad[6];
+};
+
+enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
+
+struct Slots {
+    float* x;
+    float* v;
+    uint32_t* vid;
+    int32_t* edge;
+    uint32_t* meta;
+    int32_t* nxt;     // next route edge, -1 on the last edge
+};
+
+struct LaneRear {     // rear of a lane at the start of step `stamp`
+    float xm;         // x - length of the rear vehicle
+    float v;
+    int stamp;
+    int pad;
+};
+
+struct LanePost {     // post-lane-change run of a lane in step `stamp`
+    int stamp;
+    int start;        // first slot of the run
+    int cnt;
+    float rear_xm;    // rear after Phase 2 (x_new - length)
+};
+
+struct Outbox {       // end-of-edge request of a lane's front vehicle
+    int stamp;
+    int slot;
+    uint32_t vid;
+    int target;       // global lane on the next edge, -1 for an arrival
+    float xp;         // position on the next edge
+    float phi;        // fraction of the step at which the stop line was crossed
+    uint64_t key;     // admission priority (smaller first)
+};
+
+struct EntryRec {
+    float x, v;
+    uint32_t vid;
+    int edge;
+    uint32_t meta;
+    int nxt;
+    int gl;
+    int pad;
+};
+
+struct Dev {
+    Ctl* ctl;
+    unsigned long long* counters;
+    // network
+    int n_edges, n_lanes_total;
+    const float* L;
+    const float* lim;
+    const int* lanes;
+    const int* lane_base;
+    const int* conn_off;
+    const int* conn_to;
+    const uint8_t* conn_mask;
+    // vehicles (static)
+    int n_veh;
+    const int64_t* roff;
+    const int* redges;
+    const int* dep;
+    const uint8_t* cls;
+    const float* alpha;
+    const int* ins_gl;          // global entry lane of each vehicle
+    const int* wait_order;      // vehicle ids sorted by (departure step, id)
+    const int* due;             // due[t] = vehicles with departure step <= t, t <= max_dep
+    int max_dep;
+    const ClassParams* cp;
+    float dt;
+    uint64_t seed;
+    // layout
+    Slots s[2];
+    // per vehicle (id-indexed)
+    uint8_t* status;
+    int* cursor;
+    int* held_since;
+    double* tau_in;
+    double* t_arr;
+    float* fin_x;
+    float* fin_v;
+    uint32_t* fin_meta;
+    // per lane
+    LaneRear* rear;
+    LanePost* post;
+    Outbox* outbox;
+    unsigned long long* win;
+    int* exit_stamp;
+    int* enter_stamp;
+    int* lane_newstart;
+    int* lane_newcnt;
+    // per edge
+    int* cnt;
+    int* exits;
+    int* entries;
+    int* req_stamp;
+    int* edge_off;
+    int* blk_sum;
+    int* blk_off;
+    int n_blk;
+    double* tt_sum;
+    unsigned long long* tt_cnt;
+    // lists
+    int* req_edges[2];
+    int* pend[2];
+    EntryRec* ent;
+    // big-tile scratch
+    char* big;
+    int big_cap;                // vehicles per workgroup region
+};
+
+// ---- per-tile working set -----------------------------------------------
+struct TileBuf {
+    float* x;
+    float* v;
+    uint32_t* vid;
+    uint32_t* el;       // edge << 4 | lane (S_t)
+    uint32_t* meta;
+    int* nxt;
+    int* pos;           // Phase 1: insertion point in the target lane's run
+    int* moved;
+    int* mpref;         // movers before index q (n + 1 entries)
+    int* lastm;         // last mover at or before q in the tile, or -1
+    int* lasts;         // last stayer at or before q, or -1
+    int* runst;         // first index of q's run
+    float* xn;          // Phase 2 position
+    uint32_t* fl;       // Phase 2 flags
+    uint32_t* pel;      // post-change (edge, lane), permuted to the new order
+    int* inv;           // new order -> q
+};
+
+__host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * 64 + 64; }
+
+__device__ inline TileBuf carve(char* base, int cap) {
+    TileBuf b;
+    size_t o = 0;
+    auto take = [&](size_t n) { char* p = base + o; o += n * 4; return p; };
+    b.x = (float*)take(cap);
+    b.v = (float*)take(cap);
+    b.vid = (uint32_t*)take(cap);
+    b.el = (uint32_t*)take(cap);
+    b.meta = (uint32_t*)take(cap);
+    b.nxt = (int*)take(cap);
+    b.pos = (int*)take(cap);
+    b.moved = (int*)take(cap);
+    b.mpref = (int*)take(cap + 1);
+    b.lastm = (int*)take(cap);
+    b.lasts = (int*)take(cap);
+    b.runst = (int*)take(cap);
+    b.xn = (float*)take(cap);
+    b.fl = (uint32_t*)take(cap);
+    b.pel = (uint32_t*)take(cap);
+    b.inv = (int*)take(cap);
+    return b;
+}
+
+// flags of Phase 2
+constexpr uint32_t F_WHOLD = 1u, F_VEH = 2u;
+
+// first index in [0, n) whose element does not precede (el, x, id) in the
+// tile order (el ascending, x descending, id descending)
+__device__ inline int tile_lower_bound(const TileBuf& b, int n, uint32_t el, float x, uint32_t id) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        const uint32_t e2 = b.el[mid];
+        bool before;
+        if (e2 != el) {
+            before = e2 < el;
+        } else {
+            const float x2 = b.x[mid];
+            before = (x2 > x) || (x2 == x && b.vid[mid] > id);
+        }
+        if (before) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ inline int el_lower_bound(const uint32_t* el, int n, uint32_t key) {
+    int lo = 0, hi = n;
+    while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (el[mid] < key) lo = mid + 1;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// ---- workgroup helpers ---------------------------------------------------
+struct Scan4 {
+    int s, a, b, c;     // s: sum; a, b, c: max
+};
+
+__device__ inline Scan4 scan4_op(Scan4 x, Scan4 y) {
+    return Scan4{x.s + y.s, max(x.a, y.a), max(x.b, y.b), max(x.c, y.c)};
+}
+
+// exclusive workgroup scan of one Scan4 per thread; wsh: kWaves Scan4 in LDS
+__device__ inline Scan4 wg_exclusive_scan4(Scan4 v, Scan4* wsh) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    Scan4 inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        Scan4 o;
+        o.s = __shfl_up(inc.s, d, 64);
+        o.a = __shfl_up(inc.a, d, 64);
+        o.b = __shfl_up(inc.b, d, 64);
+        o.c = __shfl_up(inc.c, d, 64);
+        if (lane >= d) inc = scan4_op(o, inc);
+    }
+    if (lane == 63) wsh[wave] = inc;
+    __syncthreads();
+    Scan4 carry{0, -1, -1, -1};
+    for (int w = 0; w < wave; ++w) carry = scan4_op(carry, wsh[w]);
+    __syncthreads();
+    Scan4 exc;
+    exc.s = __shfl_up(inc.s, 1, 64);
+    exc.a = __shfl_up(inc.a, 1, 64);
+    exc.b = __shfl_up(inc.b, 1, 64);
+    exc.c = __shfl_up(inc.c, 1, 64);
+    if (lane == 0) exc = Scan4{0, -1, -1, -1};
+    return scan4_op(carry, exc);
+}
+
+__device__ inline int wg_sum(int v, int* wsh) {
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) wsh[wave] = v;
+    __syncthreads();
+    int s = 0;
+    for (int w = 0; w < kWaves; ++w) s += wsh[w];
+    __syncthreads();
+    return s;
+}
+
+// per-workgroup counter accumulation, flushed with one atomic per counter
+struct CounterAcc {
+    unsigned c[cNumCounters];
+    __device__ void zero() {
+        for (int k = 0; k < cNumCounters; ++k) c[k] = 0;
+    }
+};
+
+__device__ inline void flush_counters(const Dev& d, CounterAcc& acc, int* wsh) {
+    for (int k = 0; k < cNumCounters; ++k) {
+        const int s = wg_sum((int)acc.c[k], wsh);
+        if (threadIdx.x == 0 && s) atomicAdd(&d.counters[k], (unsigned long long)s);
+    }
+}
+
+__device__ inline uint32_t conn_mask_of(const Dev& d, int e, int f) {
+    if (f < 0) return 0xFFu;
+    for (int c = d.conn_off[e]; c < d.conn_off[e + 1]; ++c)
+        if (d.conn_to[c] == f) return d.conn_mask[c];
+    return 0u;
+}
+
+__device__ inline bool lane_allowed(uint32_t meta, int nxt, int l) {
+    return nxt < 0 || ((m_mask(meta) >> l) & 1u);
+}
+
+// ---- tile search ---------------------------------------------------------
+// first slot s in [lo, hi) that starts an edge (s == 0 or edge differs from
+// s - 1), or hi if none; every thread of the workgroup gets the answer
+__device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int* wsh) {
+    for (int base = lo; base < hi; base += kNT) {
+        const int s = base + (int)threadIdx.x;
+        bool f = false;
+        if (s < hi) f = (s == 0) || (edge[s] != edge[s - 1]);
+        const unsigned long long bal = __ballot(f);
+        const int wave = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) wsh[wave] = bal ? (base + wave * 64 + (__ffsll((long long)bal) - 1)) : INT32_MAX;
+        __syncthreads();
+        int m = INT32_MAX;
+        for (int w = 0; w < kWaves; ++w) m = min(m, wsh[w]);
+        __syncthreads();
+        if (m != INT32_MAX) return m;
+    }
+    return hi;
+}
+
+// ---- Phases 1-2 for one tile ----------------------------------------------
+__device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
+                                    CounterAcc& acc, Scan4* wsh4) {
+    const Slots S = d.s[par];
+    const int tid = threadIdx.x;
+    const int dir = (t % 2 == 0) ? -1 : 1;
+
+    // load S_t (coalesced)
+    for (int q = tid; q < n; q += kNT) {
+        const int s = a0 + q;
+        const uint32_t m = S.meta[s];
+        b.x[q] = S.x[s];
+        b.v[q] = S.v[s];
+        b.vid[q] = S.vid[s];
+        b.el[q] = ((uint32_t)S.edge[s] << 4) | (uint32_t)m_lane(m);
+        b.meta[q] = m;
+        b.nxt[q] = S.nxt[s];
+    }
+    __syncthreads();
+
+    // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t
+    for (int q = tid; q < n; q += kNT) {
+        uint32_t m = b.meta[q];
+        int moved = 0, pos = 0;
+        if (!m_held(m)) {
+            const uint32_t el = b.el[q];
+            const int e = (int)(el >> 4), l = (int)(el & 15u);
+            const int f = b.nxt[q];
+            const float xi = b.x[q], vi = b.v[q];
+            const uint32_t id = b.vid[q];
+            const bool allowed_l = lane_allowed(m, f, l);
+            const ClassParams cpi = d.cp[m_cls(m)];
+            if (!allowed_l && !m_mand(m)) {                              // Eq. (2)
+                const float dd = d.L[e] - xi;
+                bool trig = false;
+                if (dd <= kX0) {
+                    trig = true;
+                } else {
+                    const float dm = dd - kX0;
+                    const float z = dm * dm;
+                    if (z < kZCut && draw_uniform(d.seed, t, id, 1) < exp_eq2(-z)) trig = true;
+                }
+                if (trig) {
+                    m |= 1u << 4;
+                    acc.c[cMandTriggers]++;
+                }
+            }
+            const int lp = l + dir;
+            if (lp >= 0 && lp < d.lanes[e]) {
+                const uint32_t elp = (el & ~15u) | (uint32_t)lp;
+                pos = tile_lower_bound(b, n, elp, xi, id);
+                const int la = (pos > 0 && b.el[pos - 1] == elp) ? pos - 1 : -1;
+                const int lb = (pos < n && b.el[pos] == elp) ? pos : -1;
+                const uint32_t mask = f < 0 ? 0xFFu : m_mask(m);
+                bool desire = !allowed_l && (lane_distance(mask, lp) < lane_distance(mask, l));
+                const bool allowed_lp = lane_allowed(m, f, lp);
+                if (!desire && allowed_lp && !(m_mand(m) && !allowed_l)) {
+                    const float v0 = cpi.v0f * d.lim[e];
+                    unsigned br = 0;
+                    float acc_cur, acc_new;
+                    const int lc = (q > 0 && b.el[q - 1] == el) ? q - 1 : -1;
+                    if (lc >= 0) {
+                        const float s = (b.x[lc] - d.cp[m_cls(b.meta[lc])].len) - xi;
+                        acc_cur = idm_acc(vi, v0, b.v[lc], s, cpi, kVeh, br);
+                    } else {
+                        acc_cur = idm_acc(vi, v0, 0.0f, 0.0f, cpi, kFree, br);
+                    }
+                    if (la >= 0) {
+                        const float s = (b.x[la] - d.cp[m_cls(b.meta[la])].len) - xi;
+                        acc_new = idm_acc(vi, v0, b.v[la], s, cpi, kVeh, br);
+                    } else {
+                        acc_new = idm_acc(vi, v0, 0.0f, 0.0f, cpi, kFree, br);
+                    }
+                    desire = (acc_new - acc_cur) > kIncentive;
+                }
+                if (desire) {                                            // Eqs. (3)-(4)
+                    const float g0 = desired_gap(vi);
+                    const float ai = d.alpha[id];
+                    bool ok = true;
+                    if (la >= 0) {
+                        const float G = (b.x[la] - d.cp[m_cls(b.meta[la])].len) - xi;
+                        const float g = crit_gap(g0, d.alpha[b.vid[la]], vi, ai, b.v[la]) +
+                                        draw_normal(d.seed, t, id, 2);
+                        const float need = g > 0.0f ? g : 0.0f;
+                        ok = ok && (G >= need);
+                    }
+                    if (lb >= 0) {
+                        const float G = (xi - cpi.len) - b.x[lb];
+                        const float g = crit_gap(g0, ai, vi, d.alpha[b.vid[lb]], b.v[lb]) +
+                                        draw_normal(d.seed, t, id, 3);
+                        const float need = g > 0.0f ? g : 0.0f;
+                        ok = ok && (G >= need);
+                    }
+                    if (ok) {
+                        moved = 1;
+                        acc.c[cLaneChanges]++;
+                        if (allowed_lp) m &= ~((1u << 4) | (127u << 8));   // mand = 0, ww = 0
+                    }
+                }
+            }
+        }
+        b.moved[q] = moved;
+        b.pos[q] = pos;
+        // only this vehicle's own mandatory/wait bits change; its class bits,
+        // which neighbours read, stay the same
+        b.meta[q] = m;
+    }
+    __syncthreads();
+
+    // ---- mover prefix sums and last-mover / last-stayer / run-start maxima
+    {
+        const int chunk = (n + kNT - 1) / kNT;
+        const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+        Scan4 loc{0, -1, -1, -1};
+        for (int q = lo; q < hi; ++q) {
+            const int mv = b.moved[q];
+            loc.s += mv;
+            if (mv) loc.a = q; else loc.b = q;
+            if (q == 0 || b.el[q] != b.el[q - 1]) loc.c = q;
+        }
+        Scan4 run = wg_exclusive_scan4(loc, wsh4);
+        for (int q = lo; q < hi; ++q) {
+            const int mv = b.moved[q];
+            b.mpref[q] = run.s;
+            run.s += mv;
+            if (mv) run.a = q; else run.b = q;
+            if (q == 0 || b.el[q] != b.el[q - 1]) run.c = q;
+            b.lastm[q] = run.a;
+            b.lasts[q] = run.b;
+            b.runst[q] = run.c;
+        }
+        if (hi == n && lo < hi) b.mpref[n] = run.s;
+        if (n == 0 && tid == 0) b.mpref[0] = 0;
+    }
+    for (int q = tid; q < n; q += kNT) b.inv[q] = -1;
+    __syncthreads();
+
+    // ---- Phase 2: leader on the post-change lane, Eq. (1), integration
+    for (int q = tid; q < n; q += kNT) {
+        const uint32_t el = b.el[q];
+        const int e = (int)(el >> 4), l = (int)(el & 15u);
+        const int mv = b.moved[q];
+        const int lam = mv ? l + dir : l;
+        const uint32_t elam = (el & ~15u) | (uint32_t)lam;
+        const float xi = b.x[q], vi = b.v[q];
+        const uint32_t id = b.vid[q];
+        uint32_t m = b.meta[q];
+        const int f = b.nxt[q];
+        const int lanes_e = d.lanes[e];
+        const uint32_t e0 = el & ~15u;
+        // leader candidates and rank in the post-change lane
+        int c1 = -1, c2 = -1, rank;
+        const int mu = lam - dir;   // lane whose movers enter lam
+        if (!mv) {
+            const int rs = b.runst[q];
+            if (q > 0 && b.lasts[q - 1] >= rs) c1 = b.lasts[q - 1];
+            int mov_ahead = 0;
+            if (mu >= 0 && mu < lanes_e) {
+                const uint32_t emu = e0 | (uint32_t)mu;
+                const int p2 = tile_lower_bound(b, n, emu, xi, id);
+                const int st = el_lower_bound(b.el, n, emu);
+                if (p2 > 0 && b.lastm[p2 - 1] >= st) c2 = b.lastm[p2 - 1];
+                mov_ahead = b.mpref[p2] - b.mpref[st];
+            }
+            rank = ((q - rs) - (b.mpref[q] - b.mpref[rs])) + mov_ahead;
+        } else {
+            const int p = b.pos[q];
+            const int st = el_lower_bound(b.el, n, elam);
+            if (p > 0 && b.lasts[p - 1] >= st) c1 = b.lasts[p - 1];
+            const int rs = b.runst[q];
+            if (q > 0 && b.lastm[q - 1] >= rs) c2 = b.lastm[q - 1];
+            rank = ((p - st) - (b.mpref[p] - b.mpref[st])) + (b.mpref[q] - b.mpref[rs]);
+        }
+        int j = c1;
+        if (c2 >= 0) {
+            if (j < 0) j = c2;
+            else if (b.x[c2] < b.x[j] || (b.x[c2] == b.x[j] && b.vid[c2] < b.vid[j])) j = c2;
+        }
+        // post-change vehicles of this edge in lanes below lam
+        const int es = el_lower_bound(b.el, n, e0);
+        const int sl = el_lower_bound(b.el, n, elam);
+        int below = sl - es;
+        if (dir < 0) {
+            const int ee = el_lower_bound(b.el, n, elam + 1);
+            below += b.mpref[ee] - b.mpref[sl];
+        } else if (lam >= 1) {
+            const int s0 = el_lower_bound(b.el, n, elam - 1);
+            below -= b.mpref[sl] - b.mpref[s0];
+        }
+        const int newpos = es + below + rank;
+        if (newpos < 0 || newpos >= n) {   // cannot happen if the layout is consistent
+            atomicOr(&d.ctl->err, kErrNewPos);
+            continue;
+        }
+
+        // kind and gap (A1-A8, A17)
+        const ClassParams cpi = d.cp[m_cls(m)];
+        const bool allowed_l = lane_allowed(m, f, lam);
+        int kind;
+        float s = 0.0f, vl = 0.0f, rear_j = 0.0f;
+        if (j >= 0) {
+            kind = kVeh;
+            rear_j = b.x[j] - d.cp[m_cls(b.meta[j])].len;
+            s = rear_j - xi;
+            vl = b.v[j];
+        } else if (f < 0) {
+            kind = kFree;
+        } else if (m_mand(m) && !allowed_l && m_ww(m) < kPatience) {
+            kind = kStop;
+            s = d.L[e] - xi;
+            vl = 0.0f;
+        } else {
+            const int lf = min(lam, d.lanes[f] - 1);
+            const LaneRear r = d.rear[d.lane_base[f] + lf];
+            if (r.stamp == t) {
+                kind = kLook;
+                s = (d.L[e] - xi) + r.xm;
+                vl = r.v;
+            } else {
+                kind = kFree;
+            }
+        }
+        unsigned br = 0;
+        const float v0 = cpi.v0f * d.lim[e];
+        const float a = idm_acc(vi, v0, vl, s, cpi, kind, br);
+        const float dt = d.dt;
+        float vnew = vi + (a * dt);
+        float xnew;
+        if (vnew >= 0.0f) {
+            xnew = (xi + (vi * dt)) + ((0.5f * a) * (dt * dt));
+        } else {
+            xnew = xi - ((vi * vi) / (2.0f * a));
+            vnew = 0.0f;
+            acc.c[cStopBranch]++;
+        }
+        uint32_t fl = 0;
+        if (kind == kVeh && xnew > rear_j) {
+            xnew = rear_j;
+            acc.c[cClamp]++;
+        }
+        if (f >= 0 && !allowed_l && m_ww(m) < kPatience && xnew >= d.L[e]) {
+            xnew = d.L[e];
+            vnew = 0.0f;
+            m = (m | (1u << 4));
+            m = (m & ~(127u << 8)) | ((uint32_t)(m_ww(m) + 1) << 8);
+            fl |= F_WHOLD;
+            acc.c[cWrongLaneHolds]++;
+        }
+        m = m_set_lane(m, lam);
+        // write the post-step record in the post-change order.  newpos stays
+        // inside this edge's slot range, so the edge id stored at every slot
+        // is unchanged and other workgroups may read it concurrently.
+        const int dst = a0 + newpos;
+        S.x[dst] = xnew;
+        S.v[dst] = vnew;
+        S.vid[dst] = id;
+        S.edge[dst] = e;
+        S.meta[dst] = m;
+        S.nxt[dst] = f;
+        b.xn[q] = xnew;
+        b.fl[q] = fl;
+        b.pel[newpos] = elam;
+        b.inv[newpos] = q;
+    }
+    __syncthreads();
+
+    // ---- lane fronts (requests) and rears (admission and scatter tables)
+    for (int r = tid; r < n; r += kNT) {
+        const uint32_t el = b.pel[r];
+        const bool front = (r == 0) || (b.pel[r - 1] != el);
+        const bool rear = (r == n - 1) || (b.pel[r + 1] != el);
+        if (!front && !rear) continue;
+        const int q = b.inv[r];
+        if (q < 0 || q >= n) {
+            atomicOr(&d.ctl->err, kErrPermutation);
+            continue;
+        }
+        const int e = (int)(el >> 4), lam = (int)(el & 15u);
+        const int gl = d.lane_base[e] + lam;
+        const float xnew = b.xn[q];
+        if (rear) {
+            const int fr = el_lower_bound(b.pel, n, el);
+            LanePost lp;
+            lp.stamp = t;
+            lp.start = a0 + fr;
+            lp.cnt = r - fr + 1;
+            lp.rear_xm = xnew - d.cp[m_cls(b.meta[q])].len;
+            d.post[gl] = lp;
+        }
+        if (front && xnew >= d.L[e] && !(b.fl[q] & F_WHOLD)) {
+            const int f = b.nxt[q];
+            const float xo = b.x[q];
+            Outbox ob;
+            ob.stamp = t;
+            ob.slot = a0 + r;
+            ob.vid = b.vid[q];
+            ob.phi = (xnew == xo) ? 0.0f : (d.L[e] - xo) / (xnew - xo);
+            if (f < 0) {
+                ob.target = -1;
+                ob.xp = 0.0f;
+                ob.key = 0;
+            } else {
+                ob.target = d.lane_base[f] + min(lam, d.lanes[f] - 1);
+                ob.xp = xnew - d.L[e];
+                const int hs = m_held(b.meta[q]) ? d.held_since[ob.vid] : t;
+                ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
+            }
+            d.outbox[gl] = ob;
+            if (atomicMax(&d.req_stamp[e], t) < t) {
+                const int k = atomicAdd(&d.ctl->n_req[par], 1);
+                d.req_edges[par][k] = e;
+            }
+        }
+    }
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
+    __shared__ __align__(16) char lds[kTileCapLds * 64 + 64];
+    __shared__ Scan4 wsh4[kWaves];
+    __shared__ int wsh[kWaves];
+    const int t = d.ctl->t, par = t & 1;
+    const int n = d.ctl->n_act[par];
+    CounterAcc acc;
+    acc.zero();
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        atomicAdd(&d.counters[cActiveSum], (unsigned long long)n);
+        d.ctl->n_pend[par ^ 1] = 0;
+    }
+    const int ntile = (n + kTileWindow - 1) / kTileWindow;
+    const int32_t* edge = d.s[par].edge;
+    for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
+        const int w0 = k * kTileWindow, w1 = min(n, w0 + kTileWindow);
+        const int a0 = first_edge_start(edge, w0, w1, wsh);
+        if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
+        const int a1 = first_edge_start(edge, w1, n, wsh);
+        const int cnt = a1 - a0;
+        if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
+            if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileTooBig);
+            continue;
+        }
+        if (cnt <= kTileCapLds) {
+            process_tile(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4);
+        } else {
+            char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
+            process_tile(d, carve(mine, d.big_cap), a0, cnt, t, par, acc, wsh4);
+        }
+    }
+    flush_counters(d, acc, wsh);
+}
+
+// ---- admission -------------------------------------------------------------
+__device__ inline bool transfer_eligible(const Dev& d, const Outbox& ob, int t) {
+    const LanePost p = d.post[ob.target];
+    return p.stamp != t || (p.rear_xm - ob.xp >= 0.0f);
+}
+
+__device__ inline bool insert_eligible(const Dev& d, int vid, int t) {
+    const LanePost p = d.post[d.ins_gl[vid]];
+    return p.stamp != t || (p.rear_xm >= d.cp[d.cls[vid]].s0);
+}
+
+__device__ inline unsigned long long insert_key(const Dev& d, int vid) {
+    return (1ull << 63) | ((unsigned long long)(uint32_t)d.dep[vid] << 32) | (uint32_t)vid;
+}
+
+__device__ inline void item_ranges(const Dev& d, int t, int par, int& nreq, int& npend, int& due_lo, int& ndue) {
+    nreq = d.ctl->n_req[par];
+    npend = d.ctl->n_pend[par];
+    if (d.max_dep < 0 || t > d.max_dep + 1) {
+        due_lo = 0;
+        ndue = 0;
+        return;
+    }
+    due_lo = t > 0 ? d.due[min(t - 1, d.max_dep)] : 0;
+    const int due_hi = t <= d.max_dep ? d.due[t] : d.due[d.max_dep];
+    ndue = due_hi - due_lo;
+}
+
+__global__ void __launch_bounds__(kNT) k_admit(Dev d) {
+    const int t = d.ctl->t, par = t & 1;
+    int nreq, npend, due_lo, ndue;
+    item_ranges(d, t, par, nreq, npend, due_lo, ndue);
+    const int total = nreq + npend + ndue;
+    for (int i = blockIdx.x * kNT + threadIdx.x; i < total; i += gridDim.x * kNT) {
+        if (i < nreq) {
+            const int e = d.req_edges[par][i];
+            const int base = d.lane_base[e];
+            for (int l = 0; l < d.lanes[e]; ++l) {
+                const Outbox ob = d.outbox[base + l];
+                if (ob.stamp != t || ob.target < 0) continue;
+                if (transfer_eligible(d, ob, t)) atomicMin(&d.win[ob.target], (unsigned long long)ob.key);
+            }
+        } else {
+            const int vid = i < nreq + npend ? d.pend[par][i - nreq] : d.wait_order[due_lo + (i - nreq - npend)];
+            if (insert_eligible(d, vid, t)) atomicMin(&d.win[d.ins_gl[vid]], insert_key(d, vid));
+        }
+    }
+}
+
+__device__ inline void append_entry(const Dev& d, int par, const EntryRec& r, int t) {
+    const int k = atomicAdd(&d.ctl->n_ent[par], 1);
+    d.ent[k] = r;
+    d.enter_stamp[r.gl] = t;
+    atomicAdd(&d.entries[r.edge], 1);
+}
+
+__global__ void __launch_bounds__(kNT) k_commit(Dev d) {
+    __shared__ int wsh[kWaves];
+    const int t = d.ctl->t, par = t & 1;
+    int nreq, npend, due_lo, ndue;
+    item_ranges(d, t, par, nreq, npend, due_lo, ndue);
+    const int total = nreq + npend + ndue;
+    const Slots S = d.s[par];
+    CounterAcc acc;
+    acc.zero();
+    const int stride = gridDim.x * kNT;
+    const int ibeg = blockIdx.x * kNT + threadIdx.x;
+    const int iend = ((total + stride - 1) / stride) * stride;
+    for (int i = ibeg; i < iend; i += stride) {
+        if (i >= total) continue;
+        if (i < nreq) {
+            const int e = d.req_edges[par][i];
+            const int base = d.lane_base[e];
+            // exits of this edge this step, to be summed in ascending vehicle id
+            uint32_t ex_vid[8];
+            float ex_phi[8];
+            int nex = 0;
+            for (int l = 0; l < d.lanes[e]; ++l) {
+                const Outbox ob = d.outbox[base + l];
+                if (ob.stamp != t) continue;
+                const uint32_t m = S.meta[ob.slot];
+                if (ob.target < 0) {                       // arrival at the route end
+                    d.status[ob.vid] = kArrived;
+                    d.fin_x[ob.vid] = S.x[ob.slot];
+                    d.fin_v[ob.vid] = S.v[ob.slot];
+                    d.fin_meta[ob.vid] = m;
+                    d.exit_stamp[base + l] = t;
+                    ex_vid[nex] = ob.vid;
+                    ex_phi[nex] = ob.phi;
+                    nex++;
+                    acc.c[cArrived]++;
+                    continue;
+                }
+                const bool won = transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
+                if (won) {
+                    d.win[ob.target] = ~0ull;              // reset for the next step
+                    const int f = S.nxt[ob.slot];
+                    const int k = d.cursor[ob.vid] + 1;
+                    d.cursor[ob.vid] = k;
+                    const int64_t pos = d.roff[ob.vid] + k + 1;
+                    const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
+                    if (!lane_allowed(m, S.nxt[ob.slot], l)) acc.c[cWaivedExits]++;
+                    EntryRec r;
+                    r.x = ob.xp;
+                    r.v = S.v[ob.slot];
+                    r.vid = ob.vid;
+                    r.edge = f;
+                    r.gl = ob.target;
+                    r.meta = m_make(ob.target - d.lane_base[f], false, false, 0, m_cls(m), conn_mask_of(d, f, nn));
+                    r.nxt = nn;
+                    d.held_since[ob.vid] = -1;
+                    append_entry(d, par, r, t);
+                    d.exit_stamp[base + l] = t;
+                    ex_vid[nex] = ob.vid;
+                    ex_phi[nex] = ob.phi;
+                    nex++;
+                    acc.c[cTransfers]++;
+                } else {                                   // held at the stop line
+                    S.x[ob.slot] = d.L[e];
+                    S.v[ob.slot] = 0.0f;
+                    S.meta[ob.slot] = m | (1u << 5);
+                    if (d.held_since[ob.vid] < 0) d.held_since[ob.vid] = t;
+                    acc.c[cHolds]++;
+                }
+            }
+            // insertion sort by vehicle id, then accumulate in that order
+            for (int a = 1; a < nex; ++a) {
+                const uint32_t kv = ex_vid[a];
+                const float kp = ex_phi[a];
+                int b2 = a - 1;
+                while (b2 >= 0 && ex_vid[b2] > kv) {
+                    ex_vid[b2 + 1] = ex_vid[b2];
+                    ex_phi[b2 + 1] = ex_phi[b2];
+                    --b2;
+                }
+                ex_vid[b2 + 1] = kv;
+                ex_phi[b2 + 1] = kp;
+            }
+            double sum = d.tt_sum[e];
+            for (int a = 0; a < nex; ++a) {
+                const uint32_t vid = ex_vid[a];
+                const double tau = ((double)t + (double)ex_phi[a]) * (double)d.dt;
+                sum += tau - d.tau_in[vid];
+                if (d.status[vid] == kArrived) d.t_arr[vid] = tau;
+                else d.tau_in[vid] = tau;
+            }
+            d.tt_sum[e] = sum;
+            d.tt_cnt[e] += (unsigned long long)nex;
+            d.exits[e] = nex;
+        } else {
+            const int vid = i < nreq + npend ? d.pend[par][i - nreq] : d.wait_order[due_lo + (i - nreq - npend)];
+            const int g = d.ins_gl[vid];
+            const unsigned long long key = insert_key(d, vid);
+            if (insert_eligible(d, vid, t) && d.win[g] == key) {
+                d.win[g] = ~0ull;
+                const int64_t r0 = d.roff[vid];
+                const int e0 = d.redges[r0];
+                const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
+                EntryRec r;
+                r.x = 0.0f;
+                r.v = 0.0f;
+                r.vid = (uint32_t)vid;
+                r.edge = e0;
+                r.gl = g;
+                r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], conn_mask_of(d, e0, nn));
+                r.nxt = nn;
+                d.status[vid] = kActive;
+                d.cursor[vid] = 0;
+                d.held_since[vid] = -1;
+                d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
+                append_entry(d, par, r, t);
+                acc.c[cDeparted]++;
+            } else {
+                const int k = atomicAdd(&d.ctl->n_pend[par ^ 1], 1);
+                d.pend[par ^ 1][k] = vid;
+                acc.c[cInsertDenied]++;
+            }
+        }
+    }
+    flush_counters(d, acc, wsh);
+}
+
+// ---- next layout -----------------------------------------------------------
+__global__ void __launch_bounds__(kNT) k_edge_count(Dev d) {
+    __shared__ int wsh[kWaves];
+    const int t = d.ctl->t, par = t & 1;
+    const int e0 = blockIdx.x * kEdgeBlock;
+    int loc = 0;
+    for (int e = e0 + threadIdx.x; e < min(d.n_edges, e0 + kEdgeBlock); e += kNT) {
+        const int c = d.cnt[e] - d.exits[e] + d.entries[e];
+        d.cnt[e] = c;
+        d.exits[e] = 0;
+        d.entries[e] = 0;
+        loc += c;
+    }
+    const int s = wg_sum(loc, wsh);
+    if (threadIdx.x == 0) d.blk_sum[blockIdx.x] = s;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        d.ctl->n_req[par ^ 1] = 0;
+        d.ctl->n_ent[par ^ 1] = 0;
+    }
+}
+
+__global__ void __launch_bounds__(kNT) k_block_scan(Dev d) {
+    __shared__ Scan4 wsh4[kWaves];
+    const int t = d.ctl->t, par = t & 1;
+    const int nb = d.n_blk;
+    const int chunk = (nb + kNT - 1) / kNT;
+    const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
+    Scan4 loc{0, -1, -1, -1};
+    for (int i = lo; i < hi; ++i) loc.s += d.blk_sum[i];
+    Scan4 run = wg_exclusive_scan4(loc, wsh4);
+    for (int i = lo; i < hi; ++i) {
+        d.blk_off[i] = run.s;
+        run.s += d.blk_sum[i];
+    }
+    if (threadIdx.x == kNT - 1) d.ctl->n_act[par ^ 1] = run.s;
+}
+
+__global__ void __launch_bounds__(kNT) k_edge_offset(Dev d) {
+    __shared__ Scan4 wsh4[kWaves];
+    const int t = d.ctl->t;
+    const int e0 = blockIdx.x * kEdgeBlock;
+    constexpr int kPer = kEdgeBlock / kNT;
+    const int lo = e0 + threadIdx.x * kPer;
+    Scan4 loc{0, -1, -1, -1};
+    for (int e = lo; e < min(d.n_edges, lo + kPer); ++e) loc.s += d.cnt[e];
+    Scan4 run = wg_exclusive_scan4(loc, wsh4);
+    int off = d.blk_off[blockIdx.x] + run.s;
+    for (int e = lo; e < min(d.n_edges, lo + kPer); ++e) {
+        const int c = d.cnt[e];
+        d.edge_off[e] = off;
+        if (c > 0) {
+            int o = off;
+            const int base = d.lane_base[e];
+            for (int l = 0; l < d.lanes[e]; ++l) {
+                const int gl = base + l;
+                const LanePost p = d.post[gl];
+                int nc = (p.stamp == t) ? p.cnt : 0;
+                if (d.exit_stamp[gl] == t) nc -= 1;
+                if (d.enter_stamp[gl] == t) nc += 1;
+                d.lane_newstart[gl] = o;
+                d.lane_newcnt[gl] = nc;
+                o += nc;
+            }
+        }
+        off += c;
+    }
+}
+
+__global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
+    __shared__ bool last;
+    const int t = d.ctl->t, par = t & 1;
+    const int nold = d.ctl->n_act[par];
+    const int nent = d.ctl->n_ent[par];
+    const int nnew = d.ctl->n_act[par ^ 1];
+    const Slots A = d.s[par], B = d.s[par ^ 1];
+    for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nent; i += gridDim.x * kNT) {
+        float x, v;
+        uint32_t vid, meta;
+        int edge, nxt, gl, dst;
+        bool is_rear;
+        if (i < nold) {
+            meta = A.meta[i];
+            edge = A.edge[i];
+            gl = d.lane_base[edge] + m_lane(meta);
+            const LanePost lp = d.post[gl];
+            if (lp.stamp != t) {
+                atomicOr(&d.ctl->err, kErrScatter);
+                continue;
+            }
+            const int r = i - lp.start;
+            const int ex = d.exit_stamp[gl] == t ? 1 : 0;
+            if (ex && r == 0) continue;           // the lane's front left the edge
+            const int nr = r - ex;
+            dst = d.lane_newstart[gl] + nr;
+            is_rear = (nr == d.lane_newcnt[gl] - 1) && (d.enter_stamp[gl] != t);
+            x = A.x[i];
+            v = A.v[i];
+            vid = A.vid[i];
+            nxt = A.nxt[i];
+        } else {
+            const EntryRec r = d.ent[i - nold];
+            gl = r.gl;
+            dst = d.lane_newstart[gl] + d.lane_newcnt[gl] - 1;
+            is_rear = true;
+            x = r.x;
+            v = r.v;
+            vid = r.vid;
+            meta = r.meta;
+            edge = r.edge;
+            nxt = r.nxt;
+        }
+        if (dst < 0 || dst >= nnew) {
+            atomicOr(&d.ctl->err, kErrScatter);
+            continue;
+        }
+        B.x[dst] = x;
+        B.v[dst] = v;
+        B.vid[dst] = vid;
+        B.edge[dst] = edge;
+        B.meta[dst] = meta;
+        B.nxt[dst] = nxt;
+        if (is_rear) {
+            LaneRear lr;
+            lr.xm = x - d.cp[m_cls(meta)].len;
+            lr.v = v;
+            lr.stamp = t + 1;
+            lr.pad = 0;
+            d.rear[gl] = lr;
+        }
+    }
+    // the last workgroup to finish advances the step counter
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const unsigned prev = atomicAdd(&d.ctl->done, 1u);
+        last = (prev == gridDim.x - 1);
+    }
+    __syncthreads();
+    if (last && threadIdx.x == 0) {
+        d.ctl->done = 0;
+        __threadfence();
+        d.ctl->t = t + 1;
+    }
+}
+
+// ---- diagnostics ---------------------------------------------------------
+__global__ void k_probe_fp32(int op, const float* a, const float* b, float* out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float x = a[i], y = b ? b[i] : 0.0f;
+        float r;
+        switch (op) {
+            case 0: r = x / y; break;
+            case 1: r = sqrtf(x); break;
+            case 2: r = x * y; break;
+            case 3: r = x + y; break;
+            default: r = exp_eq2(x); break;
+        }
+        out[i] = r;
+    }
+}
+
+__global__ void k_probe_philox(const uint64_t* ctr, uint64_t k0, uint64_t k1, uint64_t* out, int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const U64x4 r = philox4x64_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);
+        for (int j = 0; j < 4; ++j) out[4 * i + j] = r.w[j];
+    }
+}
+
+__global__ void k_probe_draws(uint64_t seed, const int64_t* t, const int64_t* id, float* u, float* e2, float* e3,
+                              int64_t n) {
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        u[i] = draw_uniform(seed, (int)t[i], (uint32_t)id[i], 1);
+        e2[i] = draw_normal(seed, (int)t[i], (uint32_t)id[i], 2);
+        e3[i] = draw_normal(seed, (int)t[i], (uint32_t)id[i], 3);
+    }
+}
+
+}  // namespace manta

@@ -1,0 +1,174 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the
+same seeded inputs.  The bar: discrete state (status, edge, lane, route
+cursor, held/mandatory/wait flags) and event counters bit-exact; x and v
+within 1e-5 relative (the contract makes them bitwise equal, which is also
+reported); per-edge travel-time sums equal."""
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+DISCRETE = ("status", "edge", "lane", "cursor", "held_since", "mand", "ww")
+
+
+@pytest.fixture(scope="module")
+def M():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    import paper_2007_03614_amd as M
+    return M
+
+
+def compare_states(g, o, where=""):
+    for k in DISCRETE:
+        a, b = np.asarray(g[k]), np.asarray(o[k]).astype(np.asarray(g[k]).dtype)
+        bad = np.nonzero(a != b)[0]
+        assert bad.size == 0, f"{where}: {k} differs for vehicles {bad[:10].tolist()} gpu={a[bad[:5]]} oracle={b[bad[:5]]}"
+    for k in ("x", "v"):
+        a = np.asarray(g[k], np.float32)
+        b = np.asarray(o[k], np.float32)
+        err = np.abs(a.astype(np.float64) - b) / np.maximum(np.abs(b.astype(np.float64)), 1.0)
+        assert err.max(initial=0.0) <= 1e-5, f"{where}: {k} max rel err {err.max()}"
+    for k in ("tau_in", "t_arr"):
+        a, b = np.asarray(g[k]), np.asarray(o[k])
+        assert np.allclose(a, b, rtol=1e-9, atol=1e-9), f"{where}: {k}"
+    return all(np.array_equal(np.asarray(g[k], np.float32), np.asarray(o[k], np.float32)) for k in ("x", "v"))
+
+
+def run_pair(M, oracle_mod, w, checkpoints):
+    g = M.Sim(w)
+    o = oracle_mod.OracleSim(w)
+    t = 0
+    bitwise = True
+    for cp in checkpoints:
+        g.step(cp - t)
+        o.step(cp - t)
+        t = cp
+        gs, os_ = g.state(), o.state()
+        assert gs["t"] == os_["t"] == t
+        bitwise &= compare_states(gs, os_, f"step {t}")
+        gc = dict(zip(M.COUNTERS, gs["counters"].tolist()))
+        assert gc == o.counters(), f"step {t}: counters {gc} vs {o.counters()}"
+    gsum, gcnt = g.edge_stats()
+    osum, ocnt = o.edge_stats()
+    assert np.array_equal(gcnt, ocnt)
+    assert np.array_equal(gsum, osum), np.abs(gsum - osum).max()
+    return g, o, bitwise
+
+
+# ---------------------------------------------------------------- arithmetic
+def test_fp32_division_sqrt_bitwise(M):
+    rng = np.random.default_rng(1)
+    a = np.concatenate([rng.uniform(-50, 50, 1 << 20), rng.standard_normal(1 << 18) * 1e-30,
+                        rng.uniform(1e-3, 1e3, 1 << 18)]).astype(np.float32)
+    b = np.concatenate([rng.uniform(0.01, 40, 1 << 20), rng.uniform(0.1, 10, 1 << 18),
+                        rng.uniform(-1e3, 1e3, 1 << 18)]).astype(np.float32)
+    b[b == 0] = 1.0
+    assert np.array_equal(M.probe_fp32(0, a, b), a / b)
+    pos = np.abs(a)
+    assert np.array_equal(M.probe_fp32(1, pos), np.sqrt(pos))
+    assert np.array_equal(M.probe_fp32(2, a, b), a * b)
+    assert np.array_equal(M.probe_fp32(3, a, b), a + b)
+
+
+def test_eq2_exp_bitwise_vs_oracle(M, oracle_mod):
+    bits_lo = int(np.float32(-17.0).view(np.uint32))
+    ys = np.arange(0x80000000, bits_lo, 13, dtype=np.uint64).astype(np.uint32).view(np.float32)
+    assert np.array_equal(M.probe_fp32(4, ys).view(np.uint32), oracle_mod.expf_c(ys).view(np.uint32))
+
+
+def test_philox_vs_numpy_and_draws_vs_oracle(M, oracle_mod):
+    from test_oracle_math import numpy_philox_block
+    rng = np.random.default_rng(2)
+    ctr = rng.integers(0, 2**63, size=(64, 4), dtype=np.uint64)
+    key = np.array([987654321, 0], np.uint64)
+    got = M.probe_philox(ctr, key)
+    for k in range(ctr.shape[0]):
+        assert got[k].tolist() == numpy_philox_block(ctr[k], key).tolist()
+    t = rng.integers(0, 60000, 4000)
+    vid = rng.integers(0, 3_000_000, 4000)
+    u, e2, e3 = M.probe_draws(77, t, vid)
+    for k in range(0, 4000, 7):
+        assert u[k] == np.float32(oracle_mod.uniform(77, int(t[k]), int(vid[k]), 1))
+        assert e2[k] == np.float32(oracle_mod.normal(77, int(t[k]), int(vid[k]), 2))
+        assert e3[k] == np.float32(oracle_mod.normal(77, int(t[k]), int(vid[k]), 3))
+
+
+# ---------------------------------------------------------------- trajectories
+def test_parity_single_edge_free_road(M, oracle_mod):
+    w = W.single_edge_workload(length=5000.0, n_vehicles=3, depart_step=[0, 0, 40], n_steps=600)
+    _, _, bitwise = run_pair(M, oracle_mod, w, [1, 2, 5, 50, 200, 600])
+    assert bitwise
+
+
+def test_parity_config1_full(M, oracle_mod, c1):
+    """10x10 grid, 2,000 vehicles, 3,600 steps: every 100 steps."""
+    g, o, bitwise = run_pair(M, oracle_mod, c1, list(range(1, 20)) + list(range(100, 3601, 100)))
+    assert bitwise
+    st = g.state()
+    assert (st["status"] == 2).all()
+
+
+def test_parity_config1_four_classes(M, oracle_mod):
+    w = W.config1(n_classes=4)
+    w.params = W.jitter_params(w.params, 0.1, seed=5)
+    _, _, bitwise = run_pair(M, oracle_mod, w, [10, 500, 1000, 2000, 3600])
+    assert bitwise
+
+
+def test_parity_long_edge_big_tiles(M, oracle_mod):
+    """One 8 km two-lane edge filled by 1,500 vehicles: tiles far above the LDS
+    capacity go through the global-memory tile path; lane changes by incentive."""
+    p = W.base_params(2)
+    p.v0_factor[1] = np.float32(0.6)
+    w = W.single_edge_workload(length=8000.0, lanes=2, n_vehicles=1500, depart_step=np.arange(1500) // 2,
+                               n_steps=2400, params=p)
+    w.vclass[::3] = 1
+    g, o, bitwise = run_pair(M, oracle_mod, w, [100, 600, 1200, 1800, 2400])
+    assert bitwise
+    assert o.counters()["lane_changes"] > 100
+
+
+def test_parity_scaled_config2(M, oracle_mod):
+    """Config 2's recipe on a 30x30 grid + ring with 15,000 vehicles, full 3 h."""
+    w = W.scaled_config2(n_vehicles=15000, rows=30, cols=30, n_steps=21600)
+    _, _, bitwise = run_pair(M, oracle_mod, w, [1000, 5000, 9000, 13000, 17000, 21600])
+    assert bitwise
+
+
+def test_parity_config2_full_size_prefix(M, oracle_mod):
+    """Full-size config 2 (200,000 vehicles, 35,800 edges): parity over the
+    first 2,400 steps, which the oracle finishes in seconds."""
+    w = W.config2()
+    _, _, bitwise = run_pair(M, oracle_mod, w, [600, 1200, 2400])
+    assert bitwise
+
+
+def test_determinism_and_resume(M, c1):
+    a = M.Sim(c1)
+    a.step(2000)
+    sa = a.state()
+    b = M.Sim(c1)
+    b.step(1000)
+    mid = b.state()
+    c = M.Sim(c1)
+    c.write_state(mid)
+    c.step(1000)
+    b.step(1000)
+    for s in (b.state(), c.state()):
+        for k in sa:
+            if k == "t":
+                assert s[k] == sa[k]
+            else:
+                assert np.array_equal(np.asarray(s[k]), np.asarray(sa[k])), k
+
+
+def test_empty_and_tiny_inputs(M, oracle_mod):
+    w = W.single_edge_workload(length=100.0, n_vehicles=1, depart_step=[5], n_steps=50)
+    run_pair(M, oracle_mod, w, [1, 5, 6, 7, 50])
+    w0 = W.single_edge_workload(length=100.0, n_vehicles=0, n_steps=5)
+    g = M.Sim(w0)
+    g.step(5)
+    assert g.state()["t"] == 5 and g.n_active == 0

@@ -141,12 +141,21 @@ def base_params(n_classes: int = 1, seed: int = 0) -> Params:
                   veh_len=f(5.0), seed=seed)
 
 
+# calibration bounds of the car-following parameters (Sec. IV-A)
+BOUNDS = dict(v0_factor=(0.05, 2.0), T=(0.1, 2.0), a=(1.0, 10.0), b=(1.0, 10.0), s0=(1.0, 5.0))
+
+
 def jitter_params(p: Params, rel: float, seed: int, purpose: int = _P_CLASS) -> Params:
-    """Each (class, parameter) scaled by (1 + U[-rel, rel])."""
+    """Each (class, parameter) scaled by (1 + U[-rel, rel]), then clipped to
+    the calibration bounds (a = 1 sits on its lower bound)."""
     r = _rng(seed, purpose)
     k = p.n_classes
-    g = lambda arr: (arr.astype(np.float64) * (1.0 + r.uniform(-rel, rel, size=k))).astype(np.float32)
-    return Params(v0_factor=g(p.v0_factor), T=g(p.T), a=g(p.a), b=g(p.b), s0=g(p.s0),
+
+    def g(arr, name):
+        lo, hi = BOUNDS[name]
+        return np.clip(arr.astype(np.float64) * (1.0 + r.uniform(-rel, rel, size=k)), lo, hi).astype(np.float32)
+    return Params(v0_factor=g(p.v0_factor, "v0_factor"), T=g(p.T, "T"), a=g(p.a, "a"), b=g(p.b, "b"),
+                  s0=g(p.s0, "s0"),
                   veh_len=p.veh_len.copy(), dt=p.dt, seed=p.seed,
                   intersection_mode=p.intersection_mode, record_every=p.record_every)
 
