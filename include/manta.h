@@ -139,19 +139,17 @@ sim_status sim_set_stream(sim_handle *h, void *hip_stream);
 sim_status sim_step(sim_handle *h, int32_t n);
 
 /* Measurement form of sim_step: the n steps are launched kernel by kernel
- * (not from the captured graph) with a HIP event recorded on the handle's
- * stream before the first kernel of the run and after every kernel; then the
- * stream is synchronized.  kernel_ms[SIM_N_KERNELS] (may be NULL) receives
- * the summed time between consecutive events attributed to each kernel of
- * the step, total_ms (may be NULL) the time from the first to the last event.
- * Results are identical to sim_step. */
+ * (not from the captured graph), each kernel between a start and a stop HIP
+ * event recorded on the handle's stream at the kernel's own start and end;
+ * then the stream is synchronized.  kernel_ms[SIM_N_KERNELS] (may be NULL)
+ * receives each kernel's summed duration over the n steps, total_ms (may be
+ * NULL) the time from the first start to the last stop.  Results are
+ * identical to sim_step. */
 enum {
     SIM_K_TILE_STEP = 0,   /* lane changes, leaders, Eq. (1), integration */
-    SIM_K_ADMIT,           /* intersection admission: eligibility + priority */
-    SIM_K_COMMIT,          /* transfers, arrivals, departures, travel times */
-    SIM_K_EDGE_COUNT,
-    SIM_K_BLOCK_SCAN,
-    SIM_K_EDGE_OFFSET,
+    SIM_K_TILE_BIG,        /* the same for tiles above 512 vehicles */
+    SIM_K_ADMIT,           /* intersection admission: eligibility + priority claim */
+    SIM_K_COMMIT,          /* transfers, arrivals, departures, travel times, new counts */
     SIM_K_SCATTER,         /* next sorted layout and look-ahead table */
     SIM_N_KERNELS
 };

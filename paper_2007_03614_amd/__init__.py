@@ -90,7 +90,7 @@ _lib.sim_probe_philox.restype = I32
 _lib.sim_probe_draws.argtypes = [U64, P, P, P, P, P, I64]
 _lib.sim_probe_draws.restype = I32
 
-KERNELS = ["k_tile_step", "k_admit", "k_commit", "k_edge_count", "k_block_scan", "k_edge_offset", "k_scatter"]
+KERNELS = ["k_tile_step", "k_tile_big", "k_admit", "k_commit", "k_scatter"]
 
 EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
             "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",

@@ -1,5 +1,6 @@
 // libmanta host side: input validation, device layout, the step launch
 // sequence (replayed from a captured HIP graph), and state I/O.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -75,7 +76,7 @@ struct sim_handle {
     Dev d{};
     int t = 0;
     int n_veh = 0, n_edges = 0, n_lanes = 0, n_classes = 0;
-    int g_tile = 1, g_items = 1, g_scatter = 1, n_blk = 1;
+    int g_tile = 1, g_big = 1, g_items = 1, g_ins = 1, g_scatter = 1, n_blk = 1;
     // host copies of the static inputs needed for state I/O
     std::vector<int64_t> roff;
     std::vector<int32_t> redges, dep, lanes, lane_base, conn_off, conn_to, ins_lane;
@@ -198,26 +199,24 @@ void validate(const sim_network* net, const sim_routes* r, const sim_idm_params*
     }
 }
 
-// the kernels of one step, in order; ev (optional) gets an event after each
+// The kernels of one step, in order.  ev (optional): 2 events per kernel,
+// recorded by the runtime at the kernel's start and end.
 void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     const Dev& d = h->d;
-    auto mark = [&](int k) {
-        if (ev) HIP_OK(hipEventRecord(ev[k], s));
-    };
-    hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), dim3(kNT), 0, s, d);
-    mark(0);
-    hipLaunchKernelGGL(k_admit, dim3(h->g_items), dim3(kNT), 0, s, d);
-    mark(1);
-    hipLaunchKernelGGL(k_commit, dim3(h->g_items), dim3(kNT), 0, s, d);
-    mark(2);
-    hipLaunchKernelGGL(k_edge_count, dim3(h->n_blk), dim3(kNT), 0, s, d);
-    mark(3);
-    hipLaunchKernelGGL(k_block_scan, dim3(1), dim3(kNT), 0, s, d);
-    mark(4);
-    hipLaunchKernelGGL(k_edge_offset, dim3(h->n_blk), dim3(kNT), 0, s, d);
-    mark(5);
-    hipLaunchKernelGGL(k_scatter, dim3(h->g_scatter), dim3(kNT), 0, s, d);
-    mark(6);
+    const dim3 b(kNT);
+    if (!ev) {
+        hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
+        hipLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, d);
+        hipLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, d);
+        hipLaunchKernelGGL(k_commit, dim3(h->n_blk + h->g_ins), b, 0, s, d);
+        hipLaunchKernelGGL(k_scatter, dim3(h->g_scatter), b, 0, s, d);
+        return;
+    }
+    hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
+    hipExtLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
+    hipExtLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, ev[4], ev[5], 0, d);
+    hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk + h->g_ins), b, 0, s, ev[6], ev[7], 0, d);
+    hipExtLaunchKernelGGL(k_scatter, dim3(h->g_scatter), b, 0, s, ev[8], ev[9], 0, d);
 }
 
 void capture_graph(sim_handle* h) {
@@ -300,6 +299,10 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
             d.lim = h->upload(net->speed_limit_mps, E);
             d.lanes = h->upload(h->lanes.data(), E);
             d.lane_base = h->upload(h->lane_base.data(), E + 1);
+            std::vector<int> lane_edge(NL);
+            for (int e = 0; e < E; ++e)
+                for (int l = 0; l < h->lanes[e]; ++l) lane_edge[h->lane_base[e] + l] = e;
+            d.lane_edge = h->upload(lane_edge.data(), NL);
             d.conn_off = h->upload(net->conn_off, E + 1);
             d.conn_to = h->upload(net->conn_to, NC);
             d.conn_mask = h->upload(net->conn_lane_mask, NC);
@@ -370,7 +373,9 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
             const long long cap_all = std::min<long long>(std::max(N, 1), (long long)kTileWindow - 1 + max_edge);
             d.big_cap = (int)std::max<long long>(kTileCapLds + 1, cap_all);
             h->g_tile = std::max(1, std::min(1024, (N + kTileWindow - 1) / kTileWindow));
-            h->g_items = std::max(1, std::min(1024, (E + N + kNT - 1) / kNT));
+            h->g_big = std::max(1, std::min(256, h->g_tile));
+            h->g_items = std::max(1, std::min(512, (E + N + kNT - 1) / kNT));
+            h->g_ins = std::max(1, std::min(256, (N + kNT - 1) / kNT));
             h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
             h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
             d.n_blk = h->n_blk;
@@ -401,20 +406,20 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
             d.win = h->dev<unsigned long long>(NL);
             d.exit_stamp = h->dev<int>(NL);
             d.enter_stamp = h->dev<int>(NL);
-            d.lane_newstart = h->dev<int>(NL);
+            d.lane_rel = h->dev<int>(NL);
             d.lane_newcnt = h->dev<int>(NL);
             d.cnt = h->dev<int>(E);
-            d.exits = h->dev<int>(E);
             d.entries = h->dev<int>(E);
             d.req_stamp = h->dev<int>(E);
-            d.edge_off = h->dev<int>(E);
+            d.edge_rel = h->dev<int>(E);
             d.blk_sum = h->dev<int>(h->n_blk);
             d.blk_off = h->dev<int>(h->n_blk);
             d.tt_sum = h->dev<double>(E);
             d.tt_cnt = h->dev<unsigned long long>(E);
             d.ctl = h->dev<Ctl>(1);
-            d.counters = h->dev<unsigned long long>(cNumCounters);
-            d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_tile);
+            d.counters = h->dev<unsigned long long>(cNumCounters * kCounterCopies);
+            d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindow + 2));
+            d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big);
             // ---- initial values
             HIP_OK(hipMemset(d.rear, 0xFF, sizeof(LaneRear) * NL));
             HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * NL));
@@ -424,12 +429,11 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
             HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * E));
             HIP_OK(hipMemset(d.cnt, 0, sizeof(int) * E));
-            HIP_OK(hipMemset(d.exits, 0, sizeof(int) * E));
             HIP_OK(hipMemset(d.entries, 0, sizeof(int) * E));
             HIP_OK(hipMemset(d.tt_sum, 0, sizeof(double) * E));
             HIP_OK(hipMemset(d.tt_cnt, 0, sizeof(unsigned long long) * E));
             HIP_OK(hipMemset(d.ctl, 0, sizeof(Ctl)));
-            HIP_OK(hipMemset(d.counters, 0, sizeof(unsigned long long) * cNumCounters));
+            HIP_OK(hipMemset(d.counters, 0, sizeof(unsigned long long) * cNumCounters * kCounterCopies));
             HIP_OK(hipMemset(d.status, 0, NV));
             HIP_OK(hipMemset(d.cursor, 0, sizeof(int) * NV));
             HIP_OK(hipMemset(d.held_since, 0xFF, sizeof(int) * NV));
@@ -477,26 +481,27 @@ sim_status sim_step_timed(sim_handle* h, int32_t n, double* kernel_ms, double* t
     }
     std::vector<hipEvent_t> ev;
     sim_status st = guarded(h, [&] {
-        ev.resize((size_t)n * SIM_N_KERNELS + 1, nullptr);
+        const size_t per = 2 * SIM_N_KERNELS;
+        ev.resize((size_t)n * per, nullptr);
         for (auto& e : ev) HIP_OK(hipEventCreate(&e));
-        HIP_OK(hipEventRecord(ev[0], h->stream));
-        for (int q = 0; q < n; ++q) launch_step(h, h->stream, &ev[1 + (size_t)q * SIM_N_KERNELS]);
+        for (int q = 0; q < n; ++q) launch_step(h, h->stream, &ev[(size_t)q * per]);
         HIP_OK(hipGetLastError());
-        HIP_OK(hipEventSynchronize(ev.back()));
         h->t += n;
         double ks[SIM_N_KERNELS] = {0};
-        for (int q = 0; q < n; ++q)
-            for (int k = 0; k < SIM_N_KERNELS; ++k) {
-                const size_t i = 1 + (size_t)q * SIM_N_KERNELS + k;
-                float ms = 0.f;
-                HIP_OK(hipEventElapsedTime(&ms, ev[i - 1], ev[i]));
-                ks[k] += ms;
-            }
+        if (n > 0) {
+            HIP_OK(hipEventSynchronize(ev.back()));
+            for (int q = 0; q < n; ++q)
+                for (int k = 0; k < SIM_N_KERNELS; ++k) {
+                    float ms = 0.f;
+                    HIP_OK(hipEventElapsedTime(&ms, ev[(size_t)q * per + 2 * k], ev[(size_t)q * per + 2 * k + 1]));
+                    ks[k] += ms;
+                }
+        }
         if (kernel_ms)
             for (int k = 0; k < SIM_N_KERNELS; ++k) kernel_ms[k] = ks[k];
         if (total_ms) {
             float ms = 0.f;
-            HIP_OK(hipEventElapsedTime(&ms, ev.front(), ev.back()));
+            if (n > 0) HIP_OK(hipEventElapsedTime(&ms, ev.front(), ev.back()));
             *total_ms = ms;
         }
     });
@@ -512,7 +517,7 @@ sim_status sim_n_active(sim_handle* h, int32_t* out) {
         HIP_OK(hipStreamSynchronize(h->stream));
         HIP_OK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
         if (c.err) throw Fail{SIM_EDEVICE, fmt("device layout check failed (code %d)", c.err)};
-        *out = c.n_act[c.t & 1];
+        *out = c.n_act[c.t_a & 1];
     });
 }
 
@@ -525,7 +530,7 @@ sim_status sim_read_state(sim_handle* h, sim_state* o) {
         Ctl c;
         HIP_OK(hipMemcpy(&c, d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
         if (c.err) throw Fail{SIM_EDEVICE, fmt("device layout check failed (code %d)", c.err)};
-        const int par = c.t & 1, na = c.n_act[par];
+        const int par = c.t_a & 1, na = c.n_act[par];
         std::vector<float> sx(na), sv(na), fx(N), fv(N);
         std::vector<uint32_t> svid(na), smeta(na), fmeta(N);
         std::vector<int32_t> sedge(na), cur(N), hs(N);
@@ -591,11 +596,15 @@ sim_status sim_read_state(sim_handle* h, sim_state* o) {
             if (o->t_arr) o->t_arr[i] = tar[i];
         }
         if (o->counters) {
-            unsigned long long cc[cNumCounters];
+            unsigned long long cc[cNumCounters * kCounterCopies];
             HIP_OK(hipMemcpy(cc, d.counters, sizeof(cc), hipMemcpyDeviceToHost));
-            for (int k = 0; k < cNumCounters; ++k) o->counters[k] = (int64_t)cc[k];
+            for (int k = 0; k < cNumCounters; ++k) {
+                unsigned long long v = 0;
+                for (int q = 0; q < kCounterCopies; ++q) v += cc[k * kCounterCopies + q];
+                o->counters[k] = (int64_t)v;
+            }
         }
-        o->t = c.t;
+        o->t = c.t_a;
     });
 }
 
@@ -703,16 +712,16 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * h->n_edges));
-        HIP_OK(hipMemset(d.exits, 0, sizeof(int) * h->n_edges));
         HIP_OK(hipMemset(d.entries, 0, sizeof(int) * h->n_edges));
         Ctl c{};
-        c.t = t;
+        c.t_a = t;
+        c.t_b = t;
         c.n_act[par] = na;
         c.n_pend[par] = (int)pend.size();
         HIP_OK(hipMemcpy(d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice));
         if (in->counters) {
-            unsigned long long cc[cNumCounters];
-            for (int k = 0; k < cNumCounters; ++k) cc[k] = (unsigned long long)in->counters[k];
+            unsigned long long cc[cNumCounters * kCounterCopies] = {};
+            for (int k = 0; k < cNumCounters; ++k) cc[k * kCounterCopies] = (unsigned long long)in->counters[k];
             HIP_OK(hipMemcpy(d.counters, cc, sizeof(cc), hipMemcpyHostToDevice));
         }
         HIP_OK(hipDeviceSynchronize());

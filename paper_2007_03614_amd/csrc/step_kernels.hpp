@@ -8,14 +8,13 @@
 // stamped with the step they are valid for), the rear after the move
 // (admission), and the post-lane-change run of each lane (scatter).
 //
-// One step = 7 launches, all reading the step number from device memory, so
+// One step = 5 launches, all reading the step number from device memory, so
 // a captured graph of one step can be replayed for every step:
 //   k_tile_step   Phases 1-2 per tile of whole edges, staged in LDS
+//   k_tile_big    the same for tiles above 512 vehicles (1,024 threads)
 //   k_admit       eligibility + atomicMin of a 64-bit priority key per lane
-//   k_commit      winners, losers, arrivals, per-edge travel-time sums
-//   k_edge_count  new per-edge counts + per-block sums
-//   k_block_scan  scan of the block sums (one workgroup)
-//   k_edge_offset per-edge offsets, per-lane new starts
+//   k_commit      per edge: winners, losers, arrivals, travel-time sums, new
+//                 lane/edge counts and offsets; departures; block-sum scan
 //   k_scatter     write the next layout and the next look-ahead table
 #pragma once
 #include <hip/hip_runtime.h>
@@ -29,7 +28,10 @@ constexpr int kNT = 256;                 // threads per workgroup (4 waves)
 constexpr int kWaves = kNT / 64;
 constexpr int kTileWindow = 256;         // a tile = the edges whose first slot lies in a 256-slot window
 constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
-constexpr int kEdgeBlock = 1024;         // edges per block in the offset scan
+constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
+constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
+constexpr int kBigCapLds = 2304;         // vehicles per big tile piece staged in LDS (144 KiB)
+constexpr int kCounterCopies = 32;       // each counter is spread over 32 slots (fewer colliding atomics)
 
 // ---- vehicle meta word ---------------------------------------------------
 // bits 0-3 lane | 4 mandatory | 5 held at stop line | 8-14 wrong-lane wait |
@@ -54,14 +56,20 @@ enum Counter {
 };
 
 struct Ctl {
-    int t;
+    // The step number, kept twice so that no kernel has to change a value its
+    // own workgroups are still reading: the tile kernels and k_admit read t_a,
+    // k_commit and k_scatter read t_b.  k_tile_step sets t_b = t_a; the last
+    // commit workgroup sets t_a = t + 1.
+    int t_a;
+    int t_b;
     int n_act[2];
     int n_req[2];
     int n_pend[2];
     int n_ent[2];
-    unsigned done;
+    int n_big[2];     // tiles above kTileCapLds, listed for k_tile_big
+    unsigned done2;   // commit edge blocks finished (last one scans block sums)
     int err;          // non-zero: a layout bound check failed (see kErr*)
-    int pad[6];
+    int pad[4];
 };
 
 enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
@@ -153,14 +161,14 @@ struct Dev {
     unsigned long long* win;
     int* exit_stamp;
     int* enter_stamp;
-    int* lane_newstart;
+    const int* lane_edge;       // edge of each global lane
+    int* lane_rel;              // next layout: lane start relative to its edge
     int* lane_newcnt;
     // per edge
     int* cnt;
-    int* exits;
-    int* entries;
+    int* entries;               // claimed lanes of the edge this step
     int* req_stamp;
-    int* edge_off;
+    int* edge_rel;              // next layout: edge start relative to its block
     int* blk_sum;
     int* blk_off;
     int n_blk;
@@ -170,7 +178,9 @@ struct Dev {
     int* req_edges[2];
     int* pend[2];
     EntryRec* ent;
-    // big-tile scratch
+    // big tiles: (first, end) slot pairs, and global scratch for single
+    // edges beyond the LDS of a workgroup
+    int* big_list;
     char* big;
     int big_cap;                // vehicles per workgroup region
 };
@@ -262,7 +272,8 @@ __device__ inline Scan4 scan4_op(Scan4 x, Scan4 y) {
     return Scan4{x.s + y.s, max(x.a, y.a), max(x.b, y.b), max(x.c, y.c)};
 }
 
-// exclusive workgroup scan of one Scan4 per thread; wsh: kWaves Scan4 in LDS
+// exclusive workgroup scan of one Scan4 per thread; wsh: NT/64 Scan4 in LDS
+template <int NT = kNT>
 __device__ inline Scan4 wg_exclusive_scan4(Scan4 v, Scan4* wsh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     Scan4 inc = v;
@@ -310,11 +321,14 @@ struct CounterAcc {
     }
 };
 
-__device__ inline void flush_counters(const Dev& d, CounterAcc& acc, int* wsh) {
-    for (int k = 0; k < cNumCounters; ++k) {
-        const int s = wg_sum((int)acc.c[k], wsh);
-        if (threadIdx.x == 0 && s) atomicAdd(&d.counters[k], (unsigned long long)s);
-    }
+// counters: per-thread registers -> LDS atomics -> one global atomic each
+__device__ inline void flush_counters_lds(const Dev& d, const CounterAcc& acc, unsigned* shc) {
+    for (int k = 0; k < cNumCounters; ++k)
+        if (acc.c[k]) atomicAdd(&shc[k], acc.c[k]);
+    __syncthreads();
+    if (threadIdx.x < cNumCounters && shc[threadIdx.x])
+        atomicAdd(&d.counters[threadIdx.x * kCounterCopies + (blockIdx.x % kCounterCopies)],
+                  (unsigned long long)shc[threadIdx.x]);
 }
 
 __device__ inline uint32_t conn_mask_of(const Dev& d, int e, int f) {
@@ -331,8 +345,10 @@ __device__ inline bool lane_allowed(uint32_t meta, int nxt, int l) {
 // ---- tile search ---------------------------------------------------------
 // first slot s in [lo, hi) that starts an edge (s == 0 or edge differs from
 // s - 1), or hi if none; every thread of the workgroup gets the answer
+template <int NT>
 __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int* wsh) {
-    for (int base = lo; base < hi; base += kNT) {
+    constexpr int kW = NT / 64;
+    for (int base = lo; base < hi; base += NT) {
         const int s = base + (int)threadIdx.x;
         bool f = false;
         if (s < hi) f = (s == 0) || (edge[s] != edge[s - 1]);
@@ -342,7 +358,7 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
         if ((threadIdx.x & 63) == 0) wsh[wave] = bal ? (base + wave * 64 + (__ffsll((long long)bal) - 1)) : INT32_MAX;
         __syncthreads();
         int m = INT32_MAX;
-        for (int w = 0; w < kWaves; ++w) m = min(m, wsh[w]);
+        for (int w = 0; w < kW; ++w) m = min(m, wsh[w]);
         __syncthreads();
         if (m != INT32_MAX) return m;
     }
@@ -350,6 +366,7 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
 }
 
 // ---- Phases 1-2 for one tile ----------------------------------------------
+template <int NT>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
                                     CounterAcc& acc, Scan4* wsh4) {
     const Slots S = d.s[par];
@@ -357,7 +374,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     const int dir = (t % 2 == 0) ? -1 : 1;
 
     // load S_t (coalesced)
-    for (int q = tid; q < n; q += kNT) {
+    for (int q = tid; q < n; q += NT) {
         const int s = a0 + q;
         const uint32_t m = S.meta[s];
         b.x[q] = S.x[s];
@@ -370,7 +387,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
 
     // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t
-    for (int q = tid; q < n; q += kNT) {
+    for (int q = tid; q < n; q += NT) {
         uint32_t m = b.meta[q];
         int moved = 0, pos = 0;
         if (!m_held(m)) {
@@ -460,7 +477,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
 
     // ---- mover prefix sums and last-mover / last-stayer / run-start maxima
     {
-        const int chunk = (n + kNT - 1) / kNT;
+        const int chunk = (n + NT - 1) / NT;
         const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
         Scan4 loc{0, -1, -1, -1};
         for (int q = lo; q < hi; ++q) {
@@ -469,7 +486,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             if (mv) loc.a = q; else loc.b = q;
             if (q == 0 || b.el[q] != b.el[q - 1]) loc.c = q;
         }
-        Scan4 run = wg_exclusive_scan4(loc, wsh4);
+        Scan4 run = wg_exclusive_scan4<NT>(loc, wsh4);
         for (int q = lo; q < hi; ++q) {
             const int mv = b.moved[q];
             b.mpref[q] = run.s;
@@ -483,11 +500,11 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         if (hi == n && lo < hi) b.mpref[n] = run.s;
         if (n == 0 && tid == 0) b.mpref[0] = 0;
     }
-    for (int q = tid; q < n; q += kNT) b.inv[q] = -1;
+    for (int q = tid; q < n; q += NT) b.inv[q] = -1;
     __syncthreads();
 
     // ---- Phase 2: leader on the post-change lane, Eq. (1), integration
-    for (int q = tid; q < n; q += kNT) {
+    for (int q = tid; q < n; q += NT) {
         const uint32_t el = b.el[q];
         const int e = (int)(el >> 4), l = (int)(el & 15u);
         const int mv = b.moved[q];
@@ -616,7 +633,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
 
     // ---- lane fronts (requests) and rears (admission and scatter tables)
-    for (int r = tid; r < n; r += kNT) {
+    for (int r = tid; r < n; r += NT) {
         const uint32_t el = b.pel[r];
         const bool front = (r == 0) || (b.pel[r - 1] != el);
         const bool rear = (r == n - 1) || (b.pel[r + 1] != el);
@@ -666,38 +683,104 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
 }
 
+// Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
+// tiles go to a list for k_tile_big.
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ __align__(16) char lds[kTileCapLds * 64 + 64];
     __shared__ Scan4 wsh4[kWaves];
     __shared__ int wsh[kWaves];
-    const int t = d.ctl->t, par = t & 1;
+    __shared__ unsigned shc[cNumCounters];
+    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    const int t = d.ctl->t_a, par = t & 1;
     const int n = d.ctl->n_act[par];
     CounterAcc acc;
     acc.zero();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
-        atomicAdd(&d.counters[cActiveSum], (unsigned long long)n);
+        atomicAdd(&d.counters[cActiveSum * kCounterCopies], (unsigned long long)n);
+        // the later kernels of this step read t_b; lists of the next step
+        // are unused during this one
+        d.ctl->t_b = t;
         d.ctl->n_pend[par ^ 1] = 0;
+        d.ctl->n_req[par ^ 1] = 0;
+        d.ctl->n_ent[par ^ 1] = 0;
+        d.ctl->n_big[par ^ 1] = 0;
     }
+    __syncthreads();
     const int ntile = (n + kTileWindow - 1) / kTileWindow;
     const int32_t* edge = d.s[par].edge;
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
         const int w0 = k * kTileWindow, w1 = min(n, w0 + kTileWindow);
-        const int a0 = first_edge_start(edge, w0, w1, wsh);
+        const int a0 = first_edge_start<kNT>(edge, w0, w1, wsh);
         if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
-        const int a1 = first_edge_start(edge, w1, n, wsh);
+        const int a1 = first_edge_start<kNT>(edge, w1, n, wsh);
         const int cnt = a1 - a0;
         if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
             if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileTooBig);
             continue;
         }
         if (cnt <= kTileCapLds) {
-            process_tile(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4);
-        } else {
-            char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
-            process_tile(d, carve(mine, d.big_cap), a0, cnt, t, par, acc, wsh4);
+            process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4);
+        } else if (threadIdx.x == 0) {
+            const int q = atomicAdd(&d.ctl->n_big[par], 1);
+            d.big_list[2 * q] = a0;
+            d.big_list[2 * q + 1] = a1;
         }
     }
-    flush_counters(d, acc, wsh);
+    flush_counters_lds(d, acc, shc);
+}
+
+// Tiles above kTileCapLds: 1,024-thread workgroups with kBigCapLds vehicles
+// of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
+// single edge larger than the LDS runs from the global-memory scratch.
+__global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
+    __shared__ __align__(16) char lds[kBigCapLds * 64 + 64];
+    __shared__ Scan4 wsh4[kBigNT / 64];
+    __shared__ int wsh[kBigNT / 64];
+    __shared__ unsigned shc[cNumCounters];
+    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = d.ctl->t_a, par = t & 1;
+    const int nbig = d.ctl->n_big[par];
+    const int32_t* edge = d.s[par].edge;
+    CounterAcc acc;
+    acc.zero();
+    for (int k = blockIdx.x; k < nbig; k += gridDim.x) {
+        const int a0 = d.big_list[2 * k], a1 = d.big_list[2 * k + 1];
+        int pos = a0;
+        while (pos < a1) {
+            const int lim = min(a1, pos + kBigCapLds);
+            int end;
+            if (lim == a1) {
+                end = a1;
+            } else {
+                // last edge start in (pos, lim]
+                end = -1;
+                for (int base = lim; base > pos && end < 0; base -= kBigNT) {
+                    const int s = base - (int)threadIdx.x;
+                    const bool f = (s > pos) && (s < a1) && edge[s] != edge[s - 1];
+                    const unsigned long long bal = __ballot(f);
+                    const int wave = threadIdx.x >> 6;
+                    __syncthreads();
+                    if ((threadIdx.x & 63) == 0) wsh[wave] = bal ? (base - wave * 64 - (__ffsll((long long)bal) - 1)) : -1;
+                    __syncthreads();
+                    int m = -1;
+                    for (int w = 0; w < kBigNT / 64; ++w) m = max(m, wsh[w]);
+                    __syncthreads();
+                    end = m;
+                }
+                if (end < 0) end = first_edge_start<kBigNT>(edge, lim, a1, wsh);   // one edge beyond the LDS
+            }
+            const int cnt = end - pos;
+            if (cnt <= kBigCapLds) {
+                process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4);
+            } else {
+                char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
+                process_tile<kBigNT>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4);
+            }
+            pos = end;
+        }
+    }
+    flush_counters_lds(d, acc, shc);
 }
 
 // ---- admission -------------------------------------------------------------
@@ -728,8 +811,20 @@ __device__ inline void item_ranges(const Dev& d, int t, int par, int& nreq, int&
     ndue = due_hi - due_lo;
 }
 
+// An eligible request lowers the lane's 64-bit key with atomicMin; the
+// smallest key wins whatever the order of the atomics.  The request that
+// finds the lane unclaimed also counts one entry for the lane's edge (exactly
+// one request per claimed lane sees the reset value).
+__device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t) {
+    const unsigned long long old = atomicMin(&d.win[gl], key);
+    if (old == ~0ull) {
+        d.enter_stamp[gl] = t;
+        atomicAdd(&d.entries[d.lane_edge[gl]], 1);
+    }
+}
+
 __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
-    const int t = d.ctl->t, par = t & 1;
+    const int t = d.ctl->t_a, par = t & 1;
     int nreq, npend, due_lo, ndue;
     item_ranges(d, t, par, nreq, npend, due_lo, ndue);
     const int total = nreq + npend + ndue;
@@ -740,121 +835,195 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
             for (int l = 0; l < d.lanes[e]; ++l) {
                 const Outbox ob = d.outbox[base + l];
                 if (ob.stamp != t || ob.target < 0) continue;
-                if (transfer_eligible(d, ob, t)) atomicMin(&d.win[ob.target], (unsigned long long)ob.key);
+                if (transfer_eligible(d, ob, t)) claim(d, ob.target, ob.key, t);
             }
         } else {
             const int vid = i < nreq + npend ? d.pend[par][i - nreq] : d.wait_order[due_lo + (i - nreq - npend)];
-            if (insert_eligible(d, vid, t)) atomicMin(&d.win[d.ins_gl[vid]], insert_key(d, vid));
+            if (insert_eligible(d, vid, t)) claim(d, d.ins_gl[vid], insert_key(d, vid), t);
         }
     }
 }
 
-__device__ inline void append_entry(const Dev& d, int par, const EntryRec& r, int t) {
+__device__ inline void append_entry(const Dev& d, int par, const EntryRec& r) {
     const int k = atomicAdd(&d.ctl->n_ent[par], 1);
     d.ent[k] = r;
-    d.enter_stamp[r.gl] = t;
-    atomicAdd(&d.entries[r.edge], 1);
 }
 
+
+// Outcome of the end-of-edge requests of edge e: arrivals, admitted
+// transfers (entry records for the next layout) and held losers; the
+// travel times of the vehicles leaving e are added in ascending id.
+__device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, int par, CounterAcc& acc,
+                                   int& nex, unsigned& exmask) {
+    const int base = d.lane_base[e];
+    uint32_t ex_vid[8];
+    float ex_phi[8];
+    nex = 0;
+    exmask = 0;
+    for (int l = 0; l < d.lanes[e]; ++l) {
+        const Outbox ob = d.outbox[base + l];
+        if (ob.stamp != t) continue;
+        const uint32_t m = S.meta[ob.slot];
+        if (ob.target < 0) {                       // arrival at the route end
+            d.status[ob.vid] = kArrived;
+            d.fin_x[ob.vid] = S.x[ob.slot];
+            d.fin_v[ob.vid] = S.v[ob.slot];
+            d.fin_meta[ob.vid] = m;
+            d.exit_stamp[base + l] = t;
+            exmask |= 1u << l;
+            ex_vid[nex] = ob.vid;
+            ex_phi[nex] = ob.phi;
+            nex++;
+            acc.c[cArrived]++;
+            continue;
+        }
+        const bool won = transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
+        if (won) {
+            const int f = S.nxt[ob.slot];
+            const int k = d.cursor[ob.vid] + 1;
+            d.cursor[ob.vid] = k;
+            const int64_t pos = d.roff[ob.vid] + k + 1;
+            const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
+            if (!lane_allowed(m, f, l)) acc.c[cWaivedExits]++;
+            EntryRec r;
+            r.x = ob.xp;
+            r.v = S.v[ob.slot];
+            r.vid = ob.vid;
+            r.edge = f;
+            r.gl = ob.target;
+            r.meta = m_make(ob.target - d.lane_base[f], false, false, 0, m_cls(m), conn_mask_of(d, f, nn));
+            r.nxt = nn;
+            r.pad = 0;
+            d.held_since[ob.vid] = -1;
+            append_entry(d, par, r);
+            d.exit_stamp[base + l] = t;
+            exmask |= 1u << l;
+            ex_vid[nex] = ob.vid;
+            ex_phi[nex] = ob.phi;
+            nex++;
+            acc.c[cTransfers]++;
+        } else {                                   // held at the stop line
+            S.x[ob.slot] = d.L[e];
+            S.v[ob.slot] = 0.0f;
+            S.meta[ob.slot] = m | (1u << 5);
+            if (d.held_since[ob.vid] < 0) d.held_since[ob.vid] = t;
+            acc.c[cHolds]++;
+        }
+    }
+    for (int a = 1; a < nex; ++a) {                // insertion sort by vehicle id
+        const uint32_t kv = ex_vid[a];
+        const float kp = ex_phi[a];
+        int b2 = a - 1;
+        while (b2 >= 0 && ex_vid[b2] > kv) {
+            ex_vid[b2 + 1] = ex_vid[b2];
+            ex_phi[b2 + 1] = ex_phi[b2];
+            --b2;
+        }
+        ex_vid[b2 + 1] = kv;
+        ex_phi[b2 + 1] = kp;
+    }
+    double sum = d.tt_sum[e];
+    for (int a = 0; a < nex; ++a) {
+        const uint32_t vid = ex_vid[a];
+        const double tau = ((double)t + (double)ex_phi[a]) * (double)d.dt;
+        sum += tau - d.tau_in[vid];
+        if (d.status[vid] == kArrived) d.t_arr[vid] = tau;
+        else d.tau_in[vid] = tau;
+    }
+    d.tt_sum[e] = sum;
+    d.tt_cnt[e] += (unsigned long long)nex;
+}
+
+// Workgroups [0, n_blk): 1,024 edges each -- commit, new per-edge and
+// per-lane counts, in-block offsets; the last of them to finish scans the
+// block sums.  Workgroups [n_blk, grid): departures that asked for a lane.
 __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
-    __shared__ int wsh[kWaves];
-    const int t = d.ctl->t, par = t & 1;
-    int nreq, npend, due_lo, ndue;
-    item_ranges(d, t, par, nreq, npend, due_lo, ndue);
-    const int total = nreq + npend + ndue;
+    __shared__ unsigned shc[cNumCounters];
+    __shared__ Scan4 wsh4[kWaves];
+    __shared__ int last;
+    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = d.ctl->t_b, par = t & 1;
     const Slots S = d.s[par];
     CounterAcc acc;
     acc.zero();
-    const int stride = gridDim.x * kNT;
-    const int ibeg = blockIdx.x * kNT + threadIdx.x;
-    const int iend = ((total + stride - 1) / stride) * stride;
-    for (int i = ibeg; i < iend; i += stride) {
-        if (i >= total) continue;
-        if (i < nreq) {
-            const int e = d.req_edges[par][i];
-            const int base = d.lane_base[e];
-            // exits of this edge this step, to be summed in ascending vehicle id
-            uint32_t ex_vid[8];
-            float ex_phi[8];
+    if ((int)blockIdx.x < d.n_blk) {
+        constexpr int kPer = kEdgeBlock / kNT;
+        const int e_lo = blockIdx.x * kEdgeBlock + threadIdx.x * kPer;
+        int newc[kPer];
+        int tot = 0;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = e_lo + q;
+            newc[q] = 0;
+            if (e >= d.n_edges) continue;
             int nex = 0;
-            for (int l = 0; l < d.lanes[e]; ++l) {
-                const Outbox ob = d.outbox[base + l];
-                if (ob.stamp != t) continue;
-                const uint32_t m = S.meta[ob.slot];
-                if (ob.target < 0) {                       // arrival at the route end
-                    d.status[ob.vid] = kArrived;
-                    d.fin_x[ob.vid] = S.x[ob.slot];
-                    d.fin_v[ob.vid] = S.v[ob.slot];
-                    d.fin_meta[ob.vid] = m;
-                    d.exit_stamp[base + l] = t;
-                    ex_vid[nex] = ob.vid;
-                    ex_phi[nex] = ob.phi;
-                    nex++;
-                    acc.c[cArrived]++;
-                    continue;
-                }
-                const bool won = transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
-                if (won) {
-                    d.win[ob.target] = ~0ull;              // reset for the next step
-                    const int f = S.nxt[ob.slot];
-                    const int k = d.cursor[ob.vid] + 1;
-                    d.cursor[ob.vid] = k;
-                    const int64_t pos = d.roff[ob.vid] + k + 1;
-                    const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
-                    if (!lane_allowed(m, S.nxt[ob.slot], l)) acc.c[cWaivedExits]++;
-                    EntryRec r;
-                    r.x = ob.xp;
-                    r.v = S.v[ob.slot];
-                    r.vid = ob.vid;
-                    r.edge = f;
-                    r.gl = ob.target;
-                    r.meta = m_make(ob.target - d.lane_base[f], false, false, 0, m_cls(m), conn_mask_of(d, f, nn));
-                    r.nxt = nn;
-                    d.held_since[ob.vid] = -1;
-                    append_entry(d, par, r, t);
-                    d.exit_stamp[base + l] = t;
-                    ex_vid[nex] = ob.vid;
-                    ex_phi[nex] = ob.phi;
-                    nex++;
-                    acc.c[cTransfers]++;
-                } else {                                   // held at the stop line
-                    S.x[ob.slot] = d.L[e];
-                    S.v[ob.slot] = 0.0f;
-                    S.meta[ob.slot] = m | (1u << 5);
-                    if (d.held_since[ob.vid] < 0) d.held_since[ob.vid] = t;
-                    acc.c[cHolds]++;
+            unsigned exmask = 0;
+            if (d.req_stamp[e] == t) commit_edge(d, S, e, t, par, acc, nex, exmask);
+            const int c = d.cnt[e] - nex + d.entries[e];
+            d.cnt[e] = c;
+            d.entries[e] = 0;
+            newc[q] = c;
+            tot += c;
+            if (c > 0) {
+                int o = 0;
+                const int base = d.lane_base[e];
+                for (int l = 0; l < d.lanes[e]; ++l) {
+                    const int gl = base + l;
+                    const LanePost p = d.post[gl];
+                    int nc = (p.stamp == t) ? p.cnt : 0;
+                    if ((exmask >> l) & 1u) nc -= 1;
+                    if (d.enter_stamp[gl] == t) nc += 1;
+                    d.lane_rel[gl] = o;
+                    d.lane_newcnt[gl] = nc;
+                    o += nc;
                 }
             }
-            // insertion sort by vehicle id, then accumulate in that order
-            for (int a = 1; a < nex; ++a) {
-                const uint32_t kv = ex_vid[a];
-                const float kp = ex_phi[a];
-                int b2 = a - 1;
-                while (b2 >= 0 && ex_vid[b2] > kv) {
-                    ex_vid[b2 + 1] = ex_vid[b2];
-                    ex_phi[b2 + 1] = ex_phi[b2];
-                    --b2;
-                }
-                ex_vid[b2 + 1] = kv;
-                ex_phi[b2 + 1] = kp;
+        }
+        Scan4 run = wg_exclusive_scan4(Scan4{tot, -1, -1, -1}, wsh4);
+        int off = run.s;
+#pragma unroll
+        for (int q = 0; q < kPer; ++q) {
+            const int e = e_lo + q;
+            if (e < d.n_edges) d.edge_rel[e] = off;
+            off += newc[q];
+        }
+        if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = off;
+        __syncthreads();
+        if (threadIdx.x == kNT - 1) {
+            __threadfence();
+            last = (atomicAdd(&d.ctl->done2, 1u) == (unsigned)d.n_blk - 1u);
+        }
+        __syncthreads();
+        if (last) {   // every block sum is written: scan them (one workgroup)
+            __threadfence();
+            const int nb = d.n_blk;
+            const int chunk = (nb + kNT - 1) / kNT;
+            const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
+            int loc = 0;
+            for (int i = lo; i < hi; ++i) loc += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            Scan4 r2 = wg_exclusive_scan4(Scan4{loc, -1, -1, -1}, wsh4);
+            int o2 = r2.s;
+            for (int i = lo; i < hi; ++i) {
+                d.blk_off[i] = o2;
+                o2 += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            double sum = d.tt_sum[e];
-            for (int a = 0; a < nex; ++a) {
-                const uint32_t vid = ex_vid[a];
-                const double tau = ((double)t + (double)ex_phi[a]) * (double)d.dt;
-                sum += tau - d.tau_in[vid];
-                if (d.status[vid] == kArrived) d.t_arr[vid] = tau;
-                else d.tau_in[vid] = tau;
+            if (threadIdx.x == kNT - 1) {
+                d.ctl->n_act[par ^ 1] = o2;
+                d.ctl->done2 = 0;
+                d.ctl->t_a = t + 1;   // k_tile_step and k_admit of this step are done
             }
-            d.tt_sum[e] = sum;
-            d.tt_cnt[e] += (unsigned long long)nex;
-            d.exits[e] = nex;
-        } else {
-            const int vid = i < nreq + npend ? d.pend[par][i - nreq] : d.wait_order[due_lo + (i - nreq - npend)];
+        }
+    } else {
+        int nreq, npend, due_lo, ndue;
+        item_ranges(d, t, par, nreq, npend, due_lo, ndue);
+        const int total = npend + ndue;
+        const int stride = (gridDim.x - d.n_blk) * kNT;
+        for (int i = (blockIdx.x - d.n_blk) * kNT + threadIdx.x; i < total; i += stride) {
+            const int vid = i < npend ? d.pend[par][i] : d.wait_order[due_lo + (i - npend)];
             const int g = d.ins_gl[vid];
             const unsigned long long key = insert_key(d, vid);
             if (insert_eligible(d, vid, t) && d.win[g] == key) {
-                d.win[g] = ~0ull;
                 const int64_t r0 = d.roff[vid];
                 const int e0 = d.redges[r0];
                 const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
@@ -866,11 +1035,12 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
                 r.gl = g;
                 r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], conn_mask_of(d, e0, nn));
                 r.nxt = nn;
+                r.pad = 0;
                 d.status[vid] = kActive;
                 d.cursor[vid] = 0;
                 d.held_since[vid] = -1;
                 d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
-                append_entry(d, par, r, t);
+                append_entry(d, par, r);
                 acc.c[cDeparted]++;
             } else {
                 const int k = atomicAdd(&d.ctl->n_pend[par ^ 1], 1);
@@ -879,80 +1049,14 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
             }
         }
     }
-    flush_counters(d, acc, wsh);
+    flush_counters_lds(d, acc, shc);
 }
 
 // ---- next layout -----------------------------------------------------------
-__global__ void __launch_bounds__(kNT) k_edge_count(Dev d) {
-    __shared__ int wsh[kWaves];
-    const int t = d.ctl->t, par = t & 1;
-    const int e0 = blockIdx.x * kEdgeBlock;
-    int loc = 0;
-    for (int e = e0 + threadIdx.x; e < min(d.n_edges, e0 + kEdgeBlock); e += kNT) {
-        const int c = d.cnt[e] - d.exits[e] + d.entries[e];
-        d.cnt[e] = c;
-        d.exits[e] = 0;
-        d.entries[e] = 0;
-        loc += c;
-    }
-    const int s = wg_sum(loc, wsh);
-    if (threadIdx.x == 0) d.blk_sum[blockIdx.x] = s;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-        d.ctl->n_req[par ^ 1] = 0;
-        d.ctl->n_ent[par ^ 1] = 0;
-    }
-}
-
-__global__ void __launch_bounds__(kNT) k_block_scan(Dev d) {
-    __shared__ Scan4 wsh4[kWaves];
-    const int t = d.ctl->t, par = t & 1;
-    const int nb = d.n_blk;
-    const int chunk = (nb + kNT - 1) / kNT;
-    const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
-    Scan4 loc{0, -1, -1, -1};
-    for (int i = lo; i < hi; ++i) loc.s += d.blk_sum[i];
-    Scan4 run = wg_exclusive_scan4(loc, wsh4);
-    for (int i = lo; i < hi; ++i) {
-        d.blk_off[i] = run.s;
-        run.s += d.blk_sum[i];
-    }
-    if (threadIdx.x == kNT - 1) d.ctl->n_act[par ^ 1] = run.s;
-}
-
-__global__ void __launch_bounds__(kNT) k_edge_offset(Dev d) {
-    __shared__ Scan4 wsh4[kWaves];
-    const int t = d.ctl->t;
-    const int e0 = blockIdx.x * kEdgeBlock;
-    constexpr int kPer = kEdgeBlock / kNT;
-    const int lo = e0 + threadIdx.x * kPer;
-    Scan4 loc{0, -1, -1, -1};
-    for (int e = lo; e < min(d.n_edges, lo + kPer); ++e) loc.s += d.cnt[e];
-    Scan4 run = wg_exclusive_scan4(loc, wsh4);
-    int off = d.blk_off[blockIdx.x] + run.s;
-    for (int e = lo; e < min(d.n_edges, lo + kPer); ++e) {
-        const int c = d.cnt[e];
-        d.edge_off[e] = off;
-        if (c > 0) {
-            int o = off;
-            const int base = d.lane_base[e];
-            for (int l = 0; l < d.lanes[e]; ++l) {
-                const int gl = base + l;
-                const LanePost p = d.post[gl];
-                int nc = (p.stamp == t) ? p.cnt : 0;
-                if (d.exit_stamp[gl] == t) nc -= 1;
-                if (d.enter_stamp[gl] == t) nc += 1;
-                d.lane_newstart[gl] = o;
-                d.lane_newcnt[gl] = nc;
-                o += nc;
-            }
-        }
-        off += c;
-    }
-}
-
+// slot of a vehicle in the next layout:
+//   block offset + edge offset in block + lane offset in edge + rank in lane
 __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
-    __shared__ bool last;
-    const int t = d.ctl->t, par = t & 1;
+    const int t = d.ctl->t_b, par = t & 1;
     const int nold = d.ctl->n_act[par];
     const int nent = d.ctl->n_ent[par];
     const int nnew = d.ctl->n_act[par ^ 1];
@@ -960,7 +1064,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nent; i += gridDim.x * kNT) {
         float x, v;
         uint32_t vid, meta;
-        int edge, nxt, gl, dst;
+        int edge, nxt, gl, nr;
         bool is_rear;
         if (i < nold) {
             meta = A.meta[i];
@@ -974,8 +1078,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             const int r = i - lp.start;
             const int ex = d.exit_stamp[gl] == t ? 1 : 0;
             if (ex && r == 0) continue;           // the lane's front left the edge
-            const int nr = r - ex;
-            dst = d.lane_newstart[gl] + nr;
+            nr = r - ex;
             is_rear = (nr == d.lane_newcnt[gl] - 1) && (d.enter_stamp[gl] != t);
             x = A.x[i];
             v = A.v[i];
@@ -984,7 +1087,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         } else {
             const EntryRec r = d.ent[i - nold];
             gl = r.gl;
-            dst = d.lane_newstart[gl] + d.lane_newcnt[gl] - 1;
+            nr = d.lane_newcnt[gl] - 1;           // the entry is the new rear
             is_rear = true;
             x = r.x;
             v = r.v;
@@ -992,7 +1095,9 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             meta = r.meta;
             edge = r.edge;
             nxt = r.nxt;
+            d.win[gl] = ~0ull;                    // lane free for the next step's claims
         }
+        const int dst = d.blk_off[edge / kEdgeBlock] + d.edge_rel[edge] + d.lane_rel[gl] + nr;
         if (dst < 0 || dst >= nnew) {
             atomicOr(&d.ctl->err, kErrScatter);
             continue;
@@ -1011,19 +1116,6 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             lr.pad = 0;
             d.rear[gl] = lr;
         }
-    }
-    // the last workgroup to finish advances the step counter
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        __threadfence();
-        const unsigned prev = atomicAdd(&d.ctl->done, 1u);
-        last = (prev == gridDim.x - 1);
-    }
-    __syncthreads();
-    if (last && threadIdx.x == 0) {
-        d.ctl->done = 0;
-        __threadfence();
-        d.ctl->t = t + 1;
     }
 }
 
