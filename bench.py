@@ -57,6 +57,9 @@ def main():
     ap.add_argument("--workload", default="perturbed_grid_ring", choices=["perturbed_grid_ring", "grid10x10"])
     ap.add_argument("--cpu-steps", type=int, default=3600, help="oracle sample length (0: skip)")
     ap.add_argument("--graph", action="store_true", help="also time the captured-graph path")
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="run one plain device copy of this many MiB before the timed region "
+                         "(a known-size reference for hardware byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation is "
@@ -69,6 +72,13 @@ def main():
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
     w = make_workload(args.workload)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     # warm-up on its own handle (kernels, graph, caches), then a fresh handle
     warm = M.Sim(w, stream=stream)

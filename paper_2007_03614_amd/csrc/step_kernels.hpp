@@ -321,6 +321,37 @@ struct CounterAcc {
     }
 };
 
+// Append to a device list with one atomic per wavefront: the active lanes
+// that pass `flag` get consecutive indices.  Every lane active at the call
+// must make it (the ballot covers exactly them).
+__device__ inline int wave_append(int* counter, bool flag) {
+    const unsigned long long mask = __ballot(flag);
+    if (!flag) return -1;
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
+    base = __shfl(base, leader, 64);
+    return base + __popcll(mask & ((1ull << lane) - 1ull));
+}
+
+// Reserve `cnt` consecutive slots per lane, one atomic per wavefront (all
+// 64 lanes of the wave must make the call).
+__device__ inline int wave_reserve(int* counter, int cnt) {
+    const int lane = threadIdx.x & 63;
+    int inc = cnt;
+#pragma unroll
+    for (int dd = 1; dd < 64; dd <<= 1) {
+        const int o = __shfl_up(inc, dd, 64);
+        if (lane >= dd) inc += o;
+    }
+    const int total = __shfl(inc, 63, 64);
+    int base = 0;
+    if (lane == 63 && total > 0) base = atomicAdd(counter, total);
+    base = __shfl(base, 63, 64);
+    return base + inc - cnt;
+}
+
 // counters: per-thread registers -> LDS atomics -> one global atomic each
 __device__ inline void flush_counters_lds(const Dev& d, const CounterAcc& acc, unsigned* shc) {
     for (int k = 0; k < cNumCounters; ++k)
@@ -637,48 +668,50 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const uint32_t el = b.pel[r];
         const bool front = (r == 0) || (b.pel[r - 1] != el);
         const bool rear = (r == n - 1) || (b.pel[r + 1] != el);
-        if (!front && !rear) continue;
-        const int q = b.inv[r];
-        if (q < 0 || q >= n) {
-            atomicOr(&d.ctl->err, kErrPermutation);
-            continue;
-        }
-        const int e = (int)(el >> 4), lam = (int)(el & 15u);
-        const int gl = d.lane_base[e] + lam;
-        const float xnew = b.xn[q];
-        if (rear) {
-            const int fr = el_lower_bound(b.pel, n, el);
-            LanePost lp;
-            lp.stamp = t;
-            lp.start = a0 + fr;
-            lp.cnt = r - fr + 1;
-            lp.rear_xm = xnew - d.cp[m_cls(b.meta[q])].len;
-            d.post[gl] = lp;
-        }
-        if (front && xnew >= d.L[e] && !(b.fl[q] & F_WHOLD)) {
-            const int f = b.nxt[q];
-            const float xo = b.x[q];
-            Outbox ob;
-            ob.stamp = t;
-            ob.slot = a0 + r;
-            ob.vid = b.vid[q];
-            ob.phi = (xnew == xo) ? 0.0f : (d.L[e] - xo) / (xnew - xo);
-            if (f < 0) {
-                ob.target = -1;
-                ob.xp = 0.0f;
-                ob.key = 0;
+        bool append = false;
+        int e = (int)(el >> 4);
+        if (front || rear) {
+            const int q = b.inv[r];
+            if (q < 0 || q >= n) {
+                atomicOr(&d.ctl->err, kErrPermutation);
             } else {
-                ob.target = d.lane_base[f] + min(lam, d.lanes[f] - 1);
-                ob.xp = xnew - d.L[e];
-                const int hs = m_held(b.meta[q]) ? d.held_since[ob.vid] : t;
-                ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
-            }
-            d.outbox[gl] = ob;
-            if (atomicMax(&d.req_stamp[e], t) < t) {
-                const int k = atomicAdd(&d.ctl->n_req[par], 1);
-                d.req_edges[par][k] = e;
+                const int lam = (int)(el & 15u);
+                const int gl = d.lane_base[e] + lam;
+                const float xnew = b.xn[q];
+                if (rear) {
+                    const int fr = el_lower_bound(b.pel, n, el);
+                    LanePost lp;
+                    lp.stamp = t;
+                    lp.start = a0 + fr;
+                    lp.cnt = r - fr + 1;
+                    lp.rear_xm = xnew - d.cp[m_cls(b.meta[q])].len;
+                    d.post[gl] = lp;
+                }
+                if (front && xnew >= d.L[e] && !(b.fl[q] & F_WHOLD)) {
+                    const int f = b.nxt[q];
+                    const float xo = b.x[q];
+                    Outbox ob;
+                    ob.stamp = t;
+                    ob.slot = a0 + r;
+                    ob.vid = b.vid[q];
+                    ob.phi = (xnew == xo) ? 0.0f : (d.L[e] - xo) / (xnew - xo);
+                    if (f < 0) {
+                        ob.target = -1;
+                        ob.xp = 0.0f;
+                        ob.key = 0;
+                    } else {
+                        ob.target = d.lane_base[f] + min(lam, d.lanes[f] - 1);
+                        ob.xp = xnew - d.L[e];
+                        const int hs = m_held(b.meta[q]) ? d.held_since[ob.vid] : t;
+                        ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
+                    }
+                    d.outbox[gl] = ob;
+                    append = atomicMax(&d.req_stamp[e], t) < t;   // first lane of the edge lists it
+                }
             }
         }
+        const int k = wave_append(&d.ctl->n_req[par], append);
+        if (append) d.req_edges[par][k] = e;
     }
     __syncthreads();
 }
@@ -844,22 +877,21 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
     }
 }
 
-__device__ inline void append_entry(const Dev& d, int par, const EntryRec& r) {
-    const int k = atomicAdd(&d.ctl->n_ent[par], 1);
-    d.ent[k] = r;
-}
 
 
 // Outcome of the end-of-edge requests of edge e: arrivals, admitted
-// transfers (entry records for the next layout) and held losers; the
-// travel times of the vehicles leaving e are added in ascending id.
-__device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, int par, CounterAcc& acc,
-                                   int& nex, unsigned& exmask) {
+// transfers and held losers; the travel times of the vehicles leaving e are
+// added in ascending id.  Returns the number of exits and, in winmask, the
+// lanes whose front won a transfer (their entry records are written by
+// write_entries once the wavefront has reserved the slots).
+__device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, CounterAcc& acc, int& nex,
+                                   unsigned& exmask, unsigned& winmask) {
     const int base = d.lane_base[e];
     uint32_t ex_vid[8];
     float ex_phi[8];
     nex = 0;
     exmask = 0;
+    winmask = 0;
     for (int l = 0; l < d.lanes[e]; ++l) {
         const Outbox ob = d.outbox[base + l];
         if (ob.stamp != t) continue;
@@ -879,25 +911,10 @@ __device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, i
         }
         const bool won = transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
         if (won) {
-            const int f = S.nxt[ob.slot];
-            const int k = d.cursor[ob.vid] + 1;
-            d.cursor[ob.vid] = k;
-            const int64_t pos = d.roff[ob.vid] + k + 1;
-            const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
-            if (!lane_allowed(m, f, l)) acc.c[cWaivedExits]++;
-            EntryRec r;
-            r.x = ob.xp;
-            r.v = S.v[ob.slot];
-            r.vid = ob.vid;
-            r.edge = f;
-            r.gl = ob.target;
-            r.meta = m_make(ob.target - d.lane_base[f], false, false, 0, m_cls(m), conn_mask_of(d, f, nn));
-            r.nxt = nn;
-            r.pad = 0;
-            d.held_since[ob.vid] = -1;
-            append_entry(d, par, r);
+            if (!lane_allowed(m, S.nxt[ob.slot], l)) acc.c[cWaivedExits]++;
             d.exit_stamp[base + l] = t;
             exmask |= 1u << l;
+            winmask |= 1u << l;
             ex_vid[nex] = ob.vid;
             ex_phi[nex] = ob.phi;
             nex++;
@@ -934,6 +951,33 @@ __device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, i
     d.tt_cnt[e] += (unsigned long long)nex;
 }
 
+// entry records of the transfers that won, at slots k0, k0 + 1, ...
+__device__ inline void write_entries(const Dev& d, const Slots& S, int e, unsigned winmask, int k0) {
+    const int base = d.lane_base[e];
+    int k = k0;
+    for (int l = 0; l < 8; ++l) {
+        if (!((winmask >> l) & 1u)) continue;
+        const Outbox ob = d.outbox[base + l];
+        const uint32_t m = S.meta[ob.slot];
+        const int f = S.nxt[ob.slot];
+        const int kk = d.cursor[ob.vid] + 1;
+        d.cursor[ob.vid] = kk;
+        const int64_t pos = d.roff[ob.vid] + kk + 1;
+        const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
+        EntryRec r;
+        r.x = ob.xp;
+        r.v = S.v[ob.slot];
+        r.vid = ob.vid;
+        r.edge = f;
+        r.gl = ob.target;
+        r.meta = m_make(ob.target - d.lane_base[f], false, false, 0, m_cls(m), conn_mask_of(d, f, nn));
+        r.nxt = nn;
+        r.pad = 0;
+        d.held_since[ob.vid] = -1;
+        d.ent[k++] = r;
+    }
+}
+
 // Workgroups [0, n_blk): 1,024 edges each -- commit, new per-edge and
 // per-lane counts, in-block offsets; the last of them to finish scans the
 // block sums.  Workgroups [n_blk, grid): departures that asked for a lane.
@@ -949,22 +993,21 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     acc.zero();
     if ((int)blockIdx.x < d.n_blk) {
         constexpr int kPer = kEdgeBlock / kNT;
-        const int e_lo = blockIdx.x * kEdgeBlock + threadIdx.x * kPer;
-        int newc[kPer];
+        static_assert(kPer == 1, "one edge per thread");
+        const int e = blockIdx.x * kEdgeBlock + threadIdx.x;
+        int newc[1] = {0};
         int tot = 0;
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int e = e_lo + q;
-            newc[q] = 0;
-            if (e >= d.n_edges) continue;
+        const int e_lo = e;
+        unsigned winmask = 0;
+        if (e < d.n_edges) {
             int nex = 0;
             unsigned exmask = 0;
-            if (d.req_stamp[e] == t) commit_edge(d, S, e, t, par, acc, nex, exmask);
+            if (d.req_stamp[e] == t) commit_edge(d, S, e, t, acc, nex, exmask, winmask);
             const int c = d.cnt[e] - nex + d.entries[e];
             d.cnt[e] = c;
             d.entries[e] = 0;
-            newc[q] = c;
-            tot += c;
+            newc[0] = c;
+            tot = c;
             if (c > 0) {
                 int o = 0;
                 const int base = d.lane_base[e];
@@ -980,6 +1023,8 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
                 }
             }
         }
+        const int k0 = wave_reserve(&d.ctl->n_ent[par], __popc(winmask));
+        if (winmask) write_entries(d, S, e, winmask, k0);
         Scan4 run = wg_exclusive_scan4(Scan4{tot, -1, -1, -1}, wsh4);
         int off = run.s;
 #pragma unroll
@@ -1022,8 +1067,10 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         for (int i = (blockIdx.x - d.n_blk) * kNT + threadIdx.x; i < total; i += stride) {
             const int vid = i < npend ? d.pend[par][i] : d.wait_order[due_lo + (i - npend)];
             const int g = d.ins_gl[vid];
-            const unsigned long long key = insert_key(d, vid);
-            if (insert_eligible(d, vid, t) && d.win[g] == key) {
+            const bool won = insert_eligible(d, vid, t) && d.win[g] == insert_key(d, vid);
+            const int ke = wave_append(&d.ctl->n_ent[par], won);
+            const int kp = wave_append(&d.ctl->n_pend[par ^ 1], !won);
+            if (won) {
                 const int64_t r0 = d.roff[vid];
                 const int e0 = d.redges[r0];
                 const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
@@ -1040,11 +1087,10 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
                 d.cursor[vid] = 0;
                 d.held_since[vid] = -1;
                 d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
-                append_entry(d, par, r);
+                d.ent[ke] = r;
                 acc.c[cDeparted]++;
             } else {
-                const int k = atomicAdd(&d.ctl->n_pend[par ^ 1], 1);
-                d.pend[par ^ 1][k] = vid;
+                d.pend[par ^ 1][kp] = vid;
                 acc.c[cInsertDenied]++;
             }
         }
