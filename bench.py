@@ -49,6 +49,33 @@ def cpu_baseline(w, steps: int):
             "sample": f"steps 0-{steps} of the same workload ({upd} vehicle-updates, {dt:.1f} s)"}
 
 
+def summarize_pmc(directory: str) -> dict:
+    """Per-kernel means of the counters in a `rocprofv3 --pmc --output-format
+    csv` directory: {kernel: {"dispatches": n, counter: mean per dispatch}}.
+    Device copies (`__amd_rocclr_copyBuffer`) are kept per grid size, so a
+    copy of known size can calibrate byte counters."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
+    acc = {}
+    for fn in files:
+        with open(fn, newline="") as f:
+            for row in csv.DictReader(f):
+                name = row.get("Kernel_Name", "?")
+                if "copyBuffer" in name:
+                    name = f"{name} grid={row.get('Grid_Size', '?')}"
+                key = (name, row.get("Counter_Name", "?"))
+                a = acc.setdefault(key, [0.0, 0, set()])
+                a[0] += float(row.get("Counter_Value", 0.0))
+                a[1] += 1
+    out = {}
+    for (name, ctr), (tot, n, _) in acc.items():
+        k = out.setdefault(name, {})
+        k["dispatches"] = max(k.get("dispatches", 0), n)
+        k[ctr] = tot / n
+    return {"files": len(files), "kernels": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,7 +87,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB before the timed region "
                          "(a known-size reference for hardware byte counters)")
+    ap.add_argument("--summarize-pmc", metavar="DIR", help="summarize a rocprofv3 --pmc csv directory and exit")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation is "
               "single-device and its multi-GPU sharding is not part of this build.", file=sys.stderr)
