@@ -76,12 +76,64 @@ def summarize_pmc(directory: str) -> dict:
     return {"files": len(files), "kernels": out}
 
 
+def bench_ensemble(args, M, torch, stream):
+    """64 what-if scenarios on the 10x10 grid (demand U[0.8, 1.2] x 200,000 of
+    a 240,000 master list, 1 % of edges cut to one lane each), 2 h: one
+    ensemble handle (autotuned schedule, captured graph) against the 64
+    scenarios run one after another, each on its own graph-captured handle."""
+    import workloads as W
+    master, scen = W.config4(n_scen=args.scenarios)
+    steps = args.steps if args.steps_given else master.n_steps
+    cache = os.path.join("/tmp", "manta_schedule_cache.txt")
+    tune = M.Sim(master, scenarios=scen, stream=stream)
+    tune.step(args.tune_at)
+    sched = tune.autotune(cache, steps_per_trial=10)
+    tune.close()
+    ens = M.Sim(master, scenarios=scen, stream=stream)
+    ens.autotune(cache)   # read back from the cache
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    ens.step(steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    c = ens.counters()
+    upd = c["active_sum"]
+    ens.close()
+    seq_ms, seq_upd = 0.0, 0
+    for n, red in scen:
+        solo = M.Sim(W.scenario_workload(master, n, red), stream=stream)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        solo.step(steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        seq_ms += e0.elapsed_time(e1)
+        seq_upd += solo.counters()["active_sum"]
+        solo.close()
+    assert seq_upd == upd, (seq_upd, upd)
+    return {
+        "metric": "vehicle-updates/sec (1 GPU)", "value": upd / (ms / 1e3), "unit": "vehicle-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.tune_at, "ms_per_step": ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"ensemble{args.scenarios}_grid10x10", "scenarios": args.scenarios,
+                   "vehicles": int(sum(n for n, _ in scen)), "steps": steps, "vehicle_updates": int(upd),
+                   "arrived": int(c["arrived"]), "schedule": sched},
+        "sequential": {"value": seq_upd / (seq_ms / 1e3), "ms": seq_ms, "handles": args.scenarios},
+        "ensemble_speedup": (upd / ms) / (seq_upd / seq_ms),
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=21600)
     ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="perturbed_grid_ring", choices=["perturbed_grid_ring", "grid10x10"])
+    ap.add_argument("--workload", default="perturbed_grid_ring",
+                    choices=["perturbed_grid_ring", "grid10x10", "ensemble"])
+    ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
+    ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
     ap.add_argument("--cpu-steps", type=int, default=3600, help="oracle sample length (0: skip)")
     ap.add_argument("--graph", action="store_true", help="also time the captured-graph path")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -89,6 +141,7 @@ def main():
                          "(a known-size reference for hardware byte counters)")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="summarize a rocprofv3 --pmc csv directory and exit")
     args = ap.parse_args()
+    args.steps_given = "--steps" in sys.argv
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
         return
@@ -102,6 +155,9 @@ def main():
 
     torch.cuda.set_device(0)
     stream = torch.cuda.current_stream()
+    if args.workload == "ensemble":
+        print(json.dumps(bench_ensemble(args, M, torch, stream)), flush=True)
+        return
     w = make_workload(args.workload)
     if args.copy_probe > 0:
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")

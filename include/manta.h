@@ -131,6 +131,42 @@ sim_status sim_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
 sim_status sim_create(const sim_network *net, const sim_routes *routes, const sim_idm_params *params,
                       sim_handle **out);
 
+/* What-if scenario of an ensemble: a demand subset and capacity cuts on the
+ * shared network (the paper's use case of quickly comparing scenarios,
+ * Sec. I; calibration runs several parameter sets per iteration, Sec. IV-A). */
+typedef struct {
+    int32_t n_vehicles;                   /* the first n_vehicles of the master demand, 0..master */
+    int32_t n_reduced;                    /* >= 0 */
+    const int32_t *reduced_edges;         /* [n_reduced] edge ids forced to 1 lane (all moves from lane 0) */
+} sim_scenario;
+
+/* One handle running n_scen >= 1 scenarios in the same kernels: the device
+ * network is the disjoint union of the scenario copies (edge k*n_edges + e,
+ * node k*n_nodes + v, vehicle ids scenario after scenario), so every launch of
+ * a step covers all scenarios.  The lane-change draws use each vehicle's id
+ * within its scenario, so member k evolves exactly like sim_create on its own
+ * network and demand.  State and edge statistics are read in the union
+ * numbering (sim_ensemble_offsets gives the vehicle ranges).  Errors as
+ * sim_create, plus SIM_EINVAL for an empty scenario list, n_vehicles outside
+ * [0, master], or a reduced edge out of range. */
+sim_status sim_create_ensemble(const sim_network *net, const sim_routes *master, const sim_scenario *scen,
+                               int32_t n_scen, const sim_idm_params *params, sim_handle **out);
+
+/* veh_off[n_scen + 1]: vehicles of scenario k are [veh_off[k], veh_off[k+1]). */
+sim_status sim_ensemble_offsets(const sim_handle *h, int32_t *n_scen, int32_t *veh_off);
+
+/* Pick the launch schedule (tile window, workgroups per kernel) by timing a
+ * few steps of each candidate from the current state, which is restored
+ * afterwards.  steps_per_trial >= 1.  The choice is appended to cache_path
+ * (text, one line per network/demand size) and reused from there when the
+ * same sizes come back; cache_path may be NULL.  Results of the simulation
+ * never depend on the schedule. */
+sim_status sim_autotune(sim_handle *h, const char *cache_path, int32_t steps_per_trial);
+
+/* Current schedule: [tile_window, tile_workgroups, big_tile_workgroups,
+ * admit_workgroups, scatter_workgroups]. */
+sim_status sim_get_schedule(const sim_handle *h, int32_t *sched);
+
 /* Stream for all later device work of h (a hipStream_t; NULL = null stream).
  * The captured step graph is launched on this stream. */
 sim_status sim_set_stream(sim_handle *h, void *hip_stream);

@@ -51,6 +51,10 @@ class SimIdmParams(ctypes.Structure):
                 ("record_every", I32)]
 
 
+class SimScenario(ctypes.Structure):
+    _fields_ = [("n_vehicles", I32), ("n_reduced", I32), ("reduced_edges", P)]
+
+
 class SimState(ctypes.Structure):
     _fields_ = [("status", P), ("edge", P), ("lane", P), ("cursor", P), ("x", P), ("v", P),
                 ("held_since", P), ("mand", P), ("ww", P), ("tau_in", P), ("t_arr", P), ("counters", P),
@@ -83,6 +87,15 @@ _lib.sim_destroy.argtypes = [P]
 _lib.sim_destroy.restype = I32
 _lib.sim_last_error.argtypes = [P]
 _lib.sim_last_error.restype = ctypes.c_char_p
+_lib.sim_create_ensemble.argtypes = [ctypes.POINTER(SimNetwork), ctypes.POINTER(SimRoutes), P, I32,
+                                     ctypes.POINTER(SimIdmParams), ctypes.POINTER(P)]
+_lib.sim_create_ensemble.restype = I32
+_lib.sim_ensemble_offsets.argtypes = [P, P, P]
+_lib.sim_ensemble_offsets.restype = I32
+_lib.sim_autotune.argtypes = [P, ctypes.c_char_p, I32]
+_lib.sim_autotune.restype = I32
+_lib.sim_get_schedule.argtypes = [P, P]
+_lib.sim_get_schedule.restype = I32
 _lib.sim_probe_fp32.argtypes = [I32, P, P, P, I64]
 _lib.sim_probe_fp32.restype = I32
 _lib.sim_probe_philox.argtypes = [P, P, P, I64]
@@ -94,6 +107,7 @@ KERNELS = ["k_tile_step", "k_tile_big", "k_admit", "k_commit", "k_scatter"]
 
 EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
             "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",
+            "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_get_schedule",
             "sim_probe_fp32", "sim_probe_philox", "sim_probe_draws"]
 
 
@@ -175,10 +189,12 @@ class Sim:
     (``net``, ``route_off``, ``route_edges``, ``depart_step``, ``vclass``,
     ``alpha``, ``params``)."""
 
-    def __init__(self, w, stream=None, allocator: str = "torch"):
+    def __init__(self, w, stream=None, allocator: str = "torch", scenarios=None):
+        """scenarios: optional list of (n_vehicles, reduced_edges) — an
+        ensemble over the workload's network, with the workload's demand as
+        the master list (sim_create_ensemble)."""
         net, p = w.net, w.params
-        self.n = int(w.depart_step.shape[0])
-        self.n_edges = int(net.edge_from.shape[0])
+        self.n_edges_base = int(net.edge_from.shape[0])
         keep = dict(
             ef=_c(net.edge_from, np.int32), et=_c(net.edge_to, np.int32), ln=_c(net.length, np.float32),
             li=_c(net.limit, np.float32), la=_c(net.lanes, np.uint8), co=_c(net.conn_off, np.int32),
@@ -188,25 +204,58 @@ class Sim:
             a=_c(p.a, np.float32), b=_c(p.b, np.float32), s0=_c(p.s0, np.float32),
             vl=_c(p.veh_len, np.float32))
         k = keep
+        n_master = int(w.depart_step.shape[0])
         n_nodes = int(getattr(net, "n_nodes", int(max(k["ef"].max(), k["et"].max())) + 1))
-        self._net = SimNetwork(n_nodes, self.n_edges, _p(k["ef"]), _p(k["et"]), _p(k["ln"]), _p(k["li"]),
+        self._net = SimNetwork(n_nodes, self.n_edges_base, _p(k["ef"]), _p(k["et"]), _p(k["ln"]), _p(k["li"]),
                                _p(k["la"]), _p(k["co"]), _p(k["ct"]), _p(k["cm"]))
-        self._routes = SimRoutes(self.n, _p(k["ro"]), _p(k["re"]), _p(k["dp"]), _p(k["vc"]), _p(k["al"]))
+        self._routes = SimRoutes(n_master, _p(k["ro"]), _p(k["re"]), _p(k["dp"]), _p(k["vc"]), _p(k["al"]))
         self._params = SimIdmParams(int(p.T.shape[0]), _p(k["v0"]), _p(k["T"]), _p(k["a"]), _p(k["b"]),
                                     _p(k["s0"]), _p(k["vl"]), float(p.dt), int(p.seed),
                                     int(getattr(p, "intersection_mode", 0)), int(getattr(p, "record_every", 0)))
-        self._keep = keep
         if allocator == "torch":
             use_torch_allocator()
         elif allocator == "hip":
             use_hip_allocator()
         h = P()
-        _check(_lib.sim_create(ctypes.byref(self._net), ctypes.byref(self._routes), ctypes.byref(self._params),
-                               ctypes.byref(h)))
+        if scenarios is None:
+            self.n_scen = 1
+            self.n = n_master
+            self.n_edges = self.n_edges_base
+            _check(_lib.sim_create(ctypes.byref(self._net), ctypes.byref(self._routes),
+                                   ctypes.byref(self._params), ctypes.byref(h)))
+        else:
+            red = [_c(r, np.int32) for _, r in scenarios]
+            sc = (SimScenario * len(scenarios))(*[SimScenario(int(n), int(r.size), _p(r))
+                                                  for (n, _), r in zip(scenarios, red)])
+            keep["red"], keep["sc"] = red, sc
+            self.n_scen = len(scenarios)
+            self.n = int(sum(int(n) for n, _ in scenarios))
+            self.n_edges = self.n_edges_base * self.n_scen
+            _check(_lib.sim_create_ensemble(ctypes.byref(self._net), ctypes.byref(self._routes),
+                                            ctypes.cast(sc, P), self.n_scen, ctypes.byref(self._params),
+                                            ctypes.byref(h)))
+        self._keep = keep
         self._h = h
         _live.add(self)
         if stream is not None:
             self.set_stream(stream)
+
+    def offsets(self) -> np.ndarray:
+        """Vehicle-id range of every scenario: [n_scen + 1]."""
+        out = np.zeros(self.n_scen + 1, np.int32)
+        ns = I32()
+        _check(_lib.sim_ensemble_offsets(self._h, ctypes.byref(ns), _p(out)), self._h)
+        return out
+
+    def autotune(self, cache_path=None, steps_per_trial: int = 20) -> list:
+        cp = cache_path.encode() if cache_path else None
+        _check(_lib.sim_autotune(self._h, cp, int(steps_per_trial)), self._h)
+        return self.schedule()
+
+    def schedule(self) -> list:
+        out = np.zeros(5, np.int32)
+        _check(_lib.sim_get_schedule(self._h, _p(out)), self._h)
+        return out.tolist()
 
     def close(self):
         h = getattr(self, "_h", None)

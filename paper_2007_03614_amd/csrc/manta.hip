@@ -76,10 +76,14 @@ struct sim_handle {
     Dev d{};
     int t = 0;
     int n_veh = 0, n_edges = 0, n_lanes = 0, n_classes = 0;
-    int g_tile = 1, g_big = 1, g_items = 1, g_ins = 1, g_scatter = 1, n_blk = 1;
+    int g_tile = 1, g_big = 1, g_items = 1, g_scatter = 1, n_blk = 1;
+    int g_big_max = 1, g_scatter_max = 1;
+    int n_scen = 1;
+    std::vector<int32_t> veh_off;   // ensemble: vehicles of scenario k
     // host copies of the static inputs needed for state I/O
     std::vector<int64_t> roff;
     std::vector<int32_t> redges, dep, lanes, lane_base, conn_off, conn_to, ins_lane;
+    std::vector<int32_t> qveh, qoff;   // departure queues (host copy, for state writes)
     std::vector<uint8_t> conn_mask, cls;
     std::vector<float> L, len_c, s0_c;
 
@@ -208,14 +212,14 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
         hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
         hipLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, d);
         hipLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, d);
-        hipLaunchKernelGGL(k_commit, dim3(h->n_blk + h->g_ins), b, 0, s, d);
+        hipLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, d);
         hipLaunchKernelGGL(k_scatter, dim3(h->g_scatter), b, 0, s, d);
         return;
     }
     hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
     hipExtLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     hipExtLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, ev[4], ev[5], 0, d);
-    hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk + h->g_ins), b, 0, s, ev[6], ev[7], 0, d);
+    hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[6], ev[7], 0, d);
     hipExtLaunchKernelGGL(k_scatter, dim3(h->g_scatter), b, 0, s, ev[8], ev[9], 0, d);
 }
 
@@ -265,7 +269,20 @@ sim_status sim_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void
     return SIM_OK;
 }
 
+namespace {
+sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_idm_params* p, const uint32_t* rng_id,
+                       sim_handle** out);
+}
+
 sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm_params* p, sim_handle** out) {
+    return create_impl(net, r, p, nullptr, out);
+}
+
+}  // extern "C"
+
+namespace {
+sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_idm_params* p, const uint32_t* rng_id,
+                       sim_handle** out) {
     if (!out) return SIM_EINVAL;
     *out = nullptr;
     sim_handle* h = nullptr;
@@ -348,34 +365,69 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
                 h->ins_lane[i] = il;
                 ins_gl[i] = h->lane_base[e0] + il;
             }
-            std::vector<int> order(N);
-            for (int i = 0; i < N; ++i) order[i] = i;
-            std::stable_sort(order.begin(), order.end(),
-                             [&](int a, int b) { return h->dep[a] < h->dep[b]; });
             int max_dep = -1;
             for (int i = 0; i < N; ++i) max_dep = std::max(max_dep, h->dep[i]);
             std::vector<int> due(std::max(1, max_dep + 1), 0);
             for (int i = 0; i < N; ++i) due[h->dep[i]]++;
             for (int k = 1; k <= max_dep; ++k) due[k] += due[k - 1];
+            // departure queues: (entry lane, class), each sorted by (step, id)
+            std::vector<int> order(N);
+            for (int i = 0; i < N; ++i) order[i] = i;
+            std::sort(order.begin(), order.end(), [&](int a, int b) {
+                if (ins_gl[a] != ins_gl[b]) return ins_gl[a] < ins_gl[b];
+                if (h->cls[a] != h->cls[b]) return h->cls[a] < h->cls[b];
+                if (h->dep[a] != h->dep[b]) return h->dep[a] < h->dep[b];
+                return a < b;
+            });
+            h->qveh = order;
+            h->qoff.assign(1, 0);
+            std::vector<int> qlane;
+            for (int k = 0; k < N; ++k) {
+                const int i = order[k];
+                if (k == 0 || ins_gl[i] != ins_gl[order[k - 1]] || h->cls[i] != h->cls[order[k - 1]]) {
+                    if (k > 0) h->qoff.push_back(k);
+                    qlane.push_back(ins_gl[i]);
+                }
+            }
+            if (N > 0) h->qoff.push_back(N);
+            const int NQ = (int)qlane.size();
+            std::vector<int> eq_off(E + 1, 0), lane_edge_h(NL);
+            for (int e = 0; e < E; ++e)
+                for (int l = 0; l < h->lanes[e]; ++l) lane_edge_h[h->lane_base[e] + l] = e;
+            for (int q = 0; q < NQ; ++q) eq_off[lane_edge_h[qlane[q]] + 1]++;
+            for (int e = 0; e < E; ++e) eq_off[e + 1] += eq_off[e];
+            std::vector<int> ins_edges;
+            for (int e = 0; e < E; ++e)
+                if (eq_off[e + 1] > eq_off[e]) ins_edges.push_back(e);
             d.roff = h->upload(h->roff.data(), N + 1);
             d.redges = h->upload(h->redges.data(), (size_t)NR);
             d.dep = h->upload(h->dep.data(), N);
             d.cls = h->upload(h->cls.data(), N);
             d.alpha = h->upload(r->alpha_s, N);
             d.ins_gl = h->upload(ins_gl.data(), N);
-            d.wait_order = h->upload(order.data(), N);
             d.due = h->upload(due.data(), due.size());
             d.max_dep = max_dep;
+            d.qveh = h->upload(h->qveh.data(), N);
+            d.qoff = h->upload(h->qoff.data(), NQ + 1);
+            d.qhead = h->upload(h->qoff.data(), NQ + 1);
+            d.eq_off = h->upload(eq_off.data(), E + 1);
+            d.ins_edges = h->upload(ins_edges.data(), ins_edges.size());
+            d.n_ins_edges = (int)ins_edges.size();
+            std::vector<uint32_t> rid(N);
+            for (int i = 0; i < N; ++i) rid[i] = rng_id ? rng_id[i] : (uint32_t)i;
+            d.rid = h->upload(rid.data(), N);
             // ---- capacity of the largest edge (vehicles never overlap)
             long long max_edge = 1;
             for (int e = 0; e < E; ++e)
                 max_edge = std::max(max_edge, (long long)h->lanes[e] * ((long long)(h->L[e] / len_min) + 1));
-            const long long cap_all = std::min<long long>(std::max(N, 1), (long long)kTileWindow - 1 + max_edge);
+            const long long cap_all = std::min<long long>(std::max(N, 1), (long long)kTileWindowMax - 1 + max_edge);
             d.big_cap = (int)std::max<long long>(kTileCapLds + 1, cap_all);
-            h->g_tile = std::max(1, std::min(1024, (N + kTileWindow - 1) / kTileWindow));
+            d.tile_window = kTileWindowMax;
+            h->g_tile = std::max(1, std::min(1024, (N + kTileWindowMax - 1) / kTileWindowMax));
+            h->g_big_max = std::max(1, std::min(256, (N + kTileWindowMin - 1) / kTileWindowMin));
             h->g_big = std::max(1, std::min(256, h->g_tile));
+            h->g_scatter_max = std::max(1, std::min(4096, (N + kNT - 1) / kNT));
             h->g_items = std::max(1, std::min(512, (E + N + kNT - 1) / kNT));
-            h->g_ins = std::max(1, std::min(256, (N + kNT - 1) / kNT));
             h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
             h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
             d.n_blk = h->n_blk;
@@ -389,7 +441,6 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
                 d.s[b].meta = h->dev<uint32_t>(NV);
                 d.s[b].nxt = h->dev<int32_t>(NV);
                 d.req_edges[b] = h->dev<int>(E);
-                d.pend[b] = h->dev<int>(NV);
             }
             d.ent = h->dev<EntryRec>(std::min<size_t>(NV, (size_t)NL + 1));
             d.status = h->dev<uint8_t>(NV);
@@ -418,8 +469,8 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
             d.tt_cnt = h->dev<unsigned long long>(E);
             d.ctl = h->dev<Ctl>(1);
             d.counters = h->dev<unsigned long long>(cNumCounters * kCounterCopies);
-            d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindow + 2));
-            d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big);
+            d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindowMin + 2));
+            d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big_max);
             // ---- initial values
             HIP_OK(hipMemset(d.rear, 0xFF, sizeof(LaneRear) * NL));
             HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * NL));
@@ -452,6 +503,9 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
     if (st == SIM_OK) *out = h;
     return st;
 }
+}  // namespace
+
+extern "C" {
 
 sim_status sim_set_stream(sim_handle* h, void* stream) {
     if (!h) return SIM_EINVAL;
@@ -669,10 +723,19 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
             const bool last = (k + 1 == na) || act[k + 1].edge != e || act[k + 1].lane != act[k].lane;
             if (last) rear[h->lane_base[e] + act[k].lane] = LaneRear{in->x[i] - h->len_c[h->cls[i]], in->v[i], t, 0};
         }
-        // vehicles still waiting whose departure step has passed
-        std::vector<int> pend;
-        for (int i = 0; i < N; ++i)
-            if (in->status[i] == kWaiting && h->dep[i] <= t - 1) pend.push_back(i);
+        // departure queues: the vehicles that have left a queue must be a prefix of it
+        std::vector<int> qhead(h->qoff.begin(), h->qoff.end());
+        int departed = 0;
+        for (size_t q = 0; q + 1 < h->qoff.size(); ++q) {
+            int k = h->qoff[q];
+            while (k < h->qoff[q + 1] && in->status[h->qveh[k]] != kWaiting) ++k;
+            for (int k2 = k; k2 < h->qoff[q + 1]; ++k2)
+                if (in->status[h->qveh[k2]] != kWaiting)
+                    throw Fail{SIM_EINVAL, fmt("vehicle %d departed before an earlier vehicle of its entry lane",
+                                               h->qveh[k2])};
+            qhead[q] = k;
+            departed += k - h->qoff[q];
+        }
         std::vector<uint8_t> st(in->status, in->status + N);
         std::vector<float> fx(N, 0.f), fv(N, 0.f);
         std::vector<uint32_t> fmeta(N, 0);
@@ -702,8 +765,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
             HIP_OK(hipMemcpy(d.fin_v, fv.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(d.fin_meta, fmeta.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
         }
-        if (!pend.empty())
-            HIP_OK(hipMemcpy(d.pend[par], pend.data(), 4 * pend.size(), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d.qhead, qhead.data(), 4 * qhead.size(), hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d.cnt, cnt.data(), 4 * (size_t)h->n_edges, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d.rear, rear.data(), sizeof(LaneRear) * h->n_lanes, hipMemcpyHostToDevice));
         HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * h->n_lanes));
@@ -717,7 +779,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         c.t_a = t;
         c.t_b = t;
         c.n_act[par] = na;
-        c.n_pend[par] = (int)pend.size();
+        c.n_departed = departed;
         HIP_OK(hipMemcpy(d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice));
         if (in->counters) {
             unsigned long long cc[cNumCounters * kCounterCopies] = {};
@@ -747,6 +809,214 @@ sim_status sim_destroy(sim_handle* h) {
 }
 
 const char* sim_last_error(const sim_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+// ---- ensembles -----------------------------------------------------------
+sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, const sim_scenario* sc, int32_t ns,
+                               const sim_idm_params* p, sim_handle** out) {
+    if (!out) return SIM_EINVAL;
+    *out = nullptr;
+    std::vector<int32_t> ef, et, co, ct, dp, re, vo;
+    std::vector<float> ln, li, al;
+    std::vector<uint8_t> la, cm, vc;
+    std::vector<int64_t> ro;
+    std::vector<uint32_t> rid;
+    sim_network un{};
+    sim_routes ur{};
+    sim_status st = guarded(nullptr, [&] {
+        auto bad = [](std::string msg) { throw Fail{SIM_EINVAL, std::move(msg)}; };
+        if (!net || !m || !p || !sc) bad("null argument");
+        if (ns < 1) bad("n_scen must be >= 1");
+        if (net->n_edges <= 0 || net->n_nodes <= 0 || !net->conn_off || !net->n_lanes) bad("network missing");
+        if (m->n_vehicles < 0 || (m->n_vehicles > 0 && (!m->route_off || !m->route_edges))) bad("master demand missing");
+        const int64_t E = net->n_edges, V = net->n_nodes, NC = net->conn_off[E];
+        if (E * ns >= (1ll << 27) || V * ns >= (1ll << 31)) bad("ensemble too large for 32-bit ids");
+        int64_t ntot = 0;
+        for (int k = 0; k < ns; ++k) {
+            if (sc[k].n_vehicles < 0 || sc[k].n_vehicles > m->n_vehicles)
+                bad(fmt("scenario %d: n_vehicles outside [0, master]", k));
+            if (sc[k].n_reduced < 0 || (sc[k].n_reduced > 0 && !sc[k].reduced_edges))
+                bad(fmt("scenario %d: reduced edges missing", k));
+            for (int q = 0; q < sc[k].n_reduced; ++q)
+                if (sc[k].reduced_edges[q] < 0 || sc[k].reduced_edges[q] >= E)
+                    bad(fmt("scenario %d: reduced edge out of range", k));
+            ntot += sc[k].n_vehicles;
+        }
+        if (ntot >= (1ll << 31)) bad("ensemble has too many vehicles");
+        const size_t EU = (size_t)(E * ns);
+        ef.resize(EU); et.resize(EU); ln.resize(EU); li.resize(EU); la.resize(EU);
+        co.resize(EU + 1); ct.resize((size_t)NC * ns); cm.resize((size_t)NC * ns);
+        co[0] = 0;
+        for (int k = 0; k < ns; ++k) {
+            std::vector<uint8_t> red((size_t)E, 0);
+            for (int q = 0; q < sc[k].n_reduced; ++q) red[sc[k].reduced_edges[q]] = 1;
+            for (int64_t e = 0; e < E; ++e) {
+                const size_t u = (size_t)(k * E + e);
+                ef[u] = (int32_t)(net->edge_from[e] + k * V);
+                et[u] = (int32_t)(net->edge_to[e] + k * V);
+                ln[u] = net->length_m[e];
+                li[u] = net->speed_limit_mps[e];
+                la[u] = red[e] ? 1 : net->n_lanes[e];
+                for (int c = net->conn_off[e]; c < net->conn_off[e + 1]; ++c) {
+                    const size_t cu = (size_t)(k * NC + c);
+                    ct[cu] = (int32_t)(net->conn_to[c] + k * E);
+                    cm[cu] = red[e] ? 1 : net->conn_lane_mask[c];
+                }
+                co[u + 1] = (int32_t)(k * NC + net->conn_off[e + 1]);
+            }
+        }
+        vo.assign(ns + 1, 0);
+        ro.assign(1, 0);
+        for (int k = 0; k < ns; ++k) {
+            const int n = sc[k].n_vehicles;
+            for (int i = 0; i < n; ++i) {
+                for (int64_t q = m->route_off[i]; q < m->route_off[i + 1]; ++q)
+                    re.push_back((int32_t)(m->route_edges[q] + k * E));
+                ro.push_back((int64_t)re.size());
+                dp.push_back(m->depart_step[i]);
+                vc.push_back(m->vclass[i]);
+                al.push_back(m->alpha_s[i]);
+                rid.push_back((uint32_t)i);
+            }
+            vo[k + 1] = vo[k] + n;
+        }
+        un = sim_network{(int32_t)(V * ns), (int32_t)EU, ef.data(), et.data(), ln.data(), li.data(), la.data(),
+                         co.data(), ct.data(), cm.data()};
+        ur = sim_routes{(int32_t)ntot, ro.data(), re.data(), dp.data(), vc.data(), al.data()};
+    });
+    if (st != SIM_OK) return st;
+    st = create_impl(&un, &ur, p, rid.data(), out);
+    if (st == SIM_OK) {
+        (*out)->n_scen = ns;
+        (*out)->veh_off = vo;
+    }
+    return st;
+}
+
+sim_status sim_ensemble_offsets(const sim_handle* h, int32_t* n_scen, int32_t* veh_off) {
+    if (!h) return SIM_EINVAL;
+    if (n_scen) *n_scen = h->n_scen;
+    if (veh_off) {
+        if (h->veh_off.empty()) {
+            veh_off[0] = 0;
+            veh_off[1] = h->n_veh;
+        } else {
+            for (size_t k = 0; k < h->veh_off.size(); ++k) veh_off[k] = h->veh_off[k];
+        }
+    }
+    return SIM_OK;
+}
+
+// ---- schedule and autotuner -----------------------------------------------
+sim_status sim_get_schedule(const sim_handle* h, int32_t* sched) {
+    if (!h || !sched) return SIM_EINVAL;
+    sched[0] = h->d.tile_window;
+    sched[1] = h->g_tile;
+    sched[2] = h->g_big;
+    sched[3] = h->g_items;
+    sched[4] = h->g_scatter;
+    return SIM_OK;
+}
+
+namespace {
+bool set_schedule(sim_handle* h, int w, int g1, int g2, int g3, int g4) {
+    if (w < kTileWindowMin || w > kTileWindowMax || (w & (w - 1)) != 0) return false;
+    if (g1 < 1 || g2 < 1 || g2 > h->g_big_max || g3 < 1 || g4 < 1 || g4 > h->g_scatter_max) return false;
+    h->d.tile_window = w;
+    h->g_tile = g1;
+    h->g_big = g2;
+    h->g_items = g3;
+    h->g_scatter = g4;
+    return true;
+}
+}  // namespace
+
+sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
+    if (!h || steps < 1) return SIM_EINVAL;
+    return guarded(h, [&] {
+        char key[160];
+        snprintf(key, sizeof(key), "manta-schedule E=%d L=%d N=%d S=%d", h->n_edges, h->n_lanes, h->n_veh, h->n_scen);
+        if (cache_path) {
+            if (FILE* f = fopen(cache_path, "r")) {
+                char line[256];
+                int w, g1, g2, g3, g4;
+                bool hit = false;
+                while (fgets(line, sizeof(line), f)) {
+                    if (strncmp(line, key, strlen(key)) == 0 && line[strlen(key)] == ' ' &&
+                        sscanf(line + strlen(key), " -> %d %d %d %d %d", &w, &g1, &g2, &g3, &g4) == 5 &&
+                        set_schedule(h, w, g1, g2, g3, g4))
+                        hit = true;
+                }
+                fclose(f);
+                if (hit) {
+                    capture_graph(h);
+                    return;
+                }
+            }
+        }
+        // snapshot of the state (restored after every trial)
+        const int N = h->n_veh;
+        std::vector<uint8_t> st(N), mand(N);
+        std::vector<int32_t> edge(N), lane(N), cur(N), hs(N), ww(N);
+        std::vector<float> x(N), v(N);
+        std::vector<double> tin(N), tar(N);
+        std::vector<int64_t> cnt(SIM_N_COUNTERS);
+        sim_state snap{st.data(), edge.data(), lane.data(), cur.data(), x.data(), v.data(), hs.data(),
+                       mand.data(), ww.data(), tin.data(), tar.data(), cnt.data(), 0};
+        if (sim_read_state(h, &snap) != SIM_OK) throw Fail{SIM_EDEVICE, h->err};
+        const size_t E = (size_t)h->n_edges;
+        std::vector<double> tts(E);
+        std::vector<unsigned long long> ttc(E);
+        HIP_OK(hipMemcpy(tts.data(), h->d.tt_sum, 8 * E, hipMemcpyDeviceToHost));
+        HIP_OK(hipMemcpy(ttc.data(), h->d.tt_cnt, 8 * E, hipMemcpyDeviceToHost));
+        const int w0 = h->d.tile_window, g10 = h->g_tile, g20 = h->g_big, g30 = h->g_items, g40 = h->g_scatter;
+        struct Cand {
+            int w, g1, g2, g3, g4;
+        };
+        std::vector<Cand> cands;
+        for (int w : {64, 128, 256})
+            for (int g1 : {512, 1024})
+                for (int g4 : {1024, 4096}) {
+                    const int g1c = std::max(1, std::min(g1, (N + w - 1) / w));
+                    const int g4c = std::max(1, std::min(g4, h->g_scatter_max));
+                    bool dup = false;
+                    for (auto& c : cands) dup = dup || (c.w == w && c.g1 == g1c && c.g4 == g4c);
+                    if (!dup) cands.push_back(Cand{w, g1c, g20, g30, g4c});
+                }
+        double best_ms = 1e30;
+        Cand best{w0, g10, g20, g30, g40};
+        hipEvent_t e0, e1;
+        HIP_OK(hipEventCreate(&e0));
+        HIP_OK(hipEventCreate(&e1));
+        for (const Cand& c : cands) {
+            if (!set_schedule(h, c.w, c.g1, c.g2, c.g3, c.g4)) continue;
+            if (sim_write_state(h, &snap) != SIM_OK) throw Fail{SIM_EDEVICE, h->err};
+            launch_step(h, h->stream);   // first launch of a schedule is not timed
+            HIP_OK(hipEventRecord(e0, h->stream));
+            for (int q = 0; q < steps; ++q) launch_step(h, h->stream);
+            HIP_OK(hipEventRecord(e1, h->stream));
+            HIP_OK(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_OK(hipEventElapsedTime(&ms, e0, e1));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = c;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        set_schedule(h, best.w, best.g1, best.g2, best.g3, best.g4);
+        if (sim_write_state(h, &snap) != SIM_OK) throw Fail{SIM_EDEVICE, h->err};
+        HIP_OK(hipMemcpy(h->d.tt_sum, tts.data(), 8 * E, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(h->d.tt_cnt, ttc.data(), 8 * E, hipMemcpyHostToDevice));
+        capture_graph(h);
+        if (cache_path) {
+            if (FILE* f = fopen(cache_path, "a")) {
+                fprintf(f, "%s -> %d %d %d %d %d\n", key, best.w, best.g1, best.g2, best.g3, best.g4);
+                fclose(f);
+            }
+        }
+    });
+}
 
 // ---- diagnostics ---------------------------------------------------------
 sim_status sim_probe_fp32(int32_t op, const float* a, const float* b, float* out, int64_t n) {

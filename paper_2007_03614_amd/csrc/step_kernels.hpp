@@ -26,7 +26,8 @@ namespace manta {
 
 constexpr int kNT = 256;                 // threads per workgroup (4 waves)
 constexpr int kWaves = kNT / 64;
-constexpr int kTileWindow = 256;         // a tile = the edges whose first slot lies in a 256-slot window
+constexpr int kTileWindowMax = 256;      // a tile = the edges whose first slot lies in a window of
+constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256)
 constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
 constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
@@ -64,11 +65,11 @@ struct Ctl {
     int t_b;
     int n_act[2];
     int n_req[2];
-    int n_pend[2];
     int n_ent[2];
     int n_big[2];     // tiles above kTileCapLds, listed for k_tile_big
     unsigned done2;   // commit edge blocks finished (last one scans block sums)
     int err;          // non-zero: a layout bound check failed (see kErr*)
+    int n_departed;   // vehicles admitted from the departure queues so far
     int pad[4];
 };
 
@@ -137,8 +138,17 @@ struct Dev {
     const uint8_t* cls;
     const float* alpha;
     const int* ins_gl;          // global entry lane of each vehicle
-    const int* wait_order;      // vehicle ids sorted by (departure step, id)
     const int* due;             // due[t] = vehicles with departure step <= t, t <= max_dep
+    // departure queues, one per (entry lane, class), sorted by (departure
+    // step, id): all members share the admission test, so only the head can
+    // hold the smallest eligible key of its queue
+    const int* qveh;            // vehicle ids, queue by queue
+    const int* qoff;            // [n_queues + 1]
+    int* qhead;                 // next vehicle of each queue
+    const int* eq_off;          // [n_edges + 1]: queues of edge e
+    const int* ins_edges;       // edges that have a queue
+    int n_ins_edges;
+    const uint32_t* rid;        // id used in the random-number counter
     int max_dep;
     const ClassParams* cp;
     float dt;
@@ -176,11 +186,11 @@ struct Dev {
     unsigned long long* tt_cnt;
     // lists
     int* req_edges[2];
-    int* pend[2];
     EntryRec* ent;
     // big tiles: (first, end) slot pairs, and global scratch for single
     // edges beyond the LDS of a workgroup
     int* big_list;
+    int tile_window;
     char* big;
     int big_cap;                // vehicles per workgroup region
 };
@@ -437,7 +447,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 } else {
                     const float dm = dd - kX0;
                     const float z = dm * dm;
-                    if (z < kZCut && draw_uniform(d.seed, t, id, 1) < exp_eq2(-z)) trig = true;
+                    if (z < kZCut && draw_uniform(d.seed, t, d.rid[id], 1) < exp_eq2(-z)) trig = true;
                 }
                 if (trig) {
                     m |= 1u << 4;
@@ -479,14 +489,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                     if (la >= 0) {
                         const float G = (b.x[la] - d.cp[m_cls(b.meta[la])].len) - xi;
                         const float g = crit_gap(g0, d.alpha[b.vid[la]], vi, ai, b.v[la]) +
-                                        draw_normal(d.seed, t, id, 2);
+                                        draw_normal(d.seed, t, d.rid[id], 2);
                         const float need = g > 0.0f ? g : 0.0f;
                         ok = ok && (G >= need);
                     }
                     if (lb >= 0) {
                         const float G = (xi - cpi.len) - b.x[lb];
                         const float g = crit_gap(g0, ai, vi, d.alpha[b.vid[lb]], b.v[lb]) +
-                                        draw_normal(d.seed, t, id, 3);
+                                        draw_normal(d.seed, t, d.rid[id], 3);
                         const float need = g > 0.0f ? g : 0.0f;
                         ok = ok && (G >= need);
                     }
@@ -733,16 +743,16 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         // the later kernels of this step read t_b; lists of the next step
         // are unused during this one
         d.ctl->t_b = t;
-        d.ctl->n_pend[par ^ 1] = 0;
         d.ctl->n_req[par ^ 1] = 0;
         d.ctl->n_ent[par ^ 1] = 0;
         d.ctl->n_big[par ^ 1] = 0;
     }
     __syncthreads();
-    const int ntile = (n + kTileWindow - 1) / kTileWindow;
+    const int W = d.tile_window;
+    const int ntile = (n + W - 1) / W;
     const int32_t* edge = d.s[par].edge;
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
-        const int w0 = k * kTileWindow, w1 = min(n, w0 + kTileWindow);
+        const int w0 = k * W, w1 = min(n, w0 + W);
         const int a0 = first_edge_start<kNT>(edge, w0, w1, wsh);
         if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
         const int a1 = first_edge_start<kNT>(edge, w1, n, wsh);
@@ -831,17 +841,12 @@ __device__ inline unsigned long long insert_key(const Dev& d, int vid) {
     return (1ull << 63) | ((unsigned long long)(uint32_t)d.dep[vid] << 32) | (uint32_t)vid;
 }
 
-__device__ inline void item_ranges(const Dev& d, int t, int par, int& nreq, int& npend, int& due_lo, int& ndue) {
-    nreq = d.ctl->n_req[par];
-    npend = d.ctl->n_pend[par];
-    if (d.max_dep < 0 || t > d.max_dep + 1) {
-        due_lo = 0;
-        ndue = 0;
-        return;
-    }
-    due_lo = t > 0 ? d.due[min(t - 1, d.max_dep)] : 0;
-    const int due_hi = t <= d.max_dep ? d.due[t] : d.due[d.max_dep];
-    ndue = due_hi - due_lo;
+// head of departure queue q if it is due at step t, else -1
+__device__ inline int queue_due_head(const Dev& d, int q, int t) {
+    const int h = d.qhead[q];
+    if (h >= d.qoff[q + 1]) return -1;
+    const int vid = d.qveh[h];
+    return d.dep[vid] <= t ? vid : -1;
 }
 
 // An eligible request lowers the lane's 64-bit key with atomicMin; the
@@ -858,9 +863,8 @@ __device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t
 
 __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
     const int t = d.ctl->t_a, par = t & 1;
-    int nreq, npend, due_lo, ndue;
-    item_ranges(d, t, par, nreq, npend, due_lo, ndue);
-    const int total = nreq + npend + ndue;
+    const int nreq = d.ctl->n_req[par];
+    const int total = nreq + d.n_ins_edges;
     for (int i = blockIdx.x * kNT + threadIdx.x; i < total; i += gridDim.x * kNT) {
         if (i < nreq) {
             const int e = d.req_edges[par][i];
@@ -871,13 +875,14 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
                 if (transfer_eligible(d, ob, t)) claim(d, ob.target, ob.key, t);
             }
         } else {
-            const int vid = i < nreq + npend ? d.pend[par][i - nreq] : d.wait_order[due_lo + (i - nreq - npend)];
-            if (insert_eligible(d, vid, t)) claim(d, d.ins_gl[vid], insert_key(d, vid), t);
+            const int e = d.ins_edges[i - nreq];
+            for (int q = d.eq_off[e]; q < d.eq_off[e + 1]; ++q) {
+                const int vid = queue_due_head(d, q, t);
+                if (vid >= 0 && insert_eligible(d, vid, t)) claim(d, d.ins_gl[vid], insert_key(d, vid), t);
+            }
         }
     }
 }
-
-
 
 // Outcome of the end-of-edge requests of edge e: arrivals, admitted
 // transfers and held losers; the travel times of the vehicles leaving e are
@@ -978,9 +983,10 @@ __device__ inline void write_entries(const Dev& d, const Slots& S, int e, unsign
     }
 }
 
-// Workgroups [0, n_blk): 1,024 edges each -- commit, new per-edge and
-// per-lane counts, in-block offsets; the last of them to finish scans the
-// block sums.  Workgroups [n_blk, grid): departures that asked for a lane.
+// One thread per edge: commit of its end-of-edge requests, admission of the
+// due heads of its departure queues, new lane and edge counts, offsets in
+// the workgroup.  The last workgroup to finish scans the workgroup sums and
+// adds the refused departures of the step to their counter.
 __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     __shared__ unsigned shc[cNumCounters];
     __shared__ Scan4 wsh4[kWaves];
@@ -991,111 +997,101 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     const Slots S = d.s[par];
     CounterAcc acc;
     acc.zero();
-    if ((int)blockIdx.x < d.n_blk) {
-        constexpr int kPer = kEdgeBlock / kNT;
-        static_assert(kPer == 1, "one edge per thread");
-        const int e = blockIdx.x * kEdgeBlock + threadIdx.x;
-        int newc[1] = {0};
-        int tot = 0;
-        const int e_lo = e;
-        unsigned winmask = 0;
-        if (e < d.n_edges) {
-            int nex = 0;
-            unsigned exmask = 0;
-            if (d.req_stamp[e] == t) commit_edge(d, S, e, t, acc, nex, exmask, winmask);
-            const int c = d.cnt[e] - nex + d.entries[e];
-            d.cnt[e] = c;
-            d.entries[e] = 0;
-            newc[0] = c;
-            tot = c;
-            if (c > 0) {
-                int o = 0;
-                const int base = d.lane_base[e];
-                for (int l = 0; l < d.lanes[e]; ++l) {
-                    const int gl = base + l;
-                    const LanePost p = d.post[gl];
-                    int nc = (p.stamp == t) ? p.cnt : 0;
-                    if ((exmask >> l) & 1u) nc -= 1;
-                    if (d.enter_stamp[gl] == t) nc += 1;
-                    d.lane_rel[gl] = o;
-                    d.lane_newcnt[gl] = nc;
-                    o += nc;
-                }
-            }
+    const int e = blockIdx.x * kEdgeBlock + threadIdx.x;
+    int c = 0;
+    unsigned winmask = 0;
+    int insq[8];
+    int nins = 0;
+    if (e < d.n_edges) {
+        int nex = 0;
+        unsigned exmask = 0;
+        if (d.req_stamp[e] == t) commit_edge(d, S, e, t, acc, nex, exmask, winmask);
+        for (int q = d.eq_off[e]; q < d.eq_off[e + 1]; ++q) {
+            const int vid = queue_due_head(d, q, t);
+            if (vid >= 0 && insert_eligible(d, vid, t) && d.win[d.ins_gl[vid]] == insert_key(d, vid))
+                insq[nins++] = q;   // at most one winner per lane
         }
-        const int k0 = wave_reserve(&d.ctl->n_ent[par], __popc(winmask));
-        if (winmask) write_entries(d, S, e, winmask, k0);
-        Scan4 run = wg_exclusive_scan4(Scan4{tot, -1, -1, -1}, wsh4);
-        int off = run.s;
-#pragma unroll
-        for (int q = 0; q < kPer; ++q) {
-            const int e = e_lo + q;
-            if (e < d.n_edges) d.edge_rel[e] = off;
-            off += newc[q];
-        }
-        if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = off;
-        __syncthreads();
-        if (threadIdx.x == kNT - 1) {
-            __threadfence();
-            last = (atomicAdd(&d.ctl->done2, 1u) == (unsigned)d.n_blk - 1u);
-        }
-        __syncthreads();
-        if (last) {   // every block sum is written: scan them (one workgroup)
-            __threadfence();
-            const int nb = d.n_blk;
-            const int chunk = (nb + kNT - 1) / kNT;
-            const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
-            int loc = 0;
-            for (int i = lo; i < hi; ++i) loc += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            Scan4 r2 = wg_exclusive_scan4(Scan4{loc, -1, -1, -1}, wsh4);
-            int o2 = r2.s;
-            for (int i = lo; i < hi; ++i) {
-                d.blk_off[i] = o2;
-                o2 += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-            if (threadIdx.x == kNT - 1) {
-                d.ctl->n_act[par ^ 1] = o2;
-                d.ctl->done2 = 0;
-                d.ctl->t_a = t + 1;   // k_tile_step and k_admit of this step are done
-            }
-        }
-    } else {
-        int nreq, npend, due_lo, ndue;
-        item_ranges(d, t, par, nreq, npend, due_lo, ndue);
-        const int total = npend + ndue;
-        const int stride = (gridDim.x - d.n_blk) * kNT;
-        for (int i = (blockIdx.x - d.n_blk) * kNT + threadIdx.x; i < total; i += stride) {
-            const int vid = i < npend ? d.pend[par][i] : d.wait_order[due_lo + (i - npend)];
-            const int g = d.ins_gl[vid];
-            const bool won = insert_eligible(d, vid, t) && d.win[g] == insert_key(d, vid);
-            const int ke = wave_append(&d.ctl->n_ent[par], won);
-            const int kp = wave_append(&d.ctl->n_pend[par ^ 1], !won);
-            if (won) {
-                const int64_t r0 = d.roff[vid];
-                const int e0 = d.redges[r0];
-                const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
-                EntryRec r;
-                r.x = 0.0f;
-                r.v = 0.0f;
-                r.vid = (uint32_t)vid;
-                r.edge = e0;
-                r.gl = g;
-                r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], conn_mask_of(d, e0, nn));
-                r.nxt = nn;
-                r.pad = 0;
-                d.status[vid] = kActive;
-                d.cursor[vid] = 0;
-                d.held_since[vid] = -1;
-                d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
-                d.ent[ke] = r;
-                acc.c[cDeparted]++;
-            } else {
-                d.pend[par ^ 1][kp] = vid;
-                acc.c[cInsertDenied]++;
+        c = d.cnt[e] - nex + d.entries[e];
+        d.cnt[e] = c;
+        d.entries[e] = 0;
+        if (c > 0) {
+            int o = 0;
+            const int base = d.lane_base[e];
+            for (int l = 0; l < d.lanes[e]; ++l) {
+                const int gl = base + l;
+                const LanePost p = d.post[gl];
+                int nc = (p.stamp == t) ? p.cnt : 0;
+                if ((exmask >> l) & 1u) nc -= 1;
+                if (d.enter_stamp[gl] == t) nc += 1;
+                d.lane_rel[gl] = o;
+                d.lane_newcnt[gl] = nc;
+                o += nc;
             }
         }
     }
+    int k = wave_reserve(&d.ctl->n_ent[par], __popc(winmask) + nins);
+    if (winmask) {
+        write_entries(d, S, e, winmask, k);
+        k += __popc(winmask);
+    }
+    for (int a = 0; a < nins; ++a) {
+        const int q = insq[a];
+        const int vid = d.qveh[d.qhead[q]];
+        d.qhead[q] += 1;
+        const int g = d.ins_gl[vid];
+        const int64_t r0 = d.roff[vid];
+        const int e0 = d.redges[r0];
+        const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
+        EntryRec r;
+        r.x = 0.0f;
+        r.v = 0.0f;
+        r.vid = (uint32_t)vid;
+        r.edge = e0;
+        r.gl = g;
+        r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], conn_mask_of(d, e0, nn));
+        r.nxt = nn;
+        r.pad = 0;
+        d.status[vid] = kActive;
+        d.cursor[vid] = 0;
+        d.held_since[vid] = -1;
+        d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
+        d.ent[k++] = r;
+        acc.c[cDeparted]++;
+    }
+    Scan4 run = wg_exclusive_scan4(Scan4{c, -1, -1, -1}, wsh4);
+    if (e < d.n_edges) d.edge_rel[e] = run.s;
+    if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = run.s + c;
     flush_counters_lds(d, acc, shc);
+    if (threadIdx.x == kNT - 1) {
+        if (shc[cDeparted]) atomicAdd(&d.ctl->n_departed, (int)shc[cDeparted]);
+        __threadfence();
+        last = (atomicAdd(&d.ctl->done2, 1u) == (unsigned)d.n_blk - 1u);
+    }
+    __syncthreads();
+    if (last) {   // every workgroup sum is written: scan them (one workgroup)
+        __threadfence();
+        const int nb = d.n_blk;
+        const int chunk = (nb + kNT - 1) / kNT;
+        const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
+        int loc = 0;
+        for (int i = lo; i < hi; ++i) loc += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        Scan4 r2 = wg_exclusive_scan4(Scan4{loc, -1, -1, -1}, wsh4);
+        int o2 = r2.s;
+        for (int i = lo; i < hi; ++i) {
+            d.blk_off[i] = o2;
+            o2 += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (threadIdx.x == kNT - 1) {
+            d.ctl->n_act[par ^ 1] = o2;
+            d.ctl->done2 = 0;
+            // every due vehicle still waiting asked for a lane this step and was refused
+            const int due_now = d.max_dep < 0 ? 0 : d.due[min(t, d.max_dep)];
+            const int departed = __hip_atomic_load(&d.ctl->n_departed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (due_now > departed)
+                atomicAdd(&d.counters[cInsertDenied * kCounterCopies], (unsigned long long)(due_now - departed));
+            d.ctl->t_a = t + 1;   // k_tile_step and k_admit of this step are done
+        }
+    }
 }
 
 // ---- next layout -----------------------------------------------------------

@@ -130,3 +130,15 @@ def test_allocator_callbacks_outlive_handles(M):
     M.use_hip_allocator()
     M.use_torch_allocator()
     assert M._torch_cb is first
+
+
+def test_ensemble_validation(M, base):
+    with pytest.raises(M.SimError) as ei:
+        M.Sim(base, allocator="hip", scenarios=[])
+    assert ei.value.name == "SIM_EINVAL"
+    with pytest.raises(M.SimError) as ei:
+        M.Sim(base, allocator="hip", scenarios=[(base.n_vehicles + 1, np.array([], np.int32))])
+    assert "n_vehicles" in str(ei.value)
+    with pytest.raises(M.SimError) as ei:
+        M.Sim(base, allocator="hip", scenarios=[(10, np.array([base.net.n_edges], np.int32))])
+    assert "reduced edge" in str(ei.value)

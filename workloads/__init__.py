@@ -456,4 +456,52 @@ def scaled_config2(n_vehicles: int, rows: int, cols: int, n_steps: int, seed: in
     return w
 
 
+def scenario_workload(master: Workload, n_vehicles: int, reduced_edges) -> Workload:
+    """One what-if scenario on its own: the first n_vehicles of the master
+    demand on the master network with `reduced_edges` cut to one lane (every
+    move out of a reduced edge then leaves from lane 0)."""
+    net = master.net
+    lanes = net.lanes.copy()
+    mask = net.conn_mask.copy()
+    for e in np.asarray(reduced_edges, np.int64):
+        lanes[e] = 1
+        mask[net.conn_off[e]:net.conn_off[e + 1]] = 1
+    n2 = Network(node_x=net.node_x, node_y=net.node_y, edge_from=net.edge_from, edge_to=net.edge_to,
+                 length=net.length, limit=net.limit, lanes=lanes, conn_off=net.conn_off, conn_to=net.conn_to,
+                 conn_mask=mask)
+    ro = master.route_off[:n_vehicles + 1].copy()
+    return Workload(f"{master.name}_scenario", n2, ro, master.route_edges[:int(ro[-1])].copy(),
+                    master.depart_step[:n_vehicles].copy(), master.vclass[:n_vehicles].copy(),
+                    master.alpha[:n_vehicles].copy(), master.params, master.n_steps)
+
+
+def ensemble_scenarios(n_scen: int, base: int, n_edges: int, seed: int = 0, scale=(0.8, 1.2),
+                       reduced_frac: float = 0.01):
+    """Scenario list: demand round(U[scale] * base) vehicles of the master
+    list and ceil(reduced_frac * n_edges) random edges cut to one lane."""
+    r = _rng(seed, _P_SCEN)
+    k = int(math.ceil(reduced_frac * n_edges))
+    out = []
+    for _ in range(n_scen):
+        n = int(round(r.uniform(*scale) * base))
+        red = np.sort(r.choice(n_edges, size=k, replace=False)).astype(np.int32)
+        out.append((n, red))
+    return out
+
+
+def config4(seed: int = 0, n_scen: int = 64, base: int = 200_000, n_steps: int = 14_400):
+    """Ensemble on the 10x10 grid: a master demand of 1.2 * base vehicles
+    (uniform O/D, departures U[0, 2 h)), n_scen scenarios taking the first
+    round(U[0.8, 1.2] * base) of them, 1 % of the edges cut to one lane in
+    each; 2 h at dt = 0.5 s."""
+    net = grid_network()
+    n_master = int(round(1.2 * base))
+    route_off, route_edges, _, _ = _od_routes(net, n_master, seed)
+    dep = np.floor(_rng(seed, _P_DEP).uniform(0.0, n_steps * 0.5, size=n_master) / 0.5).astype(np.int32)
+    alpha = _rng(seed, _P_ALPHA).uniform(0.05, 0.40, size=n_master).astype(np.float32)
+    master = Workload("grid10x10_master", net, route_off, route_edges, dep, np.zeros(n_master, np.uint8), alpha,
+                      base_params(1, seed), n_steps, info={"departures": "U[0, 2 h)"})
+    return master, ensemble_scenarios(n_scen, base, net.n_edges, seed)
+
+
 CONFIGS = {"grid10x10": config1, "perturbed_grid_ring": config2}
