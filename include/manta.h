@@ -77,7 +77,7 @@ typedef struct {
     float dt;                             /* (0, 1]; the paper uses 0.5 s */
     uint64_t seed;                        /* Philox key for the lane-change draws */
     int32_t intersection_mode;            /* 0 = all green (case 2); 1 = flashing red -> SIM_EUNSUPPORTED */
-    int32_t record_every;                 /* reserved for the adjoint; must be 0 */
+    int32_t record_every;                 /* >= 0; > 0: keep a checkpoint every record_every steps for sim_backward */
 } sim_idm_params;
 
 /* Per-vehicle state, all arrays [n_vehicles] indexed by vehicle id; any
@@ -151,6 +151,21 @@ typedef struct {
  * [0, master], or a reduced edge out of range. */
 sim_status sim_create_ensemble(const sim_network *net, const sim_routes *master, const sim_scenario *scen,
                                int32_t n_scen, const sim_idm_params *params, sim_handle **out);
+
+/* Gradient of a loss of the per-edge mean traversal times with respect to
+ * the class parameters, by the adjoint of the step with every discrete
+ * decision of the recorded forward run held fixed (leaders, lane changes,
+ * IDM branches, stops, clamps, admissions, arrivals).  Needs a handle created
+ * with record_every > 0 whose steps since step 0 all went through sim_step;
+ * the segments between checkpoints are re-run with a trace and swept in
+ * reverse (continuous parts of Eq. (1), the integration, the leader coupling
+ * and the crossing-time interpolation of Sec. IV-A's per-edge outputs).
+ * dL_dmean_tt: [n_edges] (edges without a completed traversal are ignored);
+ * dL_dparams: [5 * n_classes] out, per class (v0_factor, T, a, b, s0).
+ * The handle's state is left as it was.  Adjoint arithmetic is FP64 with
+ * atomic accumulation into leaders; parameter sums are reduced in a fixed
+ * order.  Errors: SIM_ESTATE (not recorded), SIM_EINVAL, SIM_ENOMEM. */
+sim_status sim_backward(sim_handle *h, const double *dL_dmean_tt, double *dL_dparams);
 
 /* veh_off[n_scen + 1]: vehicles of scenario k are [veh_off[k], veh_off[k+1]). */
 sim_status sim_ensemble_offsets(const sim_handle *h, int32_t *n_scen, int32_t *veh_off);

@@ -64,6 +64,10 @@ def _load(path):
     lib.orc_edge_stats.argtypes = [P, P, P]
     lib.orc_last_events.argtypes = [P] + [P] * 7
     lib.orc_real_bytes.restype = I32
+    lib.orc_enable_record.argtypes = [P]
+    lib.orc_enable_record.restype = I32
+    lib.orc_replay.argtypes = [P, P, P, P, P, P]
+    lib.orc_replay.restype = D
     lib.orc_philox4x64.argtypes = [P, P, P]
     lib.orc_expf_c_batch.argtypes = [P, P, I64]
     lib.orc_mand_trigger.argtypes = [U64, I64, I64, D]
@@ -164,6 +168,28 @@ class OracleSim:
         c = np.empty(self.n_edges, np.int64)
         self._lib.orc_edge_stats(self._h, _p(s), _p(c))
         return s, c
+
+    def enable_record(self) -> None:
+        """Record every discrete decision from step 0 on (differentiable form)."""
+        if self._lib.orc_enable_record(self._h) != 0:
+            raise RuntimeError("recording must start at step 0")
+
+    def theta(self, w) -> np.ndarray:
+        """Class parameters of a workload as [5 * n_classes] (v0_factor, T, a, b, s0)."""
+        p = w.params
+        return np.stack([p.v0_factor, p.T, p.a, p.b, p.s0], axis=1).astype(np.float64).ravel()
+
+    def replay(self, theta, target=None, use=None, grad: bool = False):
+        """FP64 replay of the recorded run with its decisions frozen, at the
+        class parameters theta.  Returns (loss, per-edge mean traversal time,
+        dL/dtheta or None)."""
+        th = np.ascontiguousarray(theta, np.float64)
+        tg = None if target is None else np.ascontiguousarray(target, np.float64)
+        us = None if use is None else np.ascontiguousarray(use, np.uint8)
+        mean = np.empty(self.n_edges, np.float64)
+        g = np.empty(th.size, np.float64) if grad else None
+        loss = self._lib.orc_replay(self._h, _p(th), _p(tg), _p(us), _p(mean), _p(g))
+        return loss, mean, g
 
     def last_events(self) -> dict:
         n = self.n

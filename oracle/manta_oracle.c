@@ -254,7 +254,25 @@ typedef struct orc_sim {
     uint64_t *best;     /* per global lane: smallest eligible key */
     /* last-step events */
     int *ev_leader, *ev_kind, *ev_flags;
+    int *ev_partner, *ev_bits;
+    /* record of discrete decisions for the differentiable form (optional) */
+    int recording;
+    struct orc_drec *rec;
+    int64_t n_rec, cap_rec;
+    int64_t *rec_off;          /* [steps + 1]: records of step t */
+    int *ins_step;             /* step at whose end a vehicle was admitted, -1 */
+    int rec_t0;                /* first recorded step */
 } orc_sim;
+
+/* one active vehicle in one step, with every discrete decision frozen */
+typedef struct orc_drec {
+    int32_t vid;
+    int32_t partner;           /* leader (VEH, clamp) or look-ahead rear (LOOK), -1 */
+    int16_t kind;
+    uint16_t bits;             /* RB_* */
+} orc_drec;
+enum { RB_F = 1, RB_D = 2, RB_S = 4, RB_B = 8, RB_C = 16, RB_W = 32, RB_EXIT = 64, RB_ARRIVE = 128,
+       RB_HELD = 256 };
 
 static int next_edge(const orc_sim *S, int i) {
     int64_t pos = S->roff[i] + S->k[i] + 1;
@@ -307,7 +325,7 @@ static void free_sim(orc_sim *S) {
                     S->T, S->a, S->b, S->s0, S->len, S->den, S->status, S->edge, S->k, S->lane,
                     S->mand, S->held, S->ww, S->x, S->v, S->tau_in, S->t_arr, S->tt_sum, S->tt_cnt,
                     S->nlane, S->xn, S->vn, S->tgt, S->elig, S->key, S->best, S->ev_leader,
-                    S->ev_kind, S->ev_flags};
+                    S->ev_kind, S->ev_flags, S->ev_partner, S->ev_bits, S->rec, S->rec_off, S->ins_step};
     for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
     if (S->lst) {
         for (int g = 0; g < S->n_lanes_total; g++) free(S->lst[g].a);
@@ -374,6 +392,8 @@ orc_sim *orc_create(int32_t n_nodes, int32_t n_edges, const int32_t *edge_from, 
     ALLOC(S->nlane, n_veh); ALLOC(S->xn, n_veh); ALLOC(S->vn, n_veh); ALLOC(S->tgt, n_veh);
     ALLOC(S->elig, n_veh); ALLOC(S->key, n_veh); ALLOC(S->best, S->n_lanes_total);
     ALLOC(S->ev_leader, n_veh); ALLOC(S->ev_kind, n_veh); ALLOC(S->ev_flags, n_veh);
+    ALLOC(S->ev_partner, n_veh); ALLOC(S->ev_bits, n_veh); ALLOC(S->ins_step, n_veh);
+    for (int i = 0; i < n_veh; i++) S->ins_step[i] = -1;
     S->lst = (ivec *)calloc((size_t)(S->n_lanes_total > 0 ? S->n_lanes_total : 1), sizeof(ivec));
     if (!S->lst) { free_sim(S); return NULL; }
     for (int i = 0; i < n_veh; i++) {
@@ -409,6 +429,7 @@ static void step_once(orc_sim *S) {
     int n_active = 0;
     for (int i = 0; i < n; i++) {
         S->ev_leader[i] = -1; S->ev_kind[i] = -1; S->ev_flags[i] = 0;
+        S->ev_partner[i] = -1; S->ev_bits[i] = 0;
         if (S->status[i] == ACTIVE) n_active++;
     }
     S->cnt[C_ACTIVE_SUM] += n_active;
@@ -541,8 +562,11 @@ static void step_once(orc_sim *S) {
         }
         S->ev_leader[i] = j;
         S->ev_kind[i] = kind;
+        S->ev_partner[i] = (kind == K_VEH) ? j : (kind == K_LOOK ? mrear[S->lane_base[f] + (S->nlane[i] < S->lanes[f] - 1 ? S->nlane[i] : S->lanes[f] - 1)] : -1);
         REAL v0 = S->v0f[c] * S->lim[e];
-        REAL acc = orc_idm(S->v[i], v0, vl, s, S->T[c], S->a[c], S->b[c], S->s0[c], S->den[c], kind, NULL);
+        int idm_fl = 0;
+        REAL acc = orc_idm(S->v[i], v0, vl, s, S->T[c], S->a[c], S->b[c], S->s0[c], S->den[c], kind, &idm_fl);
+        S->ev_bits[i] = idm_fl;
         /* A5: ballistic update with an exact stop */
         const REAL dt = S->dt;
         REAL vnew = S->v[i] + (acc * dt);
@@ -554,11 +578,12 @@ static void step_once(orc_sim *S) {
             vnew = RL(0);
             S->cnt[C_STOP_BRANCH]++;
             S->ev_flags[i] |= EV_STOPB;
+            S->ev_bits[i] |= RB_B;
         }
         /* A7: never past the leader's S_t rear */
         if (kind == K_VEH) {
             REAL rear = S->x[j] - S->len[S->cls[j]];
-            if (xnew > rear) { xnew = rear; S->cnt[C_CLAMP]++; S->ev_flags[i] |= EV_CLAMP; }
+            if (xnew > rear) { xnew = rear; S->cnt[C_CLAMP]++; S->ev_flags[i] |= EV_CLAMP; S->ev_bits[i] |= RB_C; }
         }
         /* A8/A19: a wrong-lane vehicle waits at the stop line */
         if (f >= 0 && !allowed_l && S->ww[i] < PATIENCE && xnew >= S->L[e]) {
@@ -568,6 +593,7 @@ static void step_once(orc_sim *S) {
             S->ww[i] += 1;
             S->cnt[C_WRONG_LANE_HOLDS]++;
             S->ev_flags[i] |= EV_WHOLD;
+            S->ev_bits[i] |= RB_W;
         }
         S->xn[i] = xnew;
         S->vn[i] = vnew;
@@ -688,12 +714,252 @@ static void step_once(orc_sim *S) {
             }
         }
     }
+    if (S->recording) {
+        for (int i = 0; i < n; i++) {
+            if (!(S->ev_kind[i] >= 0)) continue;     /* active at the start of the step */
+            int bits = S->ev_bits[i];
+            if (S->ev_flags[i] & EV_ARRIVE) bits |= RB_ARRIVE;
+            else if ((S->ev_flags[i] & EV_REQ) && (S->ev_flags[i] & EV_WIN)) bits |= RB_EXIT;
+            else if (S->ev_flags[i] & EV_REQ) bits |= RB_HELD;
+            if (S->n_rec == S->cap_rec) {
+                int64_t nc = S->cap_rec ? 2 * S->cap_rec : 4096;
+                orc_drec *nr = (orc_drec *)realloc(S->rec, (size_t)nc * sizeof(orc_drec));
+                if (!nr) { S->recording = 0; break; }
+                S->rec = nr;
+                S->cap_rec = nc;
+            }
+            orc_drec *r = &S->rec[S->n_rec++];
+            r->vid = i;
+            r->partner = S->ev_partner[i];
+            r->kind = (int16_t)S->ev_kind[i];
+            r->bits = (uint16_t)bits;
+        }
+        for (int i = 0; i < n; i++)
+            if ((S->ev_flags[i] & EV_INSERT_REQ) && (S->ev_flags[i] & EV_WIN)) S->ins_step[i] = t;
+        S->rec_off[t - S->rec_t0 + 1] = S->n_rec;
+    }
     S->t = t + 1;
 }
 
 int orc_step(orc_sim *S, int32_t n_steps) {
+    if (S->recording) {
+        int64_t *no = (int64_t *)realloc(S->rec_off, (size_t)(S->t + n_steps - S->rec_t0 + 1) * sizeof(int64_t));
+        if (!no) return -1;
+        S->rec_off = no;
+    }
     for (int q = 0; q < n_steps; q++) step_once(S);
     return 0;
+}
+
+/* ------------------------------------------------------------------ differentiable form
+ * With every discrete decision of a recorded forward run held fixed (leader
+ * or look-ahead partner, kind, IDM branches, stop, clamp, wrong-lane hold,
+ * admissions, arrivals), the trajectory is a smooth function of the class
+ * parameters theta = (v0_factor, T, a, b, s0) per class.  orc_replay
+ * recomputes it in FP64 and returns the loss
+ *     L = sum over used edges of (mean completed traversal time - target)^2
+ * (Sec. IV-A calibrates the IDM parameters against per-edge observations;
+ * here the observations are per-edge mean travel times).  With grad != NULL
+ * it also runs the reverse sweep (the adjoint of Eq. (1) and of the
+ * integration, the crossing-time interpolation and the leader coupling) and
+ * writes dL/dtheta.  Central differences of orc_replay pin the adjoint. */
+int32_t orc_enable_record(orc_sim *S) {
+    if (S->t != 0) return -1;
+    S->recording = 1;
+    S->rec_t0 = 0;
+    S->n_rec = 0;
+    free(S->rec_off);
+    S->rec_off = (int64_t *)calloc(1, sizeof(int64_t));
+    return S->rec_off ? 0 : -1;
+}
+
+/* IDM in FP64 on frozen branches, with its partial derivatives
+ * d[0..7] = d acc / d (v, vl, s, v0, T, a, b, s0) */
+static double idm64(double v, double v0, double vl, double s, double T, double a, double b, double s0, int kind,
+                    int bits, double d[8]) {
+    for (int k = 0; k < 8; k++) d[k] = 0.0;
+    const double r = v / v0;
+    double phi;
+    if (bits & RB_F) {
+        phi = -b;
+        d[6] = -1.0;
+    } else {
+        phi = a * (1.0 - r * r * r * r);
+        d[0] = -4.0 * a * r * r * r / v0;
+        d[3] = 4.0 * a * r * r * r * r / v0;
+        d[5] = 1.0 - r * r * r * r;
+    }
+    if (kind == K_FREE) return phi;
+    const double den = 2.0 * sqrt(a * b);
+    double dyn = 0.0, ddyn_dv = 0.0, ddyn_dvl = 0.0, ddyn_dT = 0.0, ddyn_dden = 0.0;
+    if (!(bits & RB_D)) {
+        dyn = v * T + v * (v - vl) / den;
+        ddyn_dv = T + (2.0 * v - vl) / den;
+        ddyn_dvl = -v / den;
+        ddyn_dT = v;
+        ddyn_dden = -v * (v - vl) / (den * den);
+    }
+    const double sst = s0 + dyn;
+    const double se = (bits & RB_S) ? S_MIN : s;
+    const double q = sst / se;
+    const double acc = phi - a * q * q;
+    const double dsst = -2.0 * a * q / se;
+    if (!(bits & RB_S)) d[2] = 2.0 * a * q * q / se;
+    d[0] += dsst * ddyn_dv;
+    d[1] = dsst * ddyn_dvl;
+    d[4] = dsst * ddyn_dT;
+    d[5] += -q * q + dsst * ddyn_dden * (den / (2.0 * a));
+    d[6] += dsst * ddyn_dden * (den / (2.0 * b));
+    d[7] = dsst;
+    return acc;
+}
+
+double orc_replay(orc_sim *S, const double *theta, const double *target, const uint8_t *use, double *mean_out,
+                  double *grad) {
+    if (!S->recording || S->rec_t0 != 0) return NAN;
+    const int n = S->n, E = S->n_edges, steps = S->t - S->rec_t0;
+    const double dt = (double)S->dt;
+    double *x = calloc((size_t)n + 1, sizeof(double)), *v = calloc((size_t)n + 1, sizeof(double));
+    double *tin = calloc((size_t)n + 1, sizeof(double));
+    int *cur = calloc((size_t)n + 1, sizeof(int));
+    double *sum = calloc((size_t)E, sizeof(double));
+    int64_t *cnt = calloc((size_t)E, sizeof(int64_t));
+    const int64_t NR = S->n_rec;
+    /* per record: x, v, xn, acc, partials[8], edge */
+    double *tx = calloc((size_t)NR + 1, sizeof(double)), *tv = calloc((size_t)NR + 1, sizeof(double));
+    double *txn = calloc((size_t)NR + 1, sizeof(double)), *tac = calloc((size_t)NR + 1, sizeof(double));
+    double *tpd = grad ? calloc((size_t)(NR + 1) * 8, sizeof(double)) : NULL;
+    int *ted = calloc((size_t)NR + 1, sizeof(int));
+    double *vn = calloc((size_t)NR + 1, sizeof(double));
+    if (!x || !v || !tin || !cur || !sum || !cnt || !tx || !tv || !txn || !tac || !ted || !vn || (grad && !tpd)) {
+        free(x); free(v); free(tin); free(cur); free(sum); free(cnt); free(tx); free(tv); free(txn); free(tac);
+        free(tpd); free(ted); free(vn);
+        return NAN;
+    }
+    for (int t = 0; t < steps; t++) {
+        const int64_t r0 = S->rec_off[t], r1 = S->rec_off[t + 1];
+        for (int64_t k = r0; k < r1; k++) {          /* all reads of S_t */
+            const orc_drec *R = &S->rec[k];
+            const int i = R->vid, c = S->cls[i];
+            const int e = S->redges[S->roff[i] + cur[i]];
+            const double L = (double)S->L[e];
+            double sgap = 0.0, vl = 0.0;
+            const int j = R->partner;
+            if (R->kind == K_VEH) { sgap = (x[j] - (double)S->len[S->cls[j]]) - x[i]; vl = v[j]; }
+            else if (R->kind == K_STOP) { sgap = L - x[i]; }
+            else if (R->kind == K_LOOK) { sgap = (L - x[i]) + (x[j] - (double)S->len[S->cls[j]]); vl = v[j]; }
+            const double *th = theta + 5 * c;
+            const double v0 = th[0] * (double)S->lim[e];
+            double pd[8];
+            const double acc = idm64(v[i], v0, vl, sgap, th[1], th[2], th[3], th[4], R->kind, R->bits, pd);
+            double xnew, vnew;
+            if (R->bits & RB_B) { xnew = x[i] - v[i] * v[i] / (2.0 * acc); vnew = 0.0; }
+            else { xnew = x[i] + v[i] * dt + 0.5 * acc * dt * dt; vnew = v[i] + acc * dt; }
+            if (R->bits & RB_C) xnew = x[j] - (double)S->len[S->cls[j]];
+            if (R->bits & RB_W) { xnew = L; vnew = 0.0; }
+            tx[k] = x[i]; tv[k] = v[i]; txn[k] = xnew; tac[k] = acc; ted[k] = e; vn[k] = vnew;
+            if (tpd) for (int q = 0; q < 8; q++) tpd[8 * k + q] = pd[q];
+        }
+        for (int64_t k = r0; k < r1; k++) {          /* commit */
+            const orc_drec *R = &S->rec[k];
+            const int i = R->vid, e = ted[k];
+            const double L = (double)S->L[e];
+            if (R->bits & (RB_EXIT | RB_ARRIVE)) {
+                const double phi = (txn[k] == tx[k]) ? 0.0 : (L - tx[k]) / (txn[k] - tx[k]);
+                const double tau = ((double)t + phi) * dt;
+                sum[e] += tau - tin[i];
+                cnt[e] += 1;
+                tin[i] = tau;
+                x[i] = txn[k] - L;
+                v[i] = vn[k];
+                cur[i] += 1;
+            } else if (R->bits & RB_HELD) {
+                x[i] = L;
+                v[i] = 0.0;
+            } else {
+                x[i] = txn[k];
+                v[i] = vn[k];
+            }
+        }
+        for (int i = 0; i < n; i++)
+            if (S->ins_step[i] == t) { x[i] = 0.0; v[i] = 0.0; cur[i] = 0; tin[i] = (double)(t + 1) * dt; }
+    }
+    double loss = 0.0;
+    double *w = calloc((size_t)E, sizeof(double));
+    for (int e = 0; e < E; e++) {
+        const double m = cnt[e] ? sum[e] / (double)cnt[e] : 0.0;
+        if (mean_out) mean_out[e] = m;
+        if (cnt[e] && (!use || use[e])) {
+            const double g = m - (target ? target[e] : 0.0);
+            loss += g * g;
+            if (w) w[e] = 2.0 * g / (double)cnt[e];
+        }
+    }
+    if (grad && w) {
+        for (int q = 0; q < 5 * S->nc; q++) grad[q] = 0.0;
+        double *lx = calloc((size_t)n + 1, sizeof(double)), *lv = calloc((size_t)n + 1, sizeof(double));
+        double *nx = calloc((size_t)n + 1, sizeof(double)), *nv = calloc((size_t)n + 1, sizeof(double));
+        double *lt = calloc((size_t)n + 1, sizeof(double));
+        int *cr = calloc((size_t)n + 1, sizeof(int));
+        if (lx && lv && nx && nv && lt && cr) {
+            for (int t = steps - 1; t >= 0; t--) {
+                for (int i = 0; i < n; i++)
+                    if (S->ins_step[i] == t) { lx[i] = 0.0; lv[i] = 0.0; lt[i] = 0.0; }
+                for (int i = 0; i < n; i++) { nx[i] = 0.0; nv[i] = 0.0; }
+                const int64_t r0 = S->rec_off[t], r1 = S->rec_off[t + 1];
+                for (int64_t k = r0; k < r1; k++) {
+                    const orc_drec *R = &S->rec[k];
+                    const int i = R->vid, c = S->cls[i], e = ted[k], j = R->partner;
+                    const double L = (double)S->L[e];
+                    double mx = lx[i], mv = lv[i];
+                    if (R->bits & (RB_HELD | RB_W)) { mx = 0.0; mv = 0.0; }
+                    if (R->bits & RB_ARRIVE) { mx = 0.0; mv = 0.0; }
+                    if (R->bits & (RB_EXIT | RB_ARRIVE)) {
+                        const double gt = w[e] + lt[i];
+                        if (txn[k] != tx[k]) {
+                            const double dd = txn[k] - tx[k];
+                            mx += gt * dt * (-(L - tx[k]) / (dd * dd));
+                            nx[i] += gt * dt * ((L - txn[k]) / (dd * dd));
+                        }
+                        lt[i] = -w[e];
+                    }
+                    if (R->bits & (RB_HELD | RB_W)) continue;
+                    double macc = 0.0;
+                    if (R->bits & RB_C) {
+                        nx[j] += mx;
+                        mx = 0.0;
+                    }
+                    if (R->bits & RB_B) {
+                        nx[i] += mx;
+                        nv[i] += mx * (-tv[k] / tac[k]);
+                        macc += mx * (tv[k] * tv[k] / (2.0 * tac[k] * tac[k]));
+                    } else {
+                        nx[i] += mx;
+                        nv[i] += mx * dt + mv;
+                        macc += mx * 0.5 * dt * dt + mv * dt;
+                    }
+                    const double *pd = tpd + 8 * k;
+                    nv[i] += macc * pd[0];
+                    if (R->kind == K_VEH) { nx[j] += macc * pd[2]; nx[i] -= macc * pd[2]; nv[j] += macc * pd[1]; }
+                    else if (R->kind == K_STOP) { nx[i] -= macc * pd[2]; }
+                    else if (R->kind == K_LOOK) { nx[i] -= macc * pd[2]; nx[j] += macc * pd[2]; nv[j] += macc * pd[1]; }
+                    grad[5 * c + 0] += macc * pd[3] * (double)S->lim[e];
+                    grad[5 * c + 1] += macc * pd[4];
+                    grad[5 * c + 2] += macc * pd[5];
+                    grad[5 * c + 3] += macc * pd[6];
+                    grad[5 * c + 4] += macc * pd[7];
+                }
+                for (int i = 0; i < n; i++) { lx[i] = nx[i]; lv[i] = nv[i]; }
+            }
+        } else {
+            loss = NAN;
+        }
+        free(lx); free(lv); free(nx); free(nv); free(lt); free(cr);
+    }
+    free(w);
+    free(x); free(v); free(tin); free(cur); free(sum); free(cnt); free(tx); free(tv); free(txn); free(tac);
+    free(tpd); free(ted); free(vn);
+    return loss;
 }
 
 int32_t orc_time(const orc_sim *S) { return S->t; }

@@ -96,6 +96,8 @@ _lib.sim_autotune.argtypes = [P, ctypes.c_char_p, I32]
 _lib.sim_autotune.restype = I32
 _lib.sim_get_schedule.argtypes = [P, P]
 _lib.sim_get_schedule.restype = I32
+_lib.sim_backward.argtypes = [P, P, P]
+_lib.sim_backward.restype = I32
 _lib.sim_probe_fp32.argtypes = [I32, P, P, P, I64]
 _lib.sim_probe_fp32.restype = I32
 _lib.sim_probe_philox.argtypes = [P, P, P, I64]
@@ -107,7 +109,7 @@ KERNELS = ["k_tile_step", "k_tile_big", "k_admit", "k_commit", "k_scatter"]
 
 EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
             "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",
-            "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_get_schedule",
+            "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_get_schedule", "sim_backward",
             "sim_probe_fp32", "sim_probe_philox", "sim_probe_draws"]
 
 
@@ -240,6 +242,19 @@ class Sim:
         if stream is not None:
             self.set_stream(stream)
 
+    def mean_travel_times(self):
+        """Per-edge mean completed traversal time (s) and traversal count."""
+        s, c = self.edge_stats()
+        return np.where(c > 0, s / np.maximum(c, 1), 0.0), c
+
+    def backward(self, dL_dmean: np.ndarray) -> np.ndarray:
+        """dL/d(class parameters) as [n_classes, 5] (v0_factor, T, a, b, s0)
+        for dL/d(per-edge mean traversal time) = dL_dmean (sim_backward)."""
+        g = _c(dL_dmean, np.float64)
+        out = np.zeros(5 * int(self._params.n_classes), np.float64)
+        _check(_lib.sim_backward(self._h, _p(g), _p(out)), self._h)
+        return out.reshape(-1, 5)
+
     def offsets(self) -> np.ndarray:
         """Vehicle-id range of every scenario: [n_scen + 1]."""
         out = np.zeros(self.n_scen + 1, np.int32)
@@ -347,3 +362,52 @@ def probe_draws(seed: int, t: np.ndarray, vid: np.ndarray):
     e3 = np.empty(t.size, np.float32)
     _check(_lib.sim_probe_draws(int(seed), _p(t), _p(vid), _p(u), _p(e2), _p(e3), int(t.size)))
     return u, e2, e3
+
+
+# ---------------------------------------------------------------- autograd
+def with_class_params(w, theta):
+    """Shallow copy of a workload whose class parameters are theta [n_classes, 5]
+    = (v0_factor, T, a, b, s0) (rounded to binary32 like every input)."""
+    import copy
+    th = np.asarray(theta, np.float64).reshape(-1, 5)
+    w2 = copy.copy(w)
+    p = copy.copy(w.params)
+    p.v0_factor, p.T, p.a, p.b, p.s0 = [th[:, k].astype(np.float32) for k in range(5)]
+    w2.params = p
+    return w2
+
+
+def _edge_tt_function():
+    import torch
+
+    class EdgeMeanTravelTime(torch.autograd.Function):
+        """theta [n_classes, 5] -> per-edge mean traversal times [n_edges]
+        after `steps` steps; the backward runs sim_backward (adjoint with the
+        forward's discrete decisions held fixed, checkpoint every
+        record_every steps)."""
+
+        @staticmethod
+        def forward(ctx, theta, workload, steps, record_every=120, stream=None):
+            w = with_class_params(workload, theta.detach().cpu().numpy())
+            w.params.record_every = int(record_every)
+            sim = Sim(w, stream=stream)
+            sim.step(int(steps))
+            mean, cnt = sim.mean_travel_times()
+            ctx.sim = sim
+            ctx.shape = theta.shape
+            ctx.dtype = theta.dtype
+            out = torch.from_numpy(mean)
+            return out
+
+        @staticmethod
+        def backward(ctx, grad_mean):
+            g = ctx.sim.backward(grad_mean.detach().cpu().numpy())
+            ctx.sim.close()
+            return torch.from_numpy(g).reshape(ctx.shape).to(ctx.dtype), None, None, None, None
+
+    return EdgeMeanTravelTime
+
+
+def edge_mean_travel_time(theta, workload, steps, record_every=120, stream=None):
+    """Differentiable per-edge mean traversal times (torch.autograd)."""
+    return _edge_tt_function().apply(theta, workload, steps, record_every, stream)

@@ -80,6 +80,12 @@ struct sim_handle {
     int g_big_max = 1, g_scatter_max = 1;
     int n_scen = 1;
     std::vector<int32_t> veh_off;   // ensemble: vehicles of scenario k
+    // differentiable form: a snapshot of the dynamic state every rec_every steps
+    int rec_every = 0;
+    bool rec_broken = false;
+    std::vector<void*> snaps;
+    size_t snap_bytes = 0;
+    int nq = 0;
     // host copies of the static inputs needed for state I/O
     std::vector<int64_t> roff;
     std::vector<int32_t> redges, dep, lanes, lane_base, conn_off, conn_to, ins_lane;
@@ -107,6 +113,8 @@ struct sim_handle {
         graph = nullptr;
         for (void* p : bufs) al.put(p);
         bufs.clear();
+        for (void* p : snaps) al.put(p);
+        snaps.clear();
     }
     uint32_t mask_of(int e, int f) const {
         if (f < 0) return 0xFFu;
@@ -163,7 +171,7 @@ void validate(const sim_network* net, const sim_routes* r, const sim_idm_params*
     if (!(std::isfinite(p->dt) && p->dt > 0.0f && p->dt <= 1.0f)) bad("dt outside (0, 1]");
     if (p->intersection_mode != 0)
         throw Fail{SIM_EUNSUPPORTED, "intersection_mode 1 (flashing red) is not implemented"};
-    if (p->record_every != 0) throw Fail{SIM_EUNSUPPORTED, "record_every is reserved and must be 0"};
+    if (p->record_every < 0) bad("record_every must be >= 0");
     // a vehicle entering an edge must land behind everything on it: the
     // overshoot of one step stays below the shortest edge minus a length
     float vmax = 0, amax = 0, lmax = 0, lmin = 1e30f, limmax = 0;
@@ -221,6 +229,61 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     hipExtLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, ev[4], ev[5], 0, d);
     hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[6], ev[7], 0, d);
     hipExtLaunchKernelGGL(k_scatter, dim3(h->g_scatter), b, 0, s, ev[8], ev[9], 0, d);
+}
+
+// The dynamic state at a step boundary, as (device pointer, bytes) pieces.
+template <class F>
+void for_each_state_piece(sim_handle* h, F&& f) {
+    Dev& d = h->d;
+    const size_t N = (size_t)std::max(h->n_veh, 1), E = (size_t)h->n_edges, NL = (size_t)h->n_lanes;
+    for (int b = 0; b < 2; ++b) {
+        f((void*)d.s[b].x, 4 * N);
+        f((void*)d.s[b].v, 4 * N);
+        f((void*)d.s[b].vid, 4 * N);
+        f((void*)d.s[b].edge, 4 * N);
+        f((void*)d.s[b].meta, 4 * N);
+        f((void*)d.s[b].nxt, 4 * N);
+    }
+    f((void*)d.status, N);
+    f((void*)d.cursor, 4 * N);
+    f((void*)d.held_since, 4 * N);
+    f((void*)d.tau_in, 8 * N);
+    f((void*)d.t_arr, 8 * N);
+    f((void*)d.fin_x, 4 * N);
+    f((void*)d.fin_v, 4 * N);
+    f((void*)d.fin_meta, 4 * N);
+    f((void*)d.rear, sizeof(LaneRear) * NL);
+    f((void*)d.qhead, 4 * ((size_t)h->nq + 1));
+    f((void*)d.cnt, 4 * E);
+    f((void*)d.tt_sum, 8 * E);
+    f((void*)d.tt_cnt, 8 * E);
+    f((void*)d.ctl, sizeof(Ctl));
+    f((void*)d.counters, sizeof(unsigned long long) * cNumCounters * kCounterCopies);
+}
+
+size_t state_bytes(sim_handle* h) {
+    size_t tot = 0;
+    for_each_state_piece(h, [&](void*, size_t b) { tot += (b + 255) & ~(size_t)255; });
+    return tot;
+}
+
+void save_state(sim_handle* h, void* dst) {
+    size_t o = 0;
+    for_each_state_piece(h, [&](void* p, size_t b) {
+        HIP_OK(hipMemcpyAsync((char*)dst + o, p, b, hipMemcpyDeviceToDevice, h->stream));
+        o += (b + 255) & ~(size_t)255;
+    });
+}
+
+void load_state(sim_handle* h, const void* src, int t) {
+    size_t o = 0;
+    for_each_state_piece(h, [&](void* p, size_t b) {
+        HIP_OK(hipMemcpyAsync(p, (const char*)src + o, b, hipMemcpyDeviceToDevice, h->stream));
+        o += (b + 255) & ~(size_t)255;
+    });
+    // first-request stamps only ever grow: reset them for a re-run
+    HIP_OK(hipMemsetAsync(h->d.req_stamp, 0xFF, sizeof(int) * h->n_edges, h->stream));
+    h->t = t;
 }
 
 void capture_graph(sim_handle* h) {
@@ -413,6 +476,8 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.eq_off = h->upload(eq_off.data(), E + 1);
             d.ins_edges = h->upload(ins_edges.data(), ins_edges.size());
             d.n_ins_edges = (int)ins_edges.size();
+            h->nq = NQ;
+            h->rec_every = p->record_every;
             std::vector<uint32_t> rid(N);
             for (int i = 0; i < N; ++i) rid[i] = rng_id ? rng_id[i] : (uint32_t)i;
             d.rid = h->upload(rid.data(), N);
@@ -521,9 +586,19 @@ sim_status sim_step(sim_handle* h, int32_t n) {
         return SIM_EINVAL;
     }
     return guarded(h, [&] {
-        for (int q = 0; q < n; ++q) HIP_OK(hipGraphLaunch(h->exec, h->stream));
+        for (int q = 0; q < n; ++q) {
+            if (h->rec_every > 0 && !h->rec_broken && h->t % h->rec_every == 0 &&
+                (size_t)(h->t / h->rec_every) == h->snaps.size()) {
+                if (!h->snap_bytes) h->snap_bytes = state_bytes(h);
+                void* p = h->al.get(h->snap_bytes);
+                if (!p) throw Fail{SIM_ENOMEM, "no device memory for a checkpoint"};
+                h->snaps.push_back(p);
+                save_state(h, p);
+            }
+            HIP_OK(hipGraphLaunch(h->exec, h->stream));
+            h->t += 1;
+        }
         HIP_OK(hipGetLastError());
-        h->t += n;
     });
 }
 
@@ -541,6 +616,7 @@ sim_status sim_step_timed(sim_handle* h, int32_t n, double* kernel_ms, double* t
         for (int q = 0; q < n; ++q) launch_step(h, h->stream, &ev[(size_t)q * per]);
         HIP_OK(hipGetLastError());
         h->t += n;
+        if (h->rec_every > 0 && n > 0) h->rec_broken = true;   // timed steps take no checkpoints
         double ks[SIM_N_KERNELS] = {0};
         if (n > 0) {
             HIP_OK(hipEventSynchronize(ev.back()));
@@ -707,7 +783,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         std::vector<uint32_t> svid(na), smeta(na);
         std::vector<int32_t> sedge(na), snxt(na), cnt(h->n_edges, 0);
         std::vector<LaneRear> rear(h->n_lanes);
-        for (auto& r : rear) r = LaneRear{0.f, 0.f, -1, 0};
+        for (auto& r : rear) r = LaneRear{0.f, 0.f, -1, 0u};
         for (int k = 0; k < na; ++k) {
             const int i = act[k].id, e = act[k].edge;
             const int64_t pos = h->roff[i] + in->cursor[i] + 1;
@@ -721,7 +797,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
                               h->mask_of(e, nx));
             cnt[e]++;
             const bool last = (k + 1 == na) || act[k + 1].edge != e || act[k + 1].lane != act[k].lane;
-            if (last) rear[h->lane_base[e] + act[k].lane] = LaneRear{in->x[i] - h->len_c[h->cls[i]], in->v[i], t, 0};
+            if (last) rear[h->lane_base[e] + act[k].lane] = LaneRear{in->x[i] - h->len_c[h->cls[i]], in->v[i], t, (uint32_t)i};
         }
         // departure queues: the vehicles that have left a queue must be a prefix of it
         std::vector<int> qhead(h->qoff.begin(), h->qoff.end());
@@ -788,6 +864,9 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         }
         HIP_OK(hipDeviceSynchronize());
         h->t = t;
+        for (void* p : h->snaps) h->al.put(p);
+        h->snaps.clear();
+        h->rec_broken = (t != 0);
     });
 }
 
@@ -809,6 +888,91 @@ sim_status sim_destroy(sim_handle* h) {
 }
 
 const char* sim_last_error(const sim_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+// ---- differentiable form ----------------------------------------------------
+sim_status sim_backward(sim_handle* h, const double* dL_dmean_tt, double* dL_dparams) {
+    if (!h || !dL_dmean_tt || !dL_dparams) return SIM_EINVAL;
+    if (h->rec_every <= 0) {
+        h->err = "the handle was created with record_every = 0";
+        return SIM_ESTATE;
+    }
+    if (h->rec_broken) {
+        h->err = "the forward run was not recorded from step 0 (state written or timed steps)";
+        return SIM_ESTATE;
+    }
+    std::vector<void*> tmp;
+    auto get = [&](size_t bytes) {
+        void* p = h->al.get(bytes);
+        if (!p) throw Fail{SIM_ENOMEM, "no device memory for the reverse sweep"};
+        tmp.push_back(p);
+        return p;
+    };
+    const Dev saved = h->d;
+    const int T = h->t;
+    sim_status st = guarded(h, [&] {
+        const int N = std::max(h->n_veh, 1), E = h->n_edges, R = h->rec_every, NC = h->n_classes;
+        const int np = 5 * NC;
+        HIP_OK(hipStreamSynchronize(h->stream));
+        std::vector<unsigned long long> cnt(E);
+        HIP_OK(hipMemcpy(cnt.data(), h->d.tt_cnt, 8 * (size_t)E, hipMemcpyDeviceToHost));
+        std::vector<double> w(E, 0.0);
+        for (int e = 0; e < E; ++e) {
+            if (!std::isfinite(dL_dmean_tt[e])) throw Fail{SIM_EINVAL, fmt("dL_dmean_tt[%d] is not finite", e)};
+            if (cnt[e]) w[e] = dL_dmean_tt[e] / (double)cnt[e];
+        }
+        const int gbw = std::max(1, std::min(256, (N + kNT - 1) / kNT));
+        double* dw = (double*)get(8 * (size_t)E);
+        HIP_OK(hipMemcpy(dw, w.data(), 8 * (size_t)E, hipMemcpyHostToDevice));
+        double* lam[5];
+        for (auto& q : lam) {
+            q = (double*)get(8 * (size_t)N);
+            HIP_OK(hipMemsetAsync(q, 0, 8 * (size_t)N, h->stream));
+        }
+        double *lx = lam[0], *lv = lam[1], *nx = lam[2], *nv = lam[3], *lt = lam[4];
+        double* gpart = (double*)get(8 * (size_t)gbw * np);
+        HIP_OK(hipMemsetAsync(gpart, 0, 8 * (size_t)gbw * np, h->stream));
+        TraceRec* trace = (TraceRec*)get(sizeof(TraceRec) * (size_t)R * N);
+        int* nact = (int*)get(4 * (size_t)R);
+        void* end_state = get(h->snap_bytes ? h->snap_bytes : (h->snap_bytes = state_bytes(h)));
+        save_state(h, end_state);
+        const int nseg = (T + R - 1) / R;
+        if ((int)h->snaps.size() < nseg) throw Fail{SIM_ESTATE, "missing checkpoints"};
+        for (int sg = nseg - 1; sg >= 0; --sg) {
+            const int t0 = sg * R, t1 = std::min(T, t0 + R);
+            load_state(h, h->snaps[sg], t0);
+            h->d.trace = trace;
+            h->d.trace_t0 = t0;
+            h->d.trace_stride = N;
+            h->d.nact_hist = nact;
+            for (int t = t0; t < t1; ++t) launch_step(h, h->stream);
+            h->d = saved;
+            for (int t = t1 - 1; t >= t0; --t) {
+                HIP_OK(hipMemsetAsync(nx, 0, 8 * (size_t)N, h->stream));
+                HIP_OK(hipMemsetAsync(nv, 0, 8 * (size_t)N, h->stream));
+                hipLaunchKernelGGL(k_backward, dim3(gbw), dim3(kNT), 0, h->stream, h->d,
+                                   trace + (size_t)(t - t0) * N, nact + (t - t0), t, NC, lx, lv, nx, nv, lt, dw,
+                                   gpart);
+                std::swap(lx, nx);
+                std::swap(lv, nv);
+            }
+        }
+        HIP_OK(hipGetLastError());
+        load_state(h, end_state, T);
+        std::vector<double> gp((size_t)gbw * np);
+        HIP_OK(hipMemcpyAsync(gp.data(), gpart, 8 * gp.size(), hipMemcpyDeviceToHost, h->stream));
+        HIP_OK(hipStreamSynchronize(h->stream));
+        for (int k = 0; k < np; ++k) {
+            double acc = 0.0;
+            for (int b = 0; b < gbw; ++b) acc += gp[(size_t)b * np + k];
+            dL_dparams[k] = acc;
+        }
+    });
+    h->d = saved;
+    h->t = T;
+    (void)hipStreamSynchronize(h->stream);
+    for (void* p : tmp) h->al.put(p);
+    return st;
+}
 
 // ---- ensembles -----------------------------------------------------------
 sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, const sim_scenario* sc, int32_t ns,

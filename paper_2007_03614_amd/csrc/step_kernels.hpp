@@ -88,8 +88,23 @@ struct LaneRear {     // rear of a lane at the start of step `stamp`
     float xm;         // x - length of the rear vehicle
     float v;
     int stamp;
-    int pad;
+    uint32_t vid;     // the rear vehicle
 };
+
+// One vehicle in one step of a traced re-run (differentiable form): every
+// discrete decision of the step, and the continuous inputs of Eq. (1).
+struct TraceRec {
+    uint32_t vid;
+    int partner;      // leader (VEH, clamp) or look-ahead rear (LOOK), -1
+    float x, v;       // start of the step
+    float s, vl;      // gap and leader speed of Eq. (1)
+    float xn;         // position after Phase 2
+    int edge;
+    uint32_t kb;      // kind | branch bits << 8 (TB_*)
+    float pad;
+};
+enum : uint32_t { TB_F = 1, TB_D = 2, TB_S = 4, TB_B = 8, TB_C = 16, TB_W = 32, TB_EXIT = 64, TB_ARRIVE = 128,
+                  TB_HELD = 256 };
 
 struct LanePost {     // post-lane-change run of a lane in step `stamp`
     int stamp;
@@ -191,6 +206,11 @@ struct Dev {
     // edges beyond the LDS of a workgroup
     int* big_list;
     int tile_window;
+    // traced re-run: record of step t at trace[(t - trace_t0) * trace_stride + slot]
+    TraceRec* trace;
+    int trace_t0;
+    int trace_stride;
+    int* nact_hist;
     char* big;
     int big_cap;                // vehicles per workgroup region
 };
@@ -606,9 +626,11 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const ClassParams cpi = d.cp[m_cls(m)];
         const bool allowed_l = lane_allowed(m, f, lam);
         int kind;
+        int partner = -1;
         float s = 0.0f, vl = 0.0f, rear_j = 0.0f;
         if (j >= 0) {
             kind = kVeh;
+            partner = (int)b.vid[j];
             rear_j = b.x[j] - d.cp[m_cls(b.meta[j])].len;
             s = rear_j - xi;
             vl = b.v[j];
@@ -625,6 +647,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 kind = kLook;
                 s = (d.L[e] - xi) + r.xm;
                 vl = r.v;
+                partner = (int)r.vid;
             } else {
                 kind = kFree;
             }
@@ -635,17 +658,20 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const float dt = d.dt;
         float vnew = vi + (a * dt);
         float xnew;
+        uint32_t tb = br;
         if (vnew >= 0.0f) {
             xnew = (xi + (vi * dt)) + ((0.5f * a) * (dt * dt));
         } else {
             xnew = xi - ((vi * vi) / (2.0f * a));
             vnew = 0.0f;
             acc.c[cStopBranch]++;
+            tb |= TB_B;
         }
         uint32_t fl = 0;
         if (kind == kVeh && xnew > rear_j) {
             xnew = rear_j;
             acc.c[cClamp]++;
+            tb |= TB_C;
         }
         if (f >= 0 && !allowed_l && m_ww(m) < kPatience && xnew >= d.L[e]) {
             xnew = d.L[e];
@@ -654,6 +680,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             m = (m & ~(127u << 8)) | ((uint32_t)(m_ww(m) + 1) << 8);
             fl |= F_WHOLD;
             acc.c[cWrongLaneHolds]++;
+            tb |= TB_W;
         }
         m = m_set_lane(m, lam);
         // write the post-step record in the post-change order.  newpos stays
@@ -668,6 +695,20 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         S.nxt[dst] = f;
         b.xn[q] = xnew;
         b.fl[q] = fl;
+        if (d.trace) {
+            TraceRec tr;
+            tr.vid = id;
+            tr.partner = partner;
+            tr.x = xi;
+            tr.v = vi;
+            tr.s = s;
+            tr.vl = vl;
+            tr.xn = xnew;
+            tr.edge = e;
+            tr.kb = (uint32_t)kind | (tb << 8);
+            tr.pad = 0.0f;
+            d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + dst] = tr;
+        }
         b.pel[newpos] = elam;
         b.inv[newpos] = q;
     }
@@ -746,6 +787,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         d.ctl->n_req[par ^ 1] = 0;
         d.ctl->n_ent[par ^ 1] = 0;
         d.ctl->n_big[par ^ 1] = 0;
+        if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
     const int W = d.tile_window;
@@ -901,6 +943,11 @@ __device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, C
         const Outbox ob = d.outbox[base + l];
         if (ob.stamp != t) continue;
         const uint32_t m = S.meta[ob.slot];
+        if (d.trace) {
+            const bool w2 = ob.target >= 0 && transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
+            d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + ob.slot].kb |=
+                (ob.target < 0 ? TB_ARRIVE : (w2 ? TB_EXIT : TB_HELD)) << 8;
+        }
         if (ob.target < 0) {                       // arrival at the route end
             d.status[ob.vid] = kArrived;
             d.fin_x[ob.vid] = S.x[ob.slot];
@@ -1155,9 +1202,141 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             lr.xm = x - d.cp[m_cls(meta)].len;
             lr.v = v;
             lr.stamp = t + 1;
-            lr.pad = 0;
+            lr.vid = vid;
             d.rear[gl] = lr;
         }
+    }
+}
+
+// ---- differentiable form: reverse sweep of one step ----------------------
+// With the step's discrete decisions frozen (trace records), the state at
+// t + 1 is a smooth function of the state at t and of the class parameters.
+// lx, lv: adjoints of (x, v) at t + 1 by vehicle id; nx, nv (zeroed): at t.
+// lt: adjoint of each vehicle's current edge-entry time.  w: dL/d(edge mean
+// travel time) / (traversals of the edge).  Parameter gradients of the
+// workgroup's records are reduced in a fixed tree and added to its own slot
+// gpart[blockIdx][5 * classes] (one workgroup per slot, kernels in order).
+constexpr int kParamMax = 5 * 16;
+
+__device__ inline double idm_partials(double v, double v0, double vl, double s, const ClassParams& p, int kind,
+                                      uint32_t bits, double d[8]) {
+    for (int k = 0; k < 8; ++k) d[k] = 0.0;   // d acc / d (v, vl, s, v0, T, a, b, s0)
+    const double a = p.a, b = p.b, T = p.T, s0 = p.s0;
+    const double r = v / v0, r2 = r * r;
+    double phi;
+    if (bits & TB_F) {
+        phi = -b;
+        d[6] = -1.0;
+    } else {
+        phi = a * (1.0 - r2 * r2);
+        d[0] = -4.0 * a * r2 * r / v0;
+        d[3] = 4.0 * a * r2 * r2 / v0;
+        d[5] = 1.0 - r2 * r2;
+    }
+    if (kind == kFree) return phi;
+    const double den = 2.0 * sqrt(a * b);
+    double dyn = 0.0, dyv = 0.0, dyvl = 0.0, dyT = 0.0, dyden = 0.0;
+    if (!(bits & TB_D)) {
+        dyn = v * T + v * (v - vl) / den;
+        dyv = T + (2.0 * v - vl) / den;
+        dyvl = -v / den;
+        dyT = v;
+        dyden = -v * (v - vl) / (den * den);
+    }
+    const double sst = s0 + dyn;
+    const double se = (bits & TB_S) ? (double)kSMin : s;
+    const double q = sst / se;
+    const double dsst = -2.0 * a * q / se;
+    if (!(bits & TB_S)) d[2] = 2.0 * a * q * q / se;
+    d[0] += dsst * dyv;
+    d[1] = dsst * dyvl;
+    d[4] = dsst * dyT;
+    d[5] += -q * q + dsst * dyden * (den / (2.0 * a));
+    d[6] += dsst * dyden * (den / (2.0 * b));
+    d[7] = dsst;
+    return phi - a * q * q;
+}
+
+__global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, const int* n_ptr, int t, int n_classes,
+                                                 const double* lx, const double* lv, double* nx, double* nv,
+                                                 double* lt, const double* w, double* gpart) {
+    __shared__ double red[kNT];
+    double g[kParamMax];
+    const int np = 5 * n_classes;
+    for (int k = 0; k < np; ++k) g[k] = 0.0;
+    const double dt = (double)d.dt;
+    const int n = *n_ptr;
+    for (int r = blockIdx.x * kNT + threadIdx.x; r < n; r += gridDim.x * kNT) {
+        const TraceRec R = rec[r];
+        const uint32_t bits = R.kb >> 8;
+        const int kind = (int)(R.kb & 255u);
+        const int i = (int)R.vid, e = R.edge, j = R.partner;
+        const double L = (double)d.L[e];
+        const double x = R.x, v = R.v, xn = R.xn;
+        double mx = lx[i], mv = lv[i];
+        if (bits & (TB_HELD | TB_W | TB_ARRIVE)) {
+            mx = 0.0;
+            mv = 0.0;
+        }
+        if (bits & (TB_EXIT | TB_ARRIVE)) {       // crossing time (t + phi) dt, phi = (L - x) / (xn - x)
+            const double gt = w[e] + lt[i];
+            if (xn != x) {
+                const double dd = xn - x;
+                mx += gt * dt * (-(L - x) / (dd * dd));
+                atomicAdd(&nx[i], gt * dt * ((L - xn) / (dd * dd)));
+            }
+            lt[i] = -w[e];
+        }
+        if (bits & (TB_HELD | TB_W)) continue;
+        const int c = d.cls[i];
+        const ClassParams cp = d.cp[c];
+        const double lim = (double)d.lim[e];
+        const double v0 = (double)cp.v0f * lim;
+        double pd[8];
+        const double acc = idm_partials(v, v0, (double)R.vl, (double)R.s, cp, kind, bits, pd);
+        double macc = 0.0, ax = 0.0, av = 0.0;
+        if (bits & TB_C) {                         // clamped to the leader's rear
+            atomicAdd(&nx[j], mx);
+            mx = 0.0;
+        }
+        if (bits & TB_B) {                         // exact stop
+            ax += mx;
+            av += mx * (-v / acc);
+            macc += mx * (v * v / (2.0 * acc * acc));
+        } else {
+            ax += mx;
+            av += mx * dt + mv;
+            macc += mx * 0.5 * dt * dt + mv * dt;
+        }
+        av += macc * pd[0];
+        if (kind == kVeh) {
+            ax -= macc * pd[2];
+            atomicAdd(&nx[j], macc * pd[2]);
+            atomicAdd(&nv[j], macc * pd[1]);
+        } else if (kind == kStop) {
+            ax -= macc * pd[2];
+        } else if (kind == kLook) {
+            ax -= macc * pd[2];
+            atomicAdd(&nx[j], macc * pd[2]);
+            atomicAdd(&nv[j], macc * pd[1]);
+        }
+        atomicAdd(&nx[i], ax);
+        atomicAdd(&nv[i], av);
+        g[5 * c + 0] += macc * pd[3] * lim;
+        g[5 * c + 1] += macc * pd[4];
+        g[5 * c + 2] += macc * pd[5];
+        g[5 * c + 3] += macc * pd[6];
+        g[5 * c + 4] += macc * pd[7];
+    }
+    for (int k = 0; k < np; ++k) {                 // fixed-order tree per parameter
+        red[threadIdx.x] = g[k];
+        __syncthreads();
+        for (int h = kNT / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) red[threadIdx.x] += red[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) gpart[(size_t)blockIdx.x * np + k] += red[0];
+        __syncthreads();
     }
 }
 

@@ -107,8 +107,8 @@ def test_unsupported_modes(M, base):
     w.params.intersection_mode = 1
     _expect(M, w, "SIM_EUNSUPPORTED")
     w = copy.deepcopy(base)
-    w.params.record_every = 120
-    _expect(M, w, "SIM_EUNSUPPORTED")
+    w.params.record_every = -1
+    _expect(M, w, "SIM_EINVAL")
 
 
 def test_step_reach_bound(M, base):
