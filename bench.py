@@ -20,6 +20,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -125,13 +127,61 @@ def bench_ensemble(args, M, torch, stream):
     }
 
 
+def bench_calibration(args, M, torch, stream):
+    """Differentiable form on the 10x10 grid at 1 h (7,200 steps), 4 classes:
+    loss = sum over edges of (mean traversal time - target)^2, targets from a
+    run at hidden parameters theta* = base * (1 + U[-0.1, 0.1]); gradient with
+    respect to the 20 class parameters at theta0 = base, checkpoint every 120
+    steps.  Reports sim_backward wall time (segment re-runs included) over the
+    recording forward's wall time."""
+    import workloads as W
+    steps = args.steps if args.steps_given else 7200
+    w = W.config1(n_classes=4, n_steps=steps)
+    hidden = W.jitter_params(w.params, 0.1, seed=5)
+    tw = M.with_class_params(w, np.stack([hidden.v0_factor, hidden.T, hidden.a, hidden.b, hidden.s0], 1))
+    ref = M.Sim(tw, stream=stream)
+    ref.step(steps)
+    target, tcnt = ref.mean_travel_times()
+    ref.close()
+    w.params.record_every = 120
+    res = []
+    for rep in range(1 + args.reps):
+        sim = M.Sim(w, stream=stream)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sim.step(steps)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        mean, cnt = sim.mean_travel_times()
+        use = (cnt > 0) & (tcnt > 0)
+        dl = np.where(use, 2.0 * (mean - target), 0.0)
+        t2 = time.perf_counter()
+        g = sim.backward(dl)
+        t3 = time.perf_counter()
+        sim.close()
+        if rep > 0 or args.reps == 0:
+            res.append((t1 - t0, t3 - t2, float(np.sum(np.where(use, (mean - target) ** 2, 0.0))), g))
+    fwd = min(r[0] for r in res)
+    bwd = min(r[1] for r in res)
+    return {
+        "metric": "backward/forward time ratio", "value": bwd / fwd, "unit": "ratio", "n_gpus": 1,
+        "steps": steps, "warmup": 1 if args.reps else 0, "ms_per_step": 1e3 * fwd / steps,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32 state, f64 adjoint",
+        "data": "synthetic",
+        "config": {"workload": "calibration_grid10x10_4classes", "vehicles": w.n_vehicles, "params": 20,
+                   "record_every": 120, "forward_s": fwd, "backward_s": bwd, "loss": res[-1][2],
+                   "grad_norm": float(np.linalg.norm(res[-1][3]))},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=21600)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="perturbed_grid_ring",
-                    choices=["perturbed_grid_ring", "grid10x10", "ensemble"])
+                    choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration"])
+    ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
     ap.add_argument("--cpu-steps", type=int, default=3600, help="oracle sample length (0: skip)")
@@ -157,6 +207,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.workload == "ensemble":
         print(json.dumps(bench_ensemble(args, M, torch, stream)), flush=True)
+        return
+    if args.workload == "calibration":
+        print(json.dumps(bench_calibration(args, M, torch, stream)), flush=True)
         return
     w = make_workload(args.workload)
     if args.copy_probe > 0:
