@@ -213,10 +213,12 @@ def main():
         return
     w = make_workload(args.workload)
     if args.copy_probe > 0:
+        # a plain streaming kernel of known size: reads MIB MiB, writes MIB MiB
+        # (torch's elementwise add; a device-to-device copy_ would use the DMA engine)
         src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
-        dst.copy_(src)
+        torch.add(src, 0.5, out=dst)
         torch.cuda.synchronize()
         del src, dst
 

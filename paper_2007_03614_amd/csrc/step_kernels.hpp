@@ -31,7 +31,7 @@ constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parame
 constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
 constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
-constexpr int kBigCapLds = 2304;         // vehicles per big tile piece staged in LDS (144 KiB)
+constexpr int kBigCapLds = 1792;         // vehicles per big tile piece staged in LDS (147 KiB)
 constexpr int kCounterCopies = 32;       // each counter is spread over 32 slots (fewer colliding atomics)
 
 // ---- vehicle meta word ---------------------------------------------------
@@ -121,6 +121,8 @@ struct Outbox {       // end-of-edge request of a lane's front vehicle
     float xp;         // position on the next edge
     float phi;        // fraction of the step at which the stop line was crossed
     uint64_t key;     // admission priority (smaller first)
+    int elig;         // set by k_admit: the request passed the no-overlap test
+    int pad;
 };
 
 struct EntryRec {
@@ -160,6 +162,8 @@ struct Dev {
     const int* qveh;            // vehicle ids, queue by queue
     const int* qoff;            // [n_queues + 1]
     int* qhead;                 // next vehicle of each queue
+    const int* qlane;           // global entry lane of each queue
+    unsigned long long* qkey;   // set by k_admit: key of the queue's due, eligible head, else ~0
     const int* eq_off;          // [n_edges + 1]: queues of edge e
     const int* ins_edges;       // edges that have a queue
     int n_ins_edges;
@@ -233,9 +237,16 @@ struct TileBuf {
     uint32_t* fl;       // Phase 2 flags
     uint32_t* pel;      // post-change (edge, lane), permuted to the new order
     int* inv;           // new order -> q
+    // per-vehicle copies of its edge's constants, loaded with the vehicle so
+    // that later phases find them in LDS
+    float* L;           // edge length
+    float* lim;         // edge speed limit
+    uint32_t* lanes2;   // lanes of the edge | lanes of the next edge << 8
+    int* lbe;           // first global lane of the edge
+    int* lbf;           // first global lane of the next edge (0 if none)
 };
 
-__host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * 64 + 64; }
+__host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * 84 + 64; }
 
 __device__ inline TileBuf carve(char* base, int cap) {
     TileBuf b;
@@ -257,6 +268,11 @@ __device__ inline TileBuf carve(char* base, int cap) {
     b.fl = (uint32_t*)take(cap);
     b.pel = (uint32_t*)take(cap);
     b.inv = (int*)take(cap);
+    b.L = (float*)take(cap);
+    b.lim = (float*)take(cap);
+    b.lanes2 = (uint32_t*)take(cap);
+    b.lbe = (int*)take(cap);
+    b.lbf = (int*)take(cap);
     return b;
 }
 
@@ -429,7 +445,7 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
 // ---- Phases 1-2 for one tile ----------------------------------------------
 template <int NT>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
-                                    CounterAcc& acc, Scan4* wsh4) {
+                                    CounterAcc& acc, Scan4* wsh4, const ClassParams* scp) {
     const Slots S = d.s[par];
     const int tid = threadIdx.x;
     const int dir = (t % 2 == 0) ? -1 : 1;
@@ -438,12 +454,18 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     for (int q = tid; q < n; q += NT) {
         const int s = a0 + q;
         const uint32_t m = S.meta[s];
+        const int e = S.edge[s], f = S.nxt[s];
         b.x[q] = S.x[s];
         b.v[q] = S.v[s];
         b.vid[q] = S.vid[s];
-        b.el[q] = ((uint32_t)S.edge[s] << 4) | (uint32_t)m_lane(m);
+        b.el[q] = ((uint32_t)e << 4) | (uint32_t)m_lane(m);
         b.meta[q] = m;
-        b.nxt[q] = S.nxt[s];
+        b.nxt[q] = f;
+        b.L[q] = d.L[e];
+        b.lim[q] = d.lim[e];
+        b.lbe[q] = d.lane_base[e];
+        b.lanes2[q] = (uint32_t)d.lanes[e] | ((f >= 0 ? (uint32_t)d.lanes[f] : 0u) << 8);
+        b.lbf[q] = f >= 0 ? d.lane_base[f] : 0;
     }
     __syncthreads();
 
@@ -458,9 +480,9 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             const float xi = b.x[q], vi = b.v[q];
             const uint32_t id = b.vid[q];
             const bool allowed_l = lane_allowed(m, f, l);
-            const ClassParams cpi = d.cp[m_cls(m)];
+            const ClassParams cpi = scp[m_cls(m)];
             if (!allowed_l && !m_mand(m)) {                              // Eq. (2)
-                const float dd = d.L[e] - xi;
+                const float dd = b.L[q] - xi;
                 bool trig = false;
                 if (dd <= kX0) {
                     trig = true;
@@ -475,7 +497,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 }
             }
             const int lp = l + dir;
-            if (lp >= 0 && lp < d.lanes[e]) {
+            if (lp >= 0 && lp < (int)(b.lanes2[q] & 255u)) {
                 const uint32_t elp = (el & ~15u) | (uint32_t)lp;
                 pos = tile_lower_bound(b, n, elp, xi, id);
                 const int la = (pos > 0 && b.el[pos - 1] == elp) ? pos - 1 : -1;
@@ -484,18 +506,18 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 bool desire = !allowed_l && (lane_distance(mask, lp) < lane_distance(mask, l));
                 const bool allowed_lp = lane_allowed(m, f, lp);
                 if (!desire && allowed_lp && !(m_mand(m) && !allowed_l)) {
-                    const float v0 = cpi.v0f * d.lim[e];
+                    const float v0 = cpi.v0f * b.lim[q];
                     unsigned br = 0;
                     float acc_cur, acc_new;
                     const int lc = (q > 0 && b.el[q - 1] == el) ? q - 1 : -1;
                     if (lc >= 0) {
-                        const float s = (b.x[lc] - d.cp[m_cls(b.meta[lc])].len) - xi;
+                        const float s = (b.x[lc] - scp[m_cls(b.meta[lc])].len) - xi;
                         acc_cur = idm_acc(vi, v0, b.v[lc], s, cpi, kVeh, br);
                     } else {
                         acc_cur = idm_acc(vi, v0, 0.0f, 0.0f, cpi, kFree, br);
                     }
                     if (la >= 0) {
-                        const float s = (b.x[la] - d.cp[m_cls(b.meta[la])].len) - xi;
+                        const float s = (b.x[la] - scp[m_cls(b.meta[la])].len) - xi;
                         acc_new = idm_acc(vi, v0, b.v[la], s, cpi, kVeh, br);
                     } else {
                         acc_new = idm_acc(vi, v0, 0.0f, 0.0f, cpi, kFree, br);
@@ -507,7 +529,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                     const float ai = d.alpha[id];
                     bool ok = true;
                     if (la >= 0) {
-                        const float G = (b.x[la] - d.cp[m_cls(b.meta[la])].len) - xi;
+                        const float G = (b.x[la] - scp[m_cls(b.meta[la])].len) - xi;
                         const float g = crit_gap(g0, d.alpha[b.vid[la]], vi, ai, b.v[la]) +
                                         draw_normal(d.seed, t, d.rid[id], 2);
                         const float need = g > 0.0f ? g : 0.0f;
@@ -575,7 +597,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const uint32_t id = b.vid[q];
         uint32_t m = b.meta[q];
         const int f = b.nxt[q];
-        const int lanes_e = d.lanes[e];
+        const int lanes_e = (int)(b.lanes2[q] & 255u);
         const uint32_t e0 = el & ~15u;
         // leader candidates and rank in the post-change lane
         int c1 = -1, c2 = -1, rank;
@@ -623,7 +645,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         }
 
         // kind and gap (A1-A8, A17)
-        const ClassParams cpi = d.cp[m_cls(m)];
+        const ClassParams cpi = scp[m_cls(m)];
         const bool allowed_l = lane_allowed(m, f, lam);
         int kind;
         int partner = -1;
@@ -631,21 +653,21 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         if (j >= 0) {
             kind = kVeh;
             partner = (int)b.vid[j];
-            rear_j = b.x[j] - d.cp[m_cls(b.meta[j])].len;
+            rear_j = b.x[j] - scp[m_cls(b.meta[j])].len;
             s = rear_j - xi;
             vl = b.v[j];
         } else if (f < 0) {
             kind = kFree;
         } else if (m_mand(m) && !allowed_l && m_ww(m) < kPatience) {
             kind = kStop;
-            s = d.L[e] - xi;
+            s = b.L[q] - xi;
             vl = 0.0f;
         } else {
-            const int lf = min(lam, d.lanes[f] - 1);
-            const LaneRear r = d.rear[d.lane_base[f] + lf];
+            const int lf = min(lam, (int)(b.lanes2[q] >> 8) - 1);
+            const LaneRear r = d.rear[b.lbf[q] + lf];
             if (r.stamp == t) {
                 kind = kLook;
-                s = (d.L[e] - xi) + r.xm;
+                s = (b.L[q] - xi) + r.xm;
                 vl = r.v;
                 partner = (int)r.vid;
             } else {
@@ -653,7 +675,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             }
         }
         unsigned br = 0;
-        const float v0 = cpi.v0f * d.lim[e];
+        const float v0 = cpi.v0f * b.lim[q];
         const float a = idm_acc(vi, v0, vl, s, cpi, kind, br);
         const float dt = d.dt;
         float vnew = vi + (a * dt);
@@ -673,8 +695,8 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             acc.c[cClamp]++;
             tb |= TB_C;
         }
-        if (f >= 0 && !allowed_l && m_ww(m) < kPatience && xnew >= d.L[e]) {
-            xnew = d.L[e];
+        if (f >= 0 && !allowed_l && m_ww(m) < kPatience && xnew >= b.L[q]) {
+            xnew = b.L[q];
             vnew = 0.0f;
             m = (m | (1u << 4));
             m = (m & ~(127u << 8)) | ((uint32_t)(m_ww(m) + 1) << 8);
@@ -727,7 +749,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 atomicOr(&d.ctl->err, kErrPermutation);
             } else {
                 const int lam = (int)(el & 15u);
-                const int gl = d.lane_base[e] + lam;
+                const int gl = b.lbe[q] + lam;
                 const float xnew = b.xn[q];
                 if (rear) {
                     const int fr = el_lower_bound(b.pel, n, el);
@@ -735,24 +757,26 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                     lp.stamp = t;
                     lp.start = a0 + fr;
                     lp.cnt = r - fr + 1;
-                    lp.rear_xm = xnew - d.cp[m_cls(b.meta[q])].len;
+                    lp.rear_xm = xnew - scp[m_cls(b.meta[q])].len;
                     d.post[gl] = lp;
                 }
-                if (front && xnew >= d.L[e] && !(b.fl[q] & F_WHOLD)) {
+                if (front && xnew >= b.L[q] && !(b.fl[q] & F_WHOLD)) {
                     const int f = b.nxt[q];
                     const float xo = b.x[q];
                     Outbox ob;
                     ob.stamp = t;
+                    ob.elig = 0;
+                    ob.pad = 0;
                     ob.slot = a0 + r;
                     ob.vid = b.vid[q];
-                    ob.phi = (xnew == xo) ? 0.0f : (d.L[e] - xo) / (xnew - xo);
+                    ob.phi = (xnew == xo) ? 0.0f : (b.L[q] - xo) / (xnew - xo);
                     if (f < 0) {
                         ob.target = -1;
                         ob.xp = 0.0f;
                         ob.key = 0;
                     } else {
-                        ob.target = d.lane_base[f] + min(lam, d.lanes[f] - 1);
-                        ob.xp = xnew - d.L[e];
+                        ob.target = b.lbf[q] + min(lam, (int)(b.lanes2[q] >> 8) - 1);
+                        ob.xp = xnew - b.L[q];
                         const int hs = m_held(b.meta[q]) ? d.held_since[ob.vid] : t;
                         ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
                     }
@@ -770,11 +794,13 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
 // Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
 // tiles go to a list for k_tile_big.
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
-    __shared__ __align__(16) char lds[kTileCapLds * 64 + 64];
+    __shared__ __align__(16) char lds[kTileCapLds * 84 + 64];
     __shared__ Scan4 wsh4[kWaves];
     __shared__ int wsh[kWaves];
     __shared__ unsigned shc[cNumCounters];
+    __shared__ ClassParams scp[16];
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     const int t = d.ctl->t_a, par = t & 1;
     const int n = d.ctl->n_act[par];
     CounterAcc acc;
@@ -804,7 +830,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
             continue;
         }
         if (cnt <= kTileCapLds) {
-            process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4);
+            process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp);
         } else if (threadIdx.x == 0) {
             const int q = atomicAdd(&d.ctl->n_big[par], 1);
             d.big_list[2 * q] = a0;
@@ -818,11 +844,13 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
 // single edge larger than the LDS runs from the global-memory scratch.
 __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
-    __shared__ __align__(16) char lds[kBigCapLds * 64 + 64];
+    __shared__ __align__(16) char lds[kBigCapLds * 84 + 64];
     __shared__ Scan4 wsh4[kBigNT / 64];
     __shared__ int wsh[kBigNT / 64];
     __shared__ unsigned shc[cNumCounters];
+    __shared__ ClassParams scp[16];
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     __syncthreads();
     const int t = d.ctl->t_a, par = t & 1;
     const int nbig = d.ctl->n_big[par];
@@ -857,10 +885,10 @@ __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
             }
             const int cnt = end - pos;
             if (cnt <= kBigCapLds) {
-                process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4);
+                process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp);
             } else {
                 char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
-                process_tile<kBigNT>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4);
+                process_tile<kBigNT>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp);
             }
             pos = end;
         }
@@ -914,13 +942,20 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
             for (int l = 0; l < d.lanes[e]; ++l) {
                 const Outbox ob = d.outbox[base + l];
                 if (ob.stamp != t || ob.target < 0) continue;
-                if (transfer_eligible(d, ob, t)) claim(d, ob.target, ob.key, t);
+                const bool ok = transfer_eligible(d, ob, t);
+                d.outbox[base + l].elig = ok ? 1 : 0;
+                if (ok) claim(d, ob.target, ob.key, t);
             }
         } else {
             const int e = d.ins_edges[i - nreq];
             for (int q = d.eq_off[e]; q < d.eq_off[e + 1]; ++q) {
                 const int vid = queue_due_head(d, q, t);
-                if (vid >= 0 && insert_eligible(d, vid, t)) claim(d, d.ins_gl[vid], insert_key(d, vid), t);
+                unsigned long long key = ~0ull;
+                if (vid >= 0 && insert_eligible(d, vid, t)) {
+                    key = insert_key(d, vid);
+                    claim(d, d.qlane[q], key, t);
+                }
+                d.qkey[q] = key;
             }
         }
     }
@@ -944,7 +979,7 @@ __device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, C
         if (ob.stamp != t) continue;
         const uint32_t m = S.meta[ob.slot];
         if (d.trace) {
-            const bool w2 = ob.target >= 0 && transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
+            const bool w2 = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
             d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + ob.slot].kb |=
                 (ob.target < 0 ? TB_ARRIVE : (w2 ? TB_EXIT : TB_HELD)) << 8;
         }
@@ -961,7 +996,7 @@ __device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, C
             acc.c[cArrived]++;
             continue;
         }
-        const bool won = transfer_eligible(d, ob, t) && d.win[ob.target] == ob.key;
+        const bool won = ob.elig && d.win[ob.target] == ob.key;
         if (won) {
             if (!lane_allowed(m, S.nxt[ob.slot], l)) acc.c[cWaivedExits]++;
             d.exit_stamp[base + l] = t;
@@ -1054,9 +1089,8 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         unsigned exmask = 0;
         if (d.req_stamp[e] == t) commit_edge(d, S, e, t, acc, nex, exmask, winmask);
         for (int q = d.eq_off[e]; q < d.eq_off[e + 1]; ++q) {
-            const int vid = queue_due_head(d, q, t);
-            if (vid >= 0 && insert_eligible(d, vid, t) && d.win[d.ins_gl[vid]] == insert_key(d, vid))
-                insq[nins++] = q;   // at most one winner per lane
+            const unsigned long long key = d.qkey[q];
+            if (key != ~0ull && d.win[d.qlane[q]] == key) insq[nins++] = q;   // at most one winner per lane
         }
         c = d.cnt[e] - nex + d.entries[e];
         d.cnt[e] = c;
