@@ -473,7 +473,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.qveh = h->upload(h->qveh.data(), N);
             d.qoff = h->upload(h->qoff.data(), NQ + 1);
             d.qhead = h->upload(h->qoff.data(), NQ + 1);
-            d.qlane = h->upload(qlane.data(), std::max(NQ, 1));
+            d.qlane = NQ ? h->upload(qlane.data(), NQ) : h->dev<int>(1);
             d.qkey = h->dev<unsigned long long>(std::max(NQ, 1));
             d.eq_off = h->upload(eq_off.data(), E + 1);
             d.ins_edges = h->upload(ins_edges.data(), ins_edges.size());
