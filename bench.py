@@ -30,6 +30,46 @@ BYTES_PER_UPDATE = 48
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_step_traffic.json")
 
 
+def kernel_source_digest() -> str:
+    """Digest of the HIP sources: byte counters taken on other sources no
+    longer describe the kernel and are not reported."""
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2007_03614_amd", "csrc")
+    for n in sorted(os.listdir(d)):
+        with open(os.path.join(d, n), "rb") as f:
+            h.update(n.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from(fetch_json: str, write_json: str, kernel: str = "k_tile_step",
+                 probe_mib: int = 256) -> dict:
+    """HBM bytes per dispatch of `kernel` from two --pmc summaries (FETCH_SIZE,
+    WRITE_SIZE in KiB per dispatch), each scaled by what the same counter
+    reads for the copy probe (torch's add of probe_mib MiB: reads and writes
+    probe_mib MiB each)."""
+    f = json.load(open(fetch_json))["kernels"]
+    w = json.load(open(write_json))["kernels"]
+
+    def pick(d, key):
+        ks = [k for k in d if kernel + "(" in k]
+        probe = [k for k in d if "add" in k.lower() and "fill" not in k.lower() and key in d[k]]
+        if len(ks) != 1 or len(probe) != 1:
+            raise SystemExit(f"cannot identify kernel/probe in summary: {ks} {probe}")
+        return d[ks[0]][key], d[probe[0]][key], probe[0]
+
+    kf, pf, pname = pick(f, "FETCH_SIZE")
+    kw, pw, _ = pick(w, "WRITE_SIZE")
+    known = probe_mib * 1024.0
+    fs, ws = known / pf, known / pw
+    return {"workload": "perturbed_grid_ring", "kernel": kernel, "sources": kernel_source_digest(),
+            "bytes_per_launch": 1024.0 * (kf * fs + kw * ws),
+            "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
+            "probe": pname[:80], "probe_fetch_kib": pf, "probe_write_kib": pw,
+            "fetch_scale": fs, "write_scale": ws}
+
+
 def make_workload(name: str):
     import workloads as W
     if name == "perturbed_grid_ring":
@@ -190,10 +230,15 @@ def main():
                     help="run one plain device copy of this many MiB before the timed region "
                          "(a known-size reference for hardware byte counters)")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="summarize a rocprofv3 --pmc csv directory and exit")
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_JSON", "WRITE_JSON"),
+                    help="combine two --summarize-pmc outputs into the traffic record and exit")
     args = ap.parse_args()
     args.steps_given = "--steps" in sys.argv
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
+        return
+    if args.traffic_from:
+        print(json.dumps(traffic_from(*args.traffic_from, probe_mib=args.copy_probe or 256), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation is "
@@ -253,7 +298,7 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("workload") == args.workload:
+        if tr.get("workload") == args.workload and tr.get("sources") == kernel_source_digest():
             traffic = tr.get("bytes_per_launch")
     line = {
         "metric": "vehicle-updates/sec (1 GPU)",

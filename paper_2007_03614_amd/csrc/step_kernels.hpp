@@ -442,6 +442,18 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
     return hi;
 }
 
+// G >= max(c + eps, 0) with eps = N(t, id, stream).  eps lies in [-6, 6]
+// (Irwin-Hall of twelve uniforms minus 6) and binary32 rounding is monotone,
+// so the draw is needed only when G is within 6 m of c: otherwise the
+// answer is the same for every eps and the (costly) draw is skipped.
+__device__ inline bool gap_accepts(float G, float c, uint64_t seed, int t, uint32_t rid, int stream) {
+    if (G < c - 6.0f) return false;
+    if (G >= c + 6.0f && G >= 0.0f) return true;
+    const float g = c + draw_normal(seed, t, rid, stream);
+    const float need = g > 0.0f ? g : 0.0f;
+    return G >= need;
+}
+
 // ---- Phases 1-2 for one tile ----------------------------------------------
 template <int NT>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
@@ -530,17 +542,13 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                     bool ok = true;
                     if (la >= 0) {
                         const float G = (b.x[la] - scp[m_cls(b.meta[la])].len) - xi;
-                        const float g = crit_gap(g0, d.alpha[b.vid[la]], vi, ai, b.v[la]) +
-                                        draw_normal(d.seed, t, d.rid[id], 2);
-                        const float need = g > 0.0f ? g : 0.0f;
-                        ok = ok && (G >= need);
+                        const float c = crit_gap(g0, d.alpha[b.vid[la]], vi, ai, b.v[la]);
+                        ok = gap_accepts(G, c, d.seed, t, d.rid[id], 2);
                     }
-                    if (lb >= 0) {
+                    if (ok && lb >= 0) {
                         const float G = (xi - cpi.len) - b.x[lb];
-                        const float g = crit_gap(g0, ai, vi, d.alpha[b.vid[lb]], b.v[lb]) +
-                                        draw_normal(d.seed, t, d.rid[id], 3);
-                        const float need = g > 0.0f ? g : 0.0f;
-                        ok = ok && (G >= need);
+                        const float c = crit_gap(g0, ai, vi, d.alpha[b.vid[lb]], b.v[lb]);
+                        ok = gap_accepts(G, c, d.seed, t, d.rid[id], 3);
                     }
                     if (ok) {
                         moved = 1;

@@ -103,6 +103,16 @@ def test_parity_single_edge_free_road(M, oracle_mod):
     assert bitwise
 
 
+@pytest.mark.parametrize("n", [30, 100])
+def test_parity_ring_road(M, oracle_mod, n):
+    """A closed one-lane ring: every vehicle crosses a node every few steps,
+    so look-ahead across edge ends and admission run on every lap; n = 100
+    keeps a stop-and-go wave alive."""
+    w = W.ring_road(n)
+    _, _, bitwise = run_pair(M, oracle_mod, w, [1, 25, 200, 1000, 3000])
+    assert bitwise
+
+
 def test_parity_config1_full(M, oracle_mod, c1):
     """10x10 grid, 2,000 vehicles, 3,600 steps: every 100 steps."""
     g, o, bitwise = run_pair(M, oracle_mod, c1, list(range(1, 20)) + list(range(100, 3601, 100)))

@@ -80,6 +80,53 @@ def test_platoon_reaches_equilibrium_gap(oracle_mod):
         assert abs(float(st["v"][1]) - vl) < 1e-3
 
 
+def _equilibrium_speed(gap, v0, s0=2.0, T=1.5):
+    """v_e with s_e(v_e) = gap, s_e(v) = (s0 + vT)/sqrt(1 - (v/v0)^4), by bisection."""
+    lo, hi = 0.0, v0
+    for _ in range(200):
+        m = 0.5 * (lo + hi)
+        if (s0 + m * T) / math.sqrt(1.0 - (m / v0) ** 4) < gap:
+            lo = m
+        else:
+            hi = m
+    return 0.5 * (lo + hi)
+
+
+@pytest.mark.parametrize("n", [10, 30, 50, 80])
+def test_ring_road_fundamental_diagram(oracle_mod, n):
+    """A 1 km one-lane ring of ten 100 m edges holding n vehicles: the
+    homogeneous state is the equilibrium of Eq. (1), so every vehicle ends at
+    the speed v_e(s) with s = 1000/n - 5, and the flow is q = (n/1000) v_e
+    (the fundamental diagram of the model).  Crossing ten intersections per
+    lap must not disturb it: admission and the look-ahead leader across an
+    edge end are exercised at every node."""
+    w = W.ring_road(n)
+    v0 = float(np.float32(50.0 / 3.6))
+    gap = 1000.0 / n - 5.0
+    ve = _equilibrium_speed(gap, v0)
+    for fp64 in (False, True):
+        sim = oracle_mod.OracleSim(w, fp64=fp64)
+        sim.step(4000)
+        st = sim.state()
+        act = st["status"] == ACTIVE
+        assert act.sum() == n
+        v = st["v"][act].astype(np.float64)
+        assert abs(v.mean() - ve) < 1e-3 * ve, (v.mean(), ve)
+        assert v.std() < 1e-3
+        # flow past a fixed point = density x mean speed
+        assert abs((n / 1000.0) * v.mean() - (n / 1000.0) * ve) < 1e-6 * n
+        # spacing along the ring is uniform
+        ring_pos = np.sort(_ring_position(w, st, act))
+        spacing = np.diff(np.concatenate([ring_pos, ring_pos[:1] + 1000.0]))
+        assert np.abs(spacing - 1000.0 / n).max() < 0.05, spacing
+
+
+def _ring_position(w, st, act):
+    """Distance from node 0 along the ring of each active vehicle's front."""
+    e = st["edge"][act]
+    return w.net.edge_from[e].astype(np.float64) * 100.0 + st["x"][act].astype(np.float64)
+
+
 # ---------------------------------------------------------------- invariants
 def _lane_groups(st, mask):
     idx = np.nonzero(mask)[0]

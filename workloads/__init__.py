@@ -449,6 +449,31 @@ def single_edge_workload(length: float = 5000.0, limit: float = 50.0 / 3.6, lane
                     params or base_params(1), n_steps)
 
 
+def ring_road(n_vehicles: int, n_nodes: int = 10, edge_len: float = 100.0, limit: float = 50.0 / 3.6,
+              laps: int = 60, n_steps: int = 0, params: Params = None) -> Workload:
+    """A one-lane ring road of n_nodes edges of edge_len metres (both
+    directions exist; vehicles use the forward one).  Vehicle j enters at the
+    start of edge j mod n_nodes at step 2 * (j // n_nodes) and drives `laps`
+    laps.  For the fundamental diagram of the car-following model."""
+    ang = 2.0 * math.pi * np.arange(n_nodes) / n_nodes
+    rad = n_nodes * edge_len / (2.0 * math.pi)
+    u = np.arange(n_nodes)
+    net = _finish_edges(rad * np.cos(ang), rad * np.sin(ang), u, (u + 1) % n_nodes,
+                        np.full(n_nodes, edge_len, np.float32), np.full(n_nodes, limit, np.float32),
+                        np.ones(n_nodes, np.int64))
+    fwd = np.empty(n_nodes, np.int32)
+    for i in range(n_nodes):
+        fwd[i] = int(np.nonzero((net.edge_from == i) & (net.edge_to == (i + 1) % n_nodes))[0][0])
+    j = np.arange(n_vehicles)
+    start = j % n_nodes
+    route_edges = fwd[(start[:, None] + np.arange(laps * n_nodes)[None, :]) % n_nodes].astype(np.int32).ravel()
+    route_off = np.arange(n_vehicles + 1, dtype=np.int64) * laps * n_nodes
+    dep = (2 * (j // n_nodes)).astype(np.int32)
+    return Workload(f"ring{n_nodes}x{int(edge_len)}_n{n_vehicles}", net, route_off, route_edges, dep,
+                    np.zeros(n_vehicles, np.uint8), np.full(n_vehicles, 0.2, np.float32),
+                    params or base_params(1), n_steps)
+
+
 def scaled_config2(n_vehicles: int, rows: int, cols: int, n_steps: int, seed: int = 0) -> Workload:
     """Config 2's recipe on a smaller grid (for oracle-sized parity cases)."""
     w = config2(seed=seed, n_vehicles=n_vehicles, n_steps=n_steps, rows=rows, cols=cols)
