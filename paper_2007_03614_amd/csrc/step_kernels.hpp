@@ -31,7 +31,7 @@ constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parame
 constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
 constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
-constexpr int kBigCapLds = 1792;         // vehicles per big tile piece staged in LDS (147 KiB)
+constexpr int kBigCapLds = 1536;         // vehicles per big tile piece staged in LDS (138 KiB)
 constexpr int kCounterCopies = 32;       // each counter is spread over 32 slots (fewer colliding atomics)
 
 // ---- vehicle meta word ---------------------------------------------------
@@ -244,9 +244,12 @@ struct TileBuf {
     uint32_t* lanes2;   // lanes of the edge | lanes of the next edge << 8
     int* lbe;           // first global lane of the edge
     int* lbf;           // first global lane of the next edge (0 if none)
+    float* alpha;       // anticipation time of the vehicle (Eqs. (3)-(4))
+    uint32_t* rid;      // counter id of its draws
 };
 
-__host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * 84 + 64; }
+constexpr int kTileBytesPerVeh = 92;   // 23 four-byte arrays
+__host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * kTileBytesPerVeh + 64; }
 
 __device__ inline TileBuf carve(char* base, int cap) {
     TileBuf b;
@@ -273,6 +276,8 @@ __device__ inline TileBuf carve(char* base, int cap) {
     b.lanes2 = (uint32_t*)take(cap);
     b.lbe = (int*)take(cap);
     b.lbf = (int*)take(cap);
+    b.alpha = (float*)take(cap);
+    b.rid = (uint32_t*)take(cap);
     return b;
 }
 
@@ -442,14 +447,61 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
     return hi;
 }
 
-// G >= max(c + eps, 0) with eps = N(t, id, stream).  eps lies in [-6, 6]
-// (Irwin-Hall of twelve uniforms minus 6) and binary32 rounding is monotone,
-// so the draw is needed only when G is within 6 m of c: otherwise the
-// answer is the same for every eps and the (costly) draw is skipped.
-__device__ inline bool gap_accepts(float G, float c, uint64_t seed, int t, uint32_t rid, int stream) {
-    if (G < c - 6.0f) return false;
-    if (G >= c + 6.0f && G >= 0.0f) return true;
-    const float g = c + draw_normal(seed, t, rid, stream);
+// ---- lane-change draws computed by the whole workgroup -------------------
+// A task is one Philox block (vehicle q of the tile, stream, block index).
+// Its 24-bit words are added into the vehicle's slot with an LDS atomic; the
+// sums are integers, so the order of the additions does not matter and the
+// result equals draw_uniform / draw_normal exactly.
+struct DrawQ {
+    uint2* task;   // [cap] {rid, q << 4 | stream << 2 | block}
+    int* n;        // [2] tasks listed in each round
+    int cap;
+};
+
+__device__ inline uint32_t philox_words(uint64_t seed, int t, uint32_t rid, int stream, int blk) {
+    const U64x4 r = philox4x64_10((uint64_t)(int64_t)t, rid, (uint64_t)stream, (uint64_t)blk, seed, 0);
+    if (stream == 1) return (uint32_t)(r.w[0] >> 40);
+    return (uint32_t)((r.w[0] >> 40) + (r.w[1] >> 40) + (r.w[2] >> 40) + (r.w[3] >> 40));
+}
+
+// list one task; a full list computes it in place
+__device__ inline void draw_task(const DrawQ& dq, int round, uint32_t rid, int q, int stream, int blk, int* slot,
+                                 uint64_t seed, int t) {
+    const int k = atomicAdd(&dq.n[round], 1);
+    if (k < dq.cap) dq.task[k] = make_uint2(rid, ((uint32_t)q << 4) | ((uint32_t)stream << 2) | (uint32_t)blk);
+    else atomicAdd(&slot[q], (int)philox_words(seed, t, rid, stream, blk));
+}
+
+template <int NT>
+__device__ inline void draw_run(const DrawQ& dq, int round, uint64_t seed, int t, int* u1, int* na, int* nb) {
+    const int nt = min(dq.n[round], dq.cap);
+    for (int i = threadIdx.x; i < nt; i += NT) {
+        const uint2 tk = dq.task[i];
+        const int q = (int)(tk.y >> 4), st = (int)((tk.y >> 2) & 3u), blk = (int)(tk.y & 3u);
+        int* slot = st == 1 ? u1 : (st == 2 ? na : nb);
+        atomicAdd(&slot[q], (int)philox_words(seed, t, tk.x, st, blk));
+    }
+}
+
+__device__ inline float uniform_of_word(uint32_t w) {
+    return (float)w * 5.9604644775390625e-08f;   // * 2^-24, exact
+}
+
+// Eqs. (3)-(4): G >= max(c + eps, 0).  eps lies in [-6, 6] (Irwin-Hall of
+// twelve uniforms minus 6) and binary32 rounding is monotone, so the noise
+// decides only when G is within 6 m of c.
+constexpr int kGapNo = 0, kGapYes = 1, kGapDraw = 2;
+constexpr int kPending = 2, kDrawA = 4, kDrawB = 8;   // Phase 1 states of b.moved
+
+__device__ inline int gap_outcome(float G, float c) {
+    if (G < c - 6.0f) return kGapNo;
+    if (G >= c + 6.0f && G >= 0.0f) return kGapYes;
+    return kGapDraw;
+}
+
+__device__ inline bool gap_with_noise(float G, float c, int word_sum) {
+    const int32_t z = (int32_t)((int64_t)(uint32_t)word_sum - 6ll * 16777216ll);
+    const float g = c + (float)z * 5.9604644775390625e-08f;
     const float need = g > 0.0f ? g : 0.0f;
     return G >= need;
 }
@@ -457,7 +509,7 @@ __device__ inline bool gap_accepts(float G, float c, uint64_t seed, int t, uint3
 // ---- Phases 1-2 for one tile ----------------------------------------------
 template <int NT>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
-                                    CounterAcc& acc, Scan4* wsh4, const ClassParams* scp) {
+                                    CounterAcc& acc, Scan4* wsh4, const ClassParams* scp, const DrawQ& dq) {
     const Slots S = d.s[par];
     const int tid = threadIdx.x;
     const int dir = (t % 2 == 0) ? -1 : 1;
@@ -478,19 +530,51 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.lbe[q] = d.lane_base[e];
         b.lanes2[q] = (uint32_t)d.lanes[e] | ((f >= 0 ? (uint32_t)d.lanes[f] : 0u) << 8);
         b.lbf[q] = f >= 0 ? d.lane_base[f] : 0;
+        const uint32_t id = S.vid[s];
+        b.alpha[q] = d.alpha[id];
+        b.rid[q] = d.rid[id];
     }
+    if (tid < 2) dq.n[tid] = 0;
     __syncthreads();
 
-    // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t
+    // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t.
+    // Few vehicles need a Philox draw, and a block costs thousands of
+    // cycles, so a wavefront in which one lane draws would make the other 63
+    // wait.  Instead the draws are listed as tasks and computed by the whole
+    // workgroup at once, in two rounds: the uniforms of Eq. (2), then the
+    // noise of Eqs. (3)-(4), whose need depends on the mandatory flag.
+    int* const u1 = b.lastm;                      // Eq. (2) uniform words (scratch until the scans)
+    int* const na = b.lasts;                      // noise word sums, leading side
+    int* const nb = b.runst;                      // noise word sums, lagging side
+    float* const Ga = b.xn;                       // gaps and critical gaps of pending decisions
+    float* const ca = (float*)b.fl;               // (scratch until Phase 2)
+    float* const Gb = (float*)b.pel;
+    float* const cb = (float*)b.inv;
+    for (int q = tid; q < n; q += NT) {
+        u1[q] = 0;
+        na[q] = 0;
+        nb[q] = 0;
+        const uint32_t m = b.meta[q];
+        if (m_held(m) || m_mand(m)) continue;
+        const int l = (int)(b.el[q] & 15u);
+        if (lane_allowed(m, b.nxt[q], l)) continue;
+        const float dd = b.L[q] - b.x[q];
+        if (dd <= kX0) continue;
+        const float dm = dd - kX0;
+        if (dm * dm < kZCut) draw_task(dq, 0, b.rid[q], q, 1, 0, u1, d.seed, t);
+    }
+    __syncthreads();
+    draw_run<NT>(dq, 0, d.seed, t, u1, na, nb);
+    __syncthreads();
+
     for (int q = tid; q < n; q += NT) {
         uint32_t m = b.meta[q];
         int moved = 0, pos = 0;
         if (!m_held(m)) {
             const uint32_t el = b.el[q];
-            const int e = (int)(el >> 4), l = (int)(el & 15u);
+            const int l = (int)(el & 15u);
             const int f = b.nxt[q];
             const float xi = b.x[q], vi = b.v[q];
-            const uint32_t id = b.vid[q];
             const bool allowed_l = lane_allowed(m, f, l);
             const ClassParams cpi = scp[m_cls(m)];
             if (!allowed_l && !m_mand(m)) {                              // Eq. (2)
@@ -501,7 +585,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 } else {
                     const float dm = dd - kX0;
                     const float z = dm * dm;
-                    if (z < kZCut && draw_uniform(d.seed, t, d.rid[id], 1) < exp_eq2(-z)) trig = true;
+                    if (z < kZCut && uniform_of_word((uint32_t)u1[q]) < exp_eq2(-z)) trig = true;
                 }
                 if (trig) {
                     m |= 1u << 4;
@@ -511,7 +595,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             const int lp = l + dir;
             if (lp >= 0 && lp < (int)(b.lanes2[q] & 255u)) {
                 const uint32_t elp = (el & ~15u) | (uint32_t)lp;
-                pos = tile_lower_bound(b, n, elp, xi, id);
+                pos = tile_lower_bound(b, n, elp, xi, b.vid[q]);
                 const int la = (pos > 0 && b.el[pos - 1] == elp) ? pos - 1 : -1;
                 const int lb = (pos < n && b.el[pos] == elp) ? pos : -1;
                 const uint32_t mask = f < 0 ? 0xFFu : m_mask(m);
@@ -538,22 +622,34 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 }
                 if (desire) {                                            // Eqs. (3)-(4)
                     const float g0 = desired_gap(vi);
-                    const float ai = d.alpha[id];
-                    bool ok = true;
+                    const float ai = b.alpha[q];
+                    int ra = kGapYes, rb = kGapYes;
                     if (la >= 0) {
                         const float G = (b.x[la] - scp[m_cls(b.meta[la])].len) - xi;
-                        const float c = crit_gap(g0, d.alpha[b.vid[la]], vi, ai, b.v[la]);
-                        ok = gap_accepts(G, c, d.seed, t, d.rid[id], 2);
+                        const float c = crit_gap(g0, b.alpha[la], vi, ai, b.v[la]);
+                        ra = gap_outcome(G, c);
+                        Ga[q] = G;
+                        ca[q] = c;
                     }
-                    if (ok && lb >= 0) {
+                    if (lb >= 0) {
                         const float G = (xi - cpi.len) - b.x[lb];
-                        const float c = crit_gap(g0, ai, vi, d.alpha[b.vid[lb]], b.v[lb]);
-                        ok = gap_accepts(G, c, d.seed, t, d.rid[id], 3);
+                        const float c = crit_gap(g0, ai, vi, b.alpha[lb], b.v[lb]);
+                        rb = gap_outcome(G, c);
+                        Gb[q] = G;
+                        cb[q] = c;
                     }
-                    if (ok) {
-                        moved = 1;
-                        acc.c[cLaneChanges]++;
-                        if (allowed_lp) m &= ~((1u << 4) | (127u << 8));   // mand = 0, ww = 0
+                    if (ra != kGapNo && rb != kGapNo) {
+                        if (ra == kGapYes && rb == kGapYes) {
+                            moved = 1;
+                            acc.c[cLaneChanges]++;
+                            if (allowed_lp) m &= ~((1u << 4) | (127u << 8));   // mand = 0, ww = 0
+                        } else {                                 // decided by the noise
+                            moved = kPending | (ra == kGapDraw ? kDrawA : 0) | (rb == kGapDraw ? kDrawB : 0);
+                            for (int k = 0; k < 3; ++k) {
+                                if (ra == kGapDraw) draw_task(dq, 1, b.rid[q], q, 2, k, na, d.seed, t);
+                                if (rb == kGapDraw) draw_task(dq, 1, b.rid[q], q, 3, k, nb, d.seed, t);
+                            }
+                        }
                     }
                 }
             }
@@ -563,6 +659,26 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         // only this vehicle's own mandatory/wait bits change; its class bits,
         // which neighbours read, stay the same
         b.meta[q] = m;
+    }
+    __syncthreads();
+    draw_run<NT>(dq, 1, d.seed, t, u1, na, nb);
+    __syncthreads();
+
+    for (int q = tid; q < n; q += NT) {
+        const int code = b.moved[q];
+        if (!(code & kPending)) continue;
+        bool ok = true;
+        if (code & kDrawA) ok = gap_with_noise(Ga[q], ca[q], na[q]);
+        if (code & kDrawB) ok = ok && gap_with_noise(Gb[q], cb[q], nb[q]);
+        int moved = 0;
+        if (ok) {
+            moved = 1;
+            acc.c[cLaneChanges]++;
+            uint32_t m = b.meta[q];
+            const int lp = (int)(b.el[q] & 15u) + dir;
+            if (lane_allowed(m, b.nxt[q], lp)) b.meta[q] = m & ~((1u << 4) | (127u << 8));
+        }
+        b.moved[q] = moved;
     }
     __syncthreads();
 
@@ -802,11 +918,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
 // Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
 // tiles go to a list for k_tile_big.
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
-    __shared__ __align__(16) char lds[kTileCapLds * 84 + 64];
+    __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kWaves];
     __shared__ int wsh[kWaves];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
+    __shared__ uint2 dtask[kNT];
+    __shared__ int dcount[2];
+    const DrawQ dq{dtask, dcount, kNT};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     const int t = d.ctl->t_a, par = t & 1;
@@ -838,7 +957,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
             continue;
         }
         if (cnt <= kTileCapLds) {
-            process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp);
+            process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
         } else if (threadIdx.x == 0) {
             const int q = atomicAdd(&d.ctl->n_big[par], 1);
             d.big_list[2 * q] = a0;
@@ -852,11 +971,14 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
 // single edge larger than the LDS runs from the global-memory scratch.
 __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
-    __shared__ __align__(16) char lds[kBigCapLds * 84 + 64];
+    __shared__ __align__(16) char lds[kBigCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kBigNT / 64];
     __shared__ int wsh[kBigNT / 64];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
+    __shared__ uint2 dtask[kBigNT];
+    __shared__ int dcount[2];
+    const DrawQ dq{dtask, dcount, kBigNT};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     __syncthreads();
@@ -893,10 +1015,10 @@ __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
             }
             const int cnt = end - pos;
             if (cnt <= kBigCapLds) {
-                process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp);
+                process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp, dq);
             } else {
                 char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
-                process_tile<kBigNT>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp);
+                process_tile<kBigNT>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp, dq);
             }
             pos = end;
         }

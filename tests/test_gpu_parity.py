@@ -37,10 +37,14 @@ def compare_states(g, o, where=""):
     return all(np.array_equal(np.asarray(g[k], np.float32), np.asarray(o[k], np.float32)) for k in ("x", "v"))
 
 
-def run_pair(M, oracle_mod, w, checkpoints):
+def run_pair(M, oracle_mod, w, checkpoints, init=None):
     g = M.Sim(w)
     o = oracle_mod.OracleSim(w)
     t = 0
+    if init is not None:   # both sides start from the same written state
+        g.write_state(init)
+        o.write_state(init["t"], init)
+        t = init["t"]
     bitwise = True
     for cp in checkpoints:
         g.step(cp - t)
@@ -128,9 +132,10 @@ def test_parity_config1_four_classes(M, oracle_mod):
     assert bitwise
 
 
-def test_parity_long_edge_big_tiles(M, oracle_mod):
-    """One 8 km two-lane edge filled by 1,500 vehicles: tiles far above the LDS
-    capacity go through the global-memory tile path; lane changes by incentive."""
+def test_parity_long_edge_two_classes(M, oracle_mod):
+    """One 8 km two-lane edge fed with 1,500 vehicles of two classes (v0
+    factor 1 and 0.6): fast vehicles pass slow ones by the lane-change
+    incentive."""
     p = W.base_params(2)
     p.v0_factor[1] = np.float32(0.6)
     w = W.single_edge_workload(length=8000.0, lanes=2, n_vehicles=1500, depart_step=np.arange(1500) // 2,
@@ -139,6 +144,30 @@ def test_parity_long_edge_big_tiles(M, oracle_mod):
     g, o, bitwise = run_pair(M, oracle_mod, w, [100, 600, 1200, 1800, 2400])
     assert bitwise
     assert o.counters()["lane_changes"] > 100
+
+
+def test_parity_dense_queue_big_tiles(M, oracle_mod):
+    """A 16 km two-lane edge that starts as a dense queue of 2,600 vehicles
+    (7.5 m apart, speeds U[0, 6] m/s, written as the state at step 0).  As the
+    queue discharges (about 0.4 vehicles per step), the edge runs first from
+    the global-memory tile scratch (above 1,536 vehicles), then from the LDS
+    of the 1,024-thread kernel; the first steps brake hard (stop branch)."""
+    n = 2600
+    w = W.single_edge_workload(length=16000.0, lanes=2, n_vehicles=n, depart_step=np.zeros(n, np.int32),
+                               n_steps=0)
+    rng = np.random.default_rng(3)
+    i = np.arange(n)
+    init = dict(status=np.ones(n, np.uint8), edge=np.full(n, int(w.route_edges[0]), np.int32),
+                lane=(i % 2).astype(np.int32), cursor=np.zeros(n, np.int32),
+                x=(16000.0 - 1.0 - 7.5 * (i // 2)).astype(np.float32),
+                v=rng.uniform(0.0, 6.0, n).astype(np.float32), held_since=np.full(n, -1, np.int32),
+                mand=np.zeros(n, np.uint8), ww=np.zeros(n, np.int32), tau_in=np.zeros(n),
+                t_arr=np.full(n, -1.0), counters=None, t=0)
+    g, o, bitwise = run_pair(M, oracle_mod, w, [1, 2, 10, 100, 400, 1000, 2000, 3000, 4000], init=init)
+    assert bitwise
+    c = o.counters()
+    assert c["stop_branch"] > 0 and c["lane_changes"] > 0, c
+    assert 512 < n - c["arrived"] < 1536, c   # started above the LDS of one workgroup, ends inside it
 
 
 def test_parity_scaled_config2(M, oracle_mod):
