@@ -254,6 +254,7 @@ void for_each_state_piece(sim_handle* h, F&& f) {
     f((void*)d.fin_meta, 4 * N);
     f((void*)d.rear, sizeof(LaneRear) * NL);
     f((void*)d.qhead, 4 * ((size_t)h->nq + 1));
+    f((void*)d.qhd, sizeof(int2) * (size_t)std::max(h->nq, 1));
     f((void*)d.cnt, 4 * E);
     f((void*)d.tt_sum, 8 * E);
     f((void*)d.tt_cnt, 8 * E);
@@ -383,9 +384,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             for (int e = 0; e < E; ++e)
                 for (int l = 0; l < h->lanes[e]; ++l) lane_edge[h->lane_base[e] + l] = e;
             d.lane_edge = h->upload(lane_edge.data(), NL);
-            d.conn_off = h->upload(net->conn_off, E + 1);
-            d.conn_to = h->upload(net->conn_to, NC);
-            d.conn_mask = h->upload(net->conn_lane_mask, NC);
             // ---- classes (den = 2 sqrt(ab), rounded once in binary32)
             std::vector<ClassParams> cp(16);
             h->len_c.assign(p->n_classes, 0.f);
@@ -454,30 +452,36 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             }
             if (N > 0) h->qoff.push_back(N);
             const int NQ = (int)qlane.size();
-            std::vector<int> eq_off(E + 1, 0), lane_edge_h(NL);
-            for (int e = 0; e < E; ++e)
-                for (int l = 0; l < h->lanes[e]; ++l) lane_edge_h[h->lane_base[e] + l] = e;
-            for (int q = 0; q < NQ; ++q) eq_off[lane_edge_h[qlane[q]] + 1]++;
-            for (int e = 0; e < E; ++e) eq_off[e + 1] += eq_off[e];
-            std::vector<int> ins_edges;
-            for (int e = 0; e < E; ++e)
-                if (eq_off[e + 1] > eq_off[e]) ins_edges.push_back(e);
+            std::vector<int4> vq(std::max(N, 1));
+            for (int q = 0; q < NQ; ++q)
+                for (int k = h->qoff[q]; k < h->qoff[q + 1]; ++k) {
+                    const int nv = k + 1 < h->qoff[q + 1] ? h->qveh[k + 1] : -1;
+                    vq[h->qveh[k]] = make_int4(q, k, nv, nv >= 0 ? h->dep[nv] : 0);
+                }
+            std::vector<int2> qhd(std::max(NQ, 1));
+            std::vector<float> qs0(std::max(NQ, 1));
+            for (int q = 0; q < NQ; ++q) {
+                const int v0 = h->qveh[h->qoff[q]];
+                qhd[q] = make_int2(h->dep[v0], v0);
+                qs0[q] = p->s0[h->cls[v0]];
+            }
             d.roff = h->upload(h->roff.data(), N + 1);
             d.redges = h->upload(h->redges.data(), (size_t)NR);
-            d.dep = h->upload(h->dep.data(), N);
+            std::vector<uint8_t> rmask(std::max<int64_t>(NR, 1), 0xFFu);
+            for (int i = 0; i < N; ++i)
+                for (int64_t k = h->roff[i]; k + 1 < h->roff[i + 1]; ++k)
+                    rmask[k] = (uint8_t)h->mask_of(h->redges[k], h->redges[k + 1]);
+            d.rmask = h->upload(rmask.data(), rmask.size());
             d.cls = h->upload(h->cls.data(), N);
             d.alpha = h->upload(r->alpha_s, N);
-            d.ins_gl = h->upload(ins_gl.data(), N);
             d.due = h->upload(due.data(), due.size());
             d.max_dep = max_dep;
-            d.qveh = h->upload(h->qveh.data(), N);
-            d.qoff = h->upload(h->qoff.data(), NQ + 1);
             d.qhead = h->upload(h->qoff.data(), NQ + 1);
             d.qlane = NQ ? h->upload(qlane.data(), NQ) : h->dev<int>(1);
-            d.qkey = h->dev<unsigned long long>(std::max(NQ, 1));
-            d.eq_off = h->upload(eq_off.data(), E + 1);
-            d.ins_edges = h->upload(ins_edges.data(), ins_edges.size());
-            d.n_ins_edges = (int)ins_edges.size();
+            d.qhd = h->upload(qhd.data(), qhd.size());
+            d.qs0 = h->upload(qs0.data(), qs0.size());
+            d.vq = h->upload(vq.data(), vq.size());
+            d.nq = NQ;
             h->nq = NQ;
             h->rec_every = p->record_every;
             std::vector<uint32_t> rid(N);
@@ -494,7 +498,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             h->g_big_max = std::max(1, std::min(256, (N + kTileWindowMin - 1) / kTileWindowMin));
             h->g_big = std::max(1, std::min(256, h->g_tile));
             h->g_scatter_max = std::max(1, std::min(4096, (N + kNT - 1) / kNT));
-            h->g_items = std::max(1, std::min(512, (E + N + kNT - 1) / kNT));
+            h->g_items = std::max(1, std::min(512, (int)((NL + N + kNT - 1) / kNT)));
             h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
             h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
             d.n_blk = h->n_blk;
@@ -507,7 +511,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 d.s[b].edge = h->dev<int32_t>(NV);
                 d.s[b].meta = h->dev<uint32_t>(NV);
                 d.s[b].nxt = h->dev<int32_t>(NV);
-                d.req_edges[b] = h->dev<int>(E);
             }
             d.ent = h->dev<EntryRec>(std::min<size_t>(NV, (size_t)NL + 1));
             d.status = h->dev<uint8_t>(NV);
@@ -844,6 +847,13 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
             HIP_OK(hipMemcpy(d.fin_meta, fmeta.data(), 4 * (size_t)N, hipMemcpyHostToDevice));
         }
         HIP_OK(hipMemcpy(d.qhead, qhead.data(), 4 * qhead.size(), hipMemcpyHostToDevice));
+        if (h->nq > 0) {
+            std::vector<int2> qhd(h->nq);
+            for (int q = 0; q < h->nq; ++q)
+                qhd[q] = qhead[q] < h->qoff[q + 1] ? make_int2(h->dep[h->qveh[qhead[q]]], h->qveh[qhead[q]])
+                                                   : make_int2(INT_MAX, -1);
+            HIP_OK(hipMemcpy(d.qhd, qhd.data(), sizeof(int2) * qhd.size(), hipMemcpyHostToDevice));
+        }
         HIP_OK(hipMemcpy(d.cnt, cnt.data(), 4 * (size_t)h->n_edges, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d.rear, rear.data(), sizeof(LaneRear) * h->n_lanes, hipMemcpyHostToDevice));
         HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * h->n_lanes));

@@ -19,6 +19,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <climits>
 
 #include "device_math.hpp"
 
@@ -64,7 +65,6 @@ struct Ctl {
     int t_a;
     int t_b;
     int n_act[2];
-    int n_req[2];
     int n_ent[2];
     int n_big[2];     // tiles above kTileCapLds, listed for k_tile_big
     unsigned done2;   // commit edge blocks finished (last one scans block sums)
@@ -122,7 +122,9 @@ struct Outbox {       // end-of-edge request of a lane's front vehicle
     float phi;        // fraction of the step at which the stop line was crossed
     uint64_t key;     // admission priority (smaller first)
     int elig;         // set by k_admit: the request passed the no-overlap test
-    int pad;
+    uint32_t tl_cls;  // lane on the next edge | class << 8
+    float v;          // speed after the step
+    int nxt;          // next edge (-1 for an arrival)
 };
 
 struct EntryRec {
@@ -144,29 +146,24 @@ struct Dev {
     const float* lim;
     const int* lanes;
     const int* lane_base;
-    const int* conn_off;
-    const int* conn_to;
-    const uint8_t* conn_mask;
     // vehicles (static)
     int n_veh;
     const int64_t* roff;
     const int* redges;
-    const int* dep;
+    const uint8_t* rmask;       // per route entry: lane mask of the move to the next route edge (0xFF last)
     const uint8_t* cls;
     const float* alpha;
-    const int* ins_gl;          // global entry lane of each vehicle
     const int* due;             // due[t] = vehicles with departure step <= t, t <= max_dep
     // departure queues, one per (entry lane, class), sorted by (departure
     // step, id): all members share the admission test, so only the head can
     // hold the smallest eligible key of its queue
-    const int* qveh;            // vehicle ids, queue by queue
-    const int* qoff;            // [n_queues + 1]
     int* qhead;                 // next vehicle of each queue
+    int2* qhd;                  // head of each queue: {departure step, id}, {INT_MAX, -1} once empty
     const int* qlane;           // global entry lane of each queue
-    unsigned long long* qkey;   // set by k_admit: key of the queue's due, eligible head, else ~0
-    const int* eq_off;          // [n_edges + 1]: queues of edge e
-    const int* ins_edges;       // edges that have a queue
-    int n_ins_edges;
+    const float* qs0;           // s0 of the queue's class (insertion test)
+    const int4* vq;             // per vehicle: {queue, index in the queue order, next vehicle of the queue or -1,
+                                //   its departure step}
+    int nq;
     const uint32_t* rid;        // id used in the random-number counter
     int max_dep;
     const ClassParams* cp;
@@ -204,7 +201,6 @@ struct Dev {
     double* tt_sum;
     unsigned long long* tt_cnt;
     // lists
-    int* req_edges[2];
     EntryRec* ent;
     // big tiles: (first, end) slot pairs, and global scratch for single
     // edges beyond the LDS of a workgroup
@@ -411,13 +407,6 @@ __device__ inline void flush_counters_lds(const Dev& d, const CounterAcc& acc, u
     if (threadIdx.x < cNumCounters && shc[threadIdx.x])
         atomicAdd(&d.counters[threadIdx.x * kCounterCopies + (blockIdx.x % kCounterCopies)],
                   (unsigned long long)shc[threadIdx.x]);
-}
-
-__device__ inline uint32_t conn_mask_of(const Dev& d, int e, int f) {
-    if (f < 0) return 0xFFu;
-    for (int c = d.conn_off[e]; c < d.conn_off[e + 1]; ++c)
-        if (d.conn_to[c] == f) return d.conn_mask[c];
-    return 0u;
 }
 
 __device__ inline bool lane_allowed(uint32_t meta, int nxt, int l) {
@@ -767,6 +756,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             atomicOr(&d.ctl->err, kErrNewPos);
             continue;
         }
+        b.moved[q] = es + below;   // start of the post-change lane's run (moved[q] is not read again)
 
         // kind and gap (A1-A8, A17)
         const ClassParams cpi = scp[m_cls(m)];
@@ -841,6 +831,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         S.nxt[dst] = f;
         b.xn[q] = xnew;
         b.fl[q] = fl;
+        b.pos[q] = __float_as_int(vnew);   // pos[q] is read only by this thread, above
         if (d.trace) {
             TraceRec tr;
             tr.vid = id;
@@ -865,8 +856,6 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const uint32_t el = b.pel[r];
         const bool front = (r == 0) || (b.pel[r - 1] != el);
         const bool rear = (r == n - 1) || (b.pel[r + 1] != el);
-        bool append = false;
-        int e = (int)(el >> 4);
         if (front || rear) {
             const int q = b.inv[r];
             if (q < 0 || q >= n) {
@@ -876,7 +865,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 const int gl = b.lbe[q] + lam;
                 const float xnew = b.xn[q];
                 if (rear) {
-                    const int fr = el_lower_bound(b.pel, n, el);
+                    const int fr = b.moved[q];
                     LanePost lp;
                     lp.stamp = t;
                     lp.start = a0 + fr;
@@ -890,27 +879,29 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                     Outbox ob;
                     ob.stamp = t;
                     ob.elig = 0;
-                    ob.pad = 0;
                     ob.slot = a0 + r;
                     ob.vid = b.vid[q];
                     ob.phi = (xnew == xo) ? 0.0f : (b.L[q] - xo) / (xnew - xo);
+                    ob.v = __int_as_float(b.pos[q]);
+                    ob.nxt = f;
                     if (f < 0) {
                         ob.target = -1;
                         ob.xp = 0.0f;
                         ob.key = 0;
+                        ob.tl_cls = 0;
                     } else {
-                        ob.target = b.lbf[q] + min(lam, (int)(b.lanes2[q] >> 8) - 1);
+                        const int tl = min(lam, (int)(b.lanes2[q] >> 8) - 1);
+                        ob.target = b.lbf[q] + tl;
+                        ob.tl_cls = (uint32_t)tl | (m_cls(b.meta[q]) << 8);
                         ob.xp = xnew - b.L[q];
                         const int hs = m_held(b.meta[q]) ? d.held_since[ob.vid] : t;
                         ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
                     }
                     d.outbox[gl] = ob;
-                    append = atomicMax(&d.req_stamp[e], t) < t;   // first lane of the edge lists it
+                    d.req_stamp[el >> 4] = t;   // the edge has requests this step
                 }
             }
         }
-        const int k = wave_append(&d.ctl->n_req[par], append);
-        if (append) d.req_edges[par][k] = e;
     }
     __syncthreads();
 }
@@ -937,7 +928,6 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         // the later kernels of this step read t_b; lists of the next step
         // are unused during this one
         d.ctl->t_b = t;
-        d.ctl->n_req[par ^ 1] = 0;
         d.ctl->n_ent[par ^ 1] = 0;
         d.ctl->n_big[par ^ 1] = 0;
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
@@ -1032,23 +1022,6 @@ __device__ inline bool transfer_eligible(const Dev& d, const Outbox& ob, int t) 
     return p.stamp != t || (p.rear_xm - ob.xp >= 0.0f);
 }
 
-__device__ inline bool insert_eligible(const Dev& d, int vid, int t) {
-    const LanePost p = d.post[d.ins_gl[vid]];
-    return p.stamp != t || (p.rear_xm >= d.cp[d.cls[vid]].s0);
-}
-
-__device__ inline unsigned long long insert_key(const Dev& d, int vid) {
-    return (1ull << 63) | ((unsigned long long)(uint32_t)d.dep[vid] << 32) | (uint32_t)vid;
-}
-
-// head of departure queue q if it is due at step t, else -1
-__device__ inline int queue_due_head(const Dev& d, int q, int t) {
-    const int h = d.qhead[q];
-    if (h >= d.qoff[q + 1]) return -1;
-    const int vid = d.qveh[h];
-    return d.dep[vid] <= t ? vid : -1;
-}
-
 // An eligible request lowers the lane's 64-bit key with atomicMin; the
 // smallest key wins whatever the order of the atomics.  The request that
 // finds the lane unclaimed also counts one entry for the lane's edge (exactly
@@ -1061,31 +1034,29 @@ __device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t
     }
 }
 
+// One item per lane (its front may have asked to leave the edge this step)
+// and one per departure queue.  A request is eligible if it does not overlap
+// the target lane's rear after the move; a due queue head if the lane's rear
+// leaves it s0 at x = 0.
 __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
-    const int t = d.ctl->t_a, par = t & 1;
-    const int nreq = d.ctl->n_req[par];
-    const int total = nreq + d.n_ins_edges;
+    const int t = d.ctl->t_a;
+    const int nl = d.n_lanes_total;
+    const int total = nl + d.nq;
     for (int i = blockIdx.x * kNT + threadIdx.x; i < total; i += gridDim.x * kNT) {
-        if (i < nreq) {
-            const int e = d.req_edges[par][i];
-            const int base = d.lane_base[e];
-            for (int l = 0; l < d.lanes[e]; ++l) {
-                const Outbox ob = d.outbox[base + l];
-                if (ob.stamp != t || ob.target < 0) continue;
-                const bool ok = transfer_eligible(d, ob, t);
-                d.outbox[base + l].elig = ok ? 1 : 0;
-                if (ok) claim(d, ob.target, ob.key, t);
-            }
+        if (i < nl) {
+            const Outbox ob = d.outbox[i];
+            if (ob.stamp != t || ob.target < 0) continue;   // no request, or an arrival
+            const bool ok = transfer_eligible(d, ob, t);
+            d.outbox[i].elig = ok ? 1 : 0;
+            if (ok) claim(d, ob.target, ob.key, t);
         } else {
-            const int e = d.ins_edges[i - nreq];
-            for (int q = d.eq_off[e]; q < d.eq_off[e + 1]; ++q) {
-                const int vid = queue_due_head(d, q, t);
-                unsigned long long key = ~0ull;
-                if (vid >= 0 && insert_eligible(d, vid, t)) {
-                    key = insert_key(d, vid);
-                    claim(d, d.qlane[q], key, t);
-                }
-                d.qkey[q] = key;
+            const int q = i - nl;
+            const int2 hd = d.qhd[q];
+            if (hd.x <= t) {
+                const int gl = d.qlane[q];
+                const LanePost p = d.post[gl];
+                if (p.stamp != t || p.rear_xm >= d.qs0[q])
+                    claim(d, gl, (1ull << 63) | ((unsigned long long)(uint32_t)hd.x << 32) | (uint32_t)hd.y, t);
             }
         }
     }
@@ -1169,25 +1140,24 @@ __device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, C
 }
 
 // entry records of the transfers that won, at slots k0, k0 + 1, ...
-__device__ inline void write_entries(const Dev& d, const Slots& S, int e, unsigned winmask, int k0) {
+__device__ inline void write_entries(const Dev& d, int e, unsigned winmask, int k0) {
     const int base = d.lane_base[e];
     int k = k0;
     for (int l = 0; l < 8; ++l) {
         if (!((winmask >> l) & 1u)) continue;
         const Outbox ob = d.outbox[base + l];
-        const uint32_t m = S.meta[ob.slot];
-        const int f = S.nxt[ob.slot];
-        const int kk = d.cursor[ob.vid] + 1;
+        const int kk = d.cursor[ob.vid] + 1;     // route index of the next edge ob.nxt
         d.cursor[ob.vid] = kk;
-        const int64_t pos = d.roff[ob.vid] + kk + 1;
+        const int64_t r0 = d.roff[ob.vid];
+        const int64_t pos = r0 + kk + 1;
         const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
         EntryRec r;
         r.x = ob.xp;
-        r.v = S.v[ob.slot];
+        r.v = ob.v;
         r.vid = ob.vid;
-        r.edge = f;
+        r.edge = ob.nxt;
         r.gl = ob.target;
-        r.meta = m_make(ob.target - d.lane_base[f], false, false, 0, m_cls(m), conn_mask_of(d, f, nn));
+        r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)(ob.tl_cls >> 8), d.rmask[r0 + kk]);
         r.nxt = nn;
         r.pad = 0;
         d.held_since[ob.vid] = -1;
@@ -1212,16 +1182,12 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     const int e = blockIdx.x * kEdgeBlock + threadIdx.x;
     int c = 0;
     unsigned winmask = 0;
-    int insq[8];
+    int ins_vid[8], ins_gl[8];
     int nins = 0;
     if (e < d.n_edges) {
         int nex = 0;
         unsigned exmask = 0;
         if (d.req_stamp[e] == t) commit_edge(d, S, e, t, acc, nex, exmask, winmask);
-        for (int q = d.eq_off[e]; q < d.eq_off[e + 1]; ++q) {
-            const unsigned long long key = d.qkey[q];
-            if (key != ~0ull && d.win[d.qlane[q]] == key) insq[nins++] = q;   // at most one winner per lane
-        }
         c = d.cnt[e] - nex + d.entries[e];
         d.cnt[e] = c;
         d.entries[e] = 0;
@@ -1233,7 +1199,14 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
                 const LanePost p = d.post[gl];
                 int nc = (p.stamp == t) ? p.cnt : 0;
                 if ((exmask >> l) & 1u) nc -= 1;
-                if (d.enter_stamp[gl] == t) nc += 1;
+                if (d.enter_stamp[gl] == t) {   // the lane was claimed: by a departure if the key says so
+                    nc += 1;
+                    const unsigned long long w = d.win[gl];
+                    if (w >> 63) {
+                        ins_vid[nins] = (int)(uint32_t)w;
+                        ins_gl[nins++] = gl;
+                    }
+                }
                 d.lane_rel[gl] = o;
                 d.lane_newcnt[gl] = nc;
                 o += nc;
@@ -1242,14 +1215,14 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     }
     int k = wave_reserve(&d.ctl->n_ent[par], __popc(winmask) + nins);
     if (winmask) {
-        write_entries(d, S, e, winmask, k);
+        write_entries(d, e, winmask, k);
         k += __popc(winmask);
     }
     for (int a = 0; a < nins; ++a) {
-        const int q = insq[a];
-        const int vid = d.qveh[d.qhead[q]];
-        d.qhead[q] += 1;
-        const int g = d.ins_gl[vid];
+        const int vid = ins_vid[a], g = ins_gl[a];
+        const int4 vq = d.vq[vid];               // vid is the head of queue vq.x
+        d.qhead[vq.x] = vq.y + 1;
+        d.qhd[vq.x] = vq.z >= 0 ? make_int2(vq.w, vq.z) : make_int2(INT_MAX, -1);
         const int64_t r0 = d.roff[vid];
         const int e0 = d.redges[r0];
         const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
@@ -1259,7 +1232,7 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         r.vid = (uint32_t)vid;
         r.edge = e0;
         r.gl = g;
-        r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], conn_mask_of(d, e0, nn));
+        r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], d.rmask[r0]);
         r.nxt = nn;
         r.pad = 0;
         d.status[vid] = kActive;
