@@ -493,10 +493,17 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 max_edge = std::max(max_edge, (long long)h->lanes[e] * ((long long)(h->L[e] / len_min) + 1));
             const long long cap_all = std::min<long long>(std::max(N, 1), (long long)kTileWindowMax - 1 + max_edge);
             d.big_cap = (int)std::max<long long>(kTileCapLds + 1, cap_all);
-            d.tile_window = kTileWindowMax;
-            h->g_tile = std::max(1, std::min(1024, (N + kTileWindowMax - 1) / kTileWindowMax));
+            {   // tile workgroups resident at once on this device
+                int dev = 0, cus = 0, per_cu = 0;
+                HIP_OK(hipGetDevice(&dev));
+                HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_step, kNT, 0));
+                d.tile_target = std::max(1, cus * std::max(per_cu, 1));
+            }
+            d.tile_window = 0;
+            h->g_tile = std::max(1, std::min(1024, (N + kTileWindowMin - 1) / kTileWindowMin));
             h->g_big_max = std::max(1, std::min(256, (N + kTileWindowMin - 1) / kTileWindowMin));
-            h->g_big = std::max(1, std::min(256, h->g_tile));
+            h->g_big = std::max(1, std::min(32, h->g_big_max));
             h->g_scatter_max = std::max(1, std::min(4096, (N + kNT - 1) / kNT));
             h->g_items = std::max(1, std::min(512, (int)((NL + N + kNT - 1) / kNT)));
             h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
@@ -1095,7 +1102,7 @@ sim_status sim_get_schedule(const sim_handle* h, int32_t* sched) {
 
 namespace {
 bool set_schedule(sim_handle* h, int w, int g1, int g2, int g3, int g4) {
-    if (w < kTileWindowMin || w > kTileWindowMax || (w & (w - 1)) != 0) return false;
+    if (w != 0 && (w < kTileWindowMin || w > kTileWindowMax || (w & (w - 1)) != 0)) return false;
     if (g1 < 1 || g2 < 1 || g2 > h->g_big_max || g3 < 1 || g4 < 1 || g4 > h->g_scatter_max) return false;
     h->d.tile_window = w;
     h->g_tile = g1;
@@ -1149,15 +1156,18 @@ sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
             int w, g1, g2, g3, g4;
         };
         std::vector<Cand> cands;
-        for (int w : {64, 128, 256})
+        for (int w : {0, 64, 128, 256})
             for (int g1 : {512, 1024})
-                for (int g4 : {1024, 4096}) {
-                    const int g1c = std::max(1, std::min(g1, (N + w - 1) / w));
-                    const int g4c = std::max(1, std::min(g4, h->g_scatter_max));
-                    bool dup = false;
-                    for (auto& c : cands) dup = dup || (c.w == w && c.g1 == g1c && c.g4 == g4c);
-                    if (!dup) cands.push_back(Cand{w, g1c, g20, g30, g4c});
-                }
+                for (int g2 : {32, 256})
+                    for (int g4 : {1024, 4096}) {
+                        const int g1c = std::max(1, std::min(g1, (N + (w ? w : kTileWindowMin) - 1) /
+                                                                     (w ? w : kTileWindowMin)));
+                        const int g2c = std::max(1, std::min(g2, h->g_big_max));
+                        const int g4c = std::max(1, std::min(g4, h->g_scatter_max));
+                        bool dup = false;
+                        for (auto& c : cands) dup = dup || (c.w == w && c.g1 == g1c && c.g2 == g2c && c.g4 == g4c);
+                        if (!dup) cands.push_back(Cand{w, g1c, g2c, g30, g4c});
+                    }
         double best_ms = 1e30;
         Cand best{w0, g10, g20, g30, g40};
         hipEvent_t e0, e1;

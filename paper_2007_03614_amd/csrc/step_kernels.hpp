@@ -205,7 +205,8 @@ struct Dev {
     // big tiles: (first, end) slot pairs, and global scratch for single
     // edges beyond the LDS of a workgroup
     int* big_list;
-    int tile_window;
+    int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
+    int tile_target;            // tiles per step that run in one round of resident workgroups
     // traced re-run: record of step t at trace[(t - trace_t0) * trace_stride + slot]
     TraceRec* trace;
     int trace_t0;
@@ -933,7 +934,13 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
-    const int W = d.tile_window;
+    // tile window: fixed by the schedule, or (0) the smallest of 64, 128,
+    // 256 slots whose tiles fit in one round of resident workgroups
+    int W = d.tile_window;
+    if (W == 0) {
+        W = kTileWindowMin;
+        while (W < kTileWindowMax && (n + W - 1) / W > d.tile_target) W *= 2;
+    }
     const int ntile = (n + W - 1) / W;
     const int32_t* edge = d.s[par].edge;
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
