@@ -32,7 +32,8 @@ constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parame
 constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
 constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
-constexpr int kBigCapLds = 1536;         // vehicles per big tile piece staged in LDS (138 KiB)
+constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
+constexpr int kScanLdsMax = 4096;        // edge blocks whose offsets k_scatter scans in LDS (16 KiB)
 constexpr int kCounterCopies = 32;       // each counter is spread over 32 slots (fewer colliding atomics)
 
 // ---- vehicle meta word ---------------------------------------------------
@@ -60,17 +61,16 @@ enum Counter {
 struct Ctl {
     // The step number, kept twice so that no kernel has to change a value its
     // own workgroups are still reading: the tile kernels and k_admit read t_a,
-    // k_commit and k_scatter read t_b.  k_tile_step sets t_b = t_a; the last
-    // commit workgroup sets t_a = t + 1.
+    // k_commit and k_scatter read t_b.  k_tile_step sets t_b = t_a; the
+    // workgroup that finishes the step (finish_step) sets t_a = t + 1.
     int t_a;
     int t_b;
     int n_act[2];
     int n_ent[2];
     int n_big[2];     // tiles above kTileCapLds, listed for k_tile_big
-    unsigned done2;   // commit edge blocks finished (last one scans block sums)
     int err;          // non-zero: a layout bound check failed (see kErr*)
     int n_departed;   // vehicles admitted from the departure queues so far
-    int pad[4];
+    int pad[5];
 };
 
 enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
@@ -229,7 +229,10 @@ struct TileBuf {
     int* mpref;         // movers before index q (n + 1 entries)
     int* lastm;         // last mover at or before q in the tile, or -1
     int* lasts;         // last stayer at or before q, or -1
-    int* runst;         // first index of q's run
+    int* rk;            // index of q's run (maximal group of one edge and lane in S_t)
+    uint32_t* run_el;   // per run: edge << 4 | lane; run_el[nruns] = ~0
+    int* run_st;        // per run: first index; run_st[nruns] = n
+    int* nruns;         // [1]
     float* xn;          // Phase 2 position
     uint32_t* fl;       // Phase 2 flags
     uint32_t* pel;      // post-change (edge, lane), permuted to the new order
@@ -245,7 +248,7 @@ struct TileBuf {
     uint32_t* rid;      // counter id of its draws
 };
 
-constexpr int kTileBytesPerVeh = 92;   // 23 four-byte arrays
+constexpr int kTileBytesPerVeh = 100;  // 25 four-byte arrays (plus a few words within the 64-byte slack)
 __host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * kTileBytesPerVeh + 64; }
 
 __device__ inline TileBuf carve(char* base, int cap) {
@@ -263,7 +266,10 @@ __device__ inline TileBuf carve(char* base, int cap) {
     b.mpref = (int*)take(cap + 1);
     b.lastm = (int*)take(cap);
     b.lasts = (int*)take(cap);
-    b.runst = (int*)take(cap);
+    b.rk = (int*)take(cap);
+    b.run_el = (uint32_t*)take(cap + 1);
+    b.run_st = (int*)take(cap + 1);
+    b.nruns = (int*)take(1);
     b.xn = (float*)take(cap);
     b.fl = (uint32_t*)take(cap);
     b.pel = (uint32_t*)take(cap);
@@ -281,31 +287,35 @@ __device__ inline TileBuf carve(char* base, int cap) {
 // flags of Phase 2
 constexpr uint32_t F_WHOLD = 1u, F_VEH = 2u;
 
-// first index in [0, n) whose element does not precede (el, x, id) in the
-// tile order (el ascending, x descending, id descending)
-__device__ inline int tile_lower_bound(const TileBuf& b, int n, uint32_t el, float x, uint32_t id) {
-    int lo = 0, hi = n;
-    while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        const uint32_t e2 = b.el[mid];
-        bool before;
-        if (e2 != el) {
-            before = e2 < el;
-        } else {
-            const float x2 = b.x[mid];
-            before = (x2 > x) || (x2 == x && b.vid[mid] > id);
+// Index of the first run whose key is not below `key`, where key is a lane
+// of the edge of run k0 or one past its last lane.  An edge has at most 8
+// lanes, so that run lies within 8 runs of k0: a few independent LDS reads
+// instead of a search of the tile.
+__device__ inline int run_lower(const TileBuf& b, int nruns, int k0, uint32_t key) {
+    int k = k0;
+    if (key > b.run_el[k0]) {
+#pragma unroll
+        for (int j = 1; j <= 8; ++j) {
+            const int kk = k0 + j;
+            if (kk <= nruns && b.run_el[kk] < key) k = kk;
         }
-        if (before) lo = mid + 1;
-        else hi = mid;
+        return k + 1;
     }
-    return lo;
+#pragma unroll
+    for (int j = 1; j <= 8; ++j) {
+        const int kk = k0 - j;
+        if (kk >= 0 && b.run_el[kk] >= key) k = kk;
+    }
+    return k;
 }
 
-__device__ inline int el_lower_bound(const uint32_t* el, int n, uint32_t key) {
-    int lo = 0, hi = n;
+// first index in [lo, hi), part of one run, that does not precede (x, id)
+// in the tile order (x descending, id descending)
+__device__ inline int run_insert(const TileBuf& b, int lo, int hi, float x, uint32_t id) {
     while (lo < hi) {
         const int mid = (lo + hi) >> 1;
-        if (el[mid] < key) lo = mid + 1;
+        const float x2 = b.x[mid];
+        if ((x2 > x) || (x2 == x && b.vid[mid] > id)) lo = mid + 1;
         else hi = mid;
     }
     return lo;
@@ -527,6 +537,36 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     if (tid < 2) dq.n[tid] = 0;
     __syncthreads();
 
+    // ---- runs of S_t (tile order: edge, lane, then x and id descending)
+    {
+        const int chunk = (n + NT - 1) / NT;
+        const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
+        int loc = 0;
+        for (int q = lo; q < hi; ++q) loc += (q == 0 || b.el[q] != b.el[q - 1]) ? 1 : 0;
+        const Scan4 r = wg_exclusive_scan4<NT>(Scan4{loc, -1, -1, -1}, wsh4);
+        int k = r.s - 1;
+        for (int q = lo; q < hi; ++q) {
+            if (q == 0 || b.el[q] != b.el[q - 1]) {
+                ++k;
+                b.run_el[k] = b.el[q];
+                b.run_st[k] = q;
+            }
+            b.rk[q] = k;
+        }
+        if (hi == n && lo < hi) {
+            b.run_el[k + 1] = ~0u;
+            b.run_st[k + 1] = n;
+            *b.nruns = k + 1;
+        }
+        if (n == 0 && tid == 0) {
+            b.run_el[0] = ~0u;
+            b.run_st[0] = 0;
+            *b.nruns = 0;
+        }
+    }
+    __syncthreads();
+    const int nruns = *b.nruns;
+
     // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t.
     // Few vehicles need a Philox draw, and a block costs thousands of
     // cycles, so a wavefront in which one lane draws would make the other 63
@@ -535,7 +575,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     // noise of Eqs. (3)-(4), whose need depends on the mandatory flag.
     int* const u1 = b.lastm;                      // Eq. (2) uniform words (scratch until the scans)
     int* const na = b.lasts;                      // noise word sums, leading side
-    int* const nb = b.runst;                      // noise word sums, lagging side
+    int* const nb = b.mpref;                      // noise word sums, lagging side
     float* const Ga = b.xn;                       // gaps and critical gaps of pending decisions
     float* const ca = (float*)b.fl;               // (scratch until Phase 2)
     float* const Gb = (float*)b.pel;
@@ -585,7 +625,9 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             const int lp = l + dir;
             if (lp >= 0 && lp < (int)(b.lanes2[q] & 255u)) {
                 const uint32_t elp = (el & ~15u) | (uint32_t)lp;
-                pos = tile_lower_bound(b, n, elp, xi, b.vid[q]);
+                const int kp = run_lower(b, nruns, b.rk[q], elp);
+                pos = b.run_st[kp];
+                if (b.run_el[kp] == elp) pos = run_insert(b, pos, b.run_st[kp + 1], xi, b.vid[q]);
                 const int la = (pos > 0 && b.el[pos - 1] == elp) ? pos - 1 : -1;
                 const int lb = (pos < n && b.el[pos] == elp) ? pos : -1;
                 const uint32_t mask = f < 0 ? 0xFFu : m_mask(m);
@@ -681,7 +723,6 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             const int mv = b.moved[q];
             loc.s += mv;
             if (mv) loc.a = q; else loc.b = q;
-            if (q == 0 || b.el[q] != b.el[q - 1]) loc.c = q;
         }
         Scan4 run = wg_exclusive_scan4<NT>(loc, wsh4);
         for (int q = lo; q < hi; ++q) {
@@ -689,10 +730,8 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             b.mpref[q] = run.s;
             run.s += mv;
             if (mv) run.a = q; else run.b = q;
-            if (q == 0 || b.el[q] != b.el[q - 1]) run.c = q;
             b.lastm[q] = run.a;
             b.lasts[q] = run.b;
-            b.runst[q] = run.c;
         }
         if (hi == n && lo < hi) b.mpref[n] = run.s;
         if (n == 0 && tid == 0) b.mpref[0] = 0;
@@ -716,23 +755,27 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         // leader candidates and rank in the post-change lane
         int c1 = -1, c2 = -1, rank;
         const int mu = lam - dir;   // lane whose movers enter lam
+        const int k0 = b.rk[q];
+        const int rs = b.run_st[k0];
+        int sl;                     // start of lam's run in S_t (lower bound if empty)
         if (!mv) {
-            const int rs = b.runst[q];
+            sl = rs;
             if (q > 0 && b.lasts[q - 1] >= rs) c1 = b.lasts[q - 1];
             int mov_ahead = 0;
             if (mu >= 0 && mu < lanes_e) {
                 const uint32_t emu = e0 | (uint32_t)mu;
-                const int p2 = tile_lower_bound(b, n, emu, xi, id);
-                const int st = el_lower_bound(b.el, n, emu);
+                const int kmu = run_lower(b, nruns, k0, emu);
+                const int st = b.run_st[kmu];
+                const int p2 = (b.run_el[kmu] == emu) ? run_insert(b, st, b.run_st[kmu + 1], xi, id) : st;
                 if (p2 > 0 && b.lastm[p2 - 1] >= st) c2 = b.lastm[p2 - 1];
                 mov_ahead = b.mpref[p2] - b.mpref[st];
             }
             rank = ((q - rs) - (b.mpref[q] - b.mpref[rs])) + mov_ahead;
         } else {
             const int p = b.pos[q];
-            const int st = el_lower_bound(b.el, n, elam);
+            const int st = b.run_st[run_lower(b, nruns, k0, elam)];
+            sl = st;
             if (p > 0 && b.lasts[p - 1] >= st) c1 = b.lasts[p - 1];
-            const int rs = b.runst[q];
             if (q > 0 && b.lastm[q - 1] >= rs) c2 = b.lastm[q - 1];
             rank = ((p - st) - (b.mpref[p] - b.mpref[st])) + (b.mpref[q] - b.mpref[rs]);
         }
@@ -742,14 +785,13 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             else if (b.x[c2] < b.x[j] || (b.x[c2] == b.x[j] && b.vid[c2] < b.vid[j])) j = c2;
         }
         // post-change vehicles of this edge in lanes below lam
-        const int es = el_lower_bound(b.el, n, e0);
-        const int sl = el_lower_bound(b.el, n, elam);
+        const int es = b.run_st[run_lower(b, nruns, k0, e0)];
         int below = sl - es;
         if (dir < 0) {
-            const int ee = el_lower_bound(b.el, n, elam + 1);
+            const int ee = b.run_st[run_lower(b, nruns, k0, elam + 1)];
             below += b.mpref[ee] - b.mpref[sl];
         } else if (lam >= 1) {
-            const int s0 = el_lower_bound(b.el, n, elam - 1);
+            const int s0 = b.run_st[run_lower(b, nruns, k0, elam - 1)];
             below -= b.mpref[sl] - b.mpref[s0];
         }
         const int newpos = es + below + rank;
@@ -1179,7 +1221,6 @@ __device__ inline void write_entries(const Dev& d, int e, unsigned winmask, int 
 __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     __shared__ unsigned shc[cNumCounters];
     __shared__ Scan4 wsh4[kWaves];
-    __shared__ int last;
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     __syncthreads();
     const int t = d.ctl->t_b, par = t & 1;
@@ -1252,47 +1293,78 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     Scan4 run = wg_exclusive_scan4(Scan4{c, -1, -1, -1}, wsh4);
     if (e < d.n_edges) d.edge_rel[e] = run.s;
     if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = run.s + c;
-    flush_counters_lds(d, acc, shc);
-    if (threadIdx.x == kNT - 1) {
-        if (shc[cDeparted]) atomicAdd(&d.ctl->n_departed, (int)shc[cDeparted]);
-        __threadfence();
-        last = (atomicAdd(&d.ctl->done2, 1u) == (unsigned)d.n_blk - 1u);
+    flush_counters_lds(d, acc, shc);   // ends with a barrier: shc is complete
+    if (threadIdx.x == 0 && shc[cDeparted]) atomicAdd(&d.ctl->n_departed, (int)shc[cDeparted]);
+}
+
+// ---- offsets of the edge blocks and the end of the step --------------------
+// Exclusive scan of the commit workgroups' vehicle counts into off[0, nb);
+// returns the total (the active vehicles of the next step).  The sums were
+// written by k_commit, a previous kernel, so no fence is needed: no workgroup
+// waits for another inside a kernel, which on a GPU of several L2 caches
+// would cost a write-back of the L2 at every release.
+template <int NT>
+__device__ inline int scan_block_sums(const int* blk_sum, int nb, int* off, Scan4* wsh4, int* tot) {
+    const int chunk = (nb + NT - 1) / NT;
+    const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
+    int loc = 0;
+    for (int i = lo; i < hi; ++i) loc += blk_sum[i];
+    const Scan4 r = wg_exclusive_scan4<NT>(Scan4{loc, -1, -1, -1}, wsh4);
+    int o = r.s;
+    for (int i = lo; i < hi; ++i) {
+        off[i] = o;
+        o += blk_sum[i];
     }
+    if (hi == nb && lo < hi) *tot = o;
     __syncthreads();
-    if (last) {   // every workgroup sum is written: scan them (one workgroup)
-        __threadfence();
-        const int nb = d.n_blk;
-        const int chunk = (nb + kNT - 1) / kNT;
-        const int lo = min(nb, (int)threadIdx.x * chunk), hi = min(nb, lo + chunk);
-        int loc = 0;
-        for (int i = lo; i < hi; ++i) loc += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        Scan4 r2 = wg_exclusive_scan4(Scan4{loc, -1, -1, -1}, wsh4);
-        int o2 = r2.s;
-        for (int i = lo; i < hi; ++i) {
-            d.blk_off[i] = o2;
-            o2 += __hip_atomic_load(&d.blk_sum[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        if (threadIdx.x == kNT - 1) {
-            d.ctl->n_act[par ^ 1] = o2;
-            d.ctl->done2 = 0;
-            // every due vehicle still waiting asked for a lane this step and was refused
-            const int due_now = d.max_dep < 0 ? 0 : d.due[min(t, d.max_dep)];
-            const int departed = __hip_atomic_load(&d.ctl->n_departed, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (due_now > departed)
-                atomicAdd(&d.counters[cInsertDenied * kCounterCopies], (unsigned long long)(due_now - departed));
-            d.ctl->t_a = t + 1;   // k_tile_step and k_admit of this step are done
-        }
-    }
+    return *tot;
+}
+
+// n_act of the next step, refused departures of this one (every due vehicle
+// still waiting asked for a lane and was refused), and the step counter
+__device__ inline void finish_step(const Dev& d, int t, int par, int total) {
+    d.ctl->n_act[par ^ 1] = total;
+    const int due_now = d.max_dep < 0 ? 0 : d.due[min(t, d.max_dep)];
+    const int departed = d.ctl->n_departed;
+    if (due_now > departed)
+        atomicAdd(&d.counters[cInsertDenied * kCounterCopies], (unsigned long long)(due_now - departed));
+    d.ctl->t_a = t + 1;   // the tile kernels and k_admit of this step are done
+}
+
+// Networks with more edge blocks than kScanLdsMax: one workgroup scans the
+// block offsets into global memory before k_scatter.
+__global__ void __launch_bounds__(kBigNT) k_blkscan(Dev d) {
+    __shared__ Scan4 wsh4[kBigNT / 64];
+    __shared__ int tot;
+    const int t = d.ctl->t_b, par = t & 1;
+    const int total = scan_block_sums<kBigNT>(d.blk_sum, d.n_blk, d.blk_off, wsh4, &tot);
+    if (threadIdx.x == 0) finish_step(d, t, par, total);
 }
 
 // ---- next layout -----------------------------------------------------------
 // slot of a vehicle in the next layout:
 //   block offset + edge offset in block + lane offset in edge + rank in lane
+// kLds: the workgroup scans the block offsets itself into LDS (at most
+// kScanLdsMax edge blocks), and workgroup 0 finishes the step; otherwise
+// k_blkscan has done both.
+template <bool kLds>
 __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
+    __shared__ int soff[kLds ? kScanLdsMax : 1];
+    __shared__ Scan4 wsh4[kWaves];
+    __shared__ int tot;
     const int t = d.ctl->t_b, par = t & 1;
     const int nold = d.ctl->n_act[par];
     const int nent = d.ctl->n_ent[par];
-    const int nnew = d.ctl->n_act[par ^ 1];
+    const int* boff;
+    int nnew;
+    if (kLds) {
+        nnew = scan_block_sums<kNT>(d.blk_sum, d.n_blk, soff, wsh4, &tot);
+        boff = soff;
+        if (blockIdx.x == 0 && threadIdx.x == 0) finish_step(d, t, par, nnew);
+    } else {
+        boff = d.blk_off;
+        nnew = d.ctl->n_act[par ^ 1];
+    }
     const Slots A = d.s[par], B = d.s[par ^ 1];
     for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nent; i += gridDim.x * kNT) {
         float x, v;
@@ -1330,7 +1402,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             nxt = r.nxt;
             d.win[gl] = ~0ull;                    // lane free for the next step's claims
         }
-        const int dst = d.blk_off[edge / kEdgeBlock] + d.edge_rel[edge] + d.lane_rel[gl] + nr;
+        const int dst = boff[edge / kEdgeBlock] + d.edge_rel[edge] + d.lane_rel[gl] + nr;
         if (dst < 0 || dst >= nnew) {
             atomicOr(&d.ctl->err, kErrScatter);
             continue;

@@ -66,6 +66,29 @@ def test_member_matches_oracle(M, oracle_mod, small_ensemble):
         assert compare_states(member, o.state(), f"step {cp}")
 
 
+def test_large_ensemble_scans_block_offsets_in_global_memory(M):
+    """3,000 scenarios of the 10x10 grid make a union network of 1.08M edges,
+    more edge blocks than one workgroup scans in LDS: the block offsets then
+    come from their own kernel.  Members still equal their standalone runs."""
+    master, scen = W.config4(n_scen=3000, base=20, n_steps=600)
+    assert master.net.n_edges * len(scen) > 4096 * 256
+    ens = M.Sim(master, scenarios=scen)
+    ens.step(600)
+    es = ens.state()
+    off = ens.offsets()
+    E = master.net.n_edges
+    for k in (0, 1500, 2999):
+        n, red = scen[k]
+        solo = M.Sim(W.scenario_workload(master, n, red))
+        solo.step(600)
+        ss = solo.state()
+        sl = slice(int(off[k]), int(off[k + 1]))
+        for f in FIELDS:
+            assert np.array_equal(es[f][sl], ss[f]), (k, f)
+        assert np.array_equal(es["edge"][sl] - k * E, ss["edge"]), k
+    assert es["counters"][list(M.COUNTERS).index("arrived")] > 0
+
+
 def test_autotune_keeps_results_and_caches(M, c1, tmp_path):
     ref = M.Sim(c1)
     ref.step(1500)
