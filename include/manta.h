@@ -180,8 +180,8 @@ sim_status sim_autotune(sim_handle *h, const char *cache_path, int32_t steps_per
 
 /* Current schedule: [tile_window, tile_workgroups, big_tile_workgroups,
  * admit_workgroups, scatter_workgroups].  tile_window 0 (the default) picks
- * 64, 128 or 256 slots at every step: the smallest whose tiles fit in one
- * round of the tile workgroups the device holds at once. */
+ * 64 or 128 slots at every step: the smallest whose tiles fit in one round
+ * of the tile workgroups the device holds at once. */
 sim_status sim_get_schedule(const sim_handle *h, int32_t *sched);
 
 /* Stream for all later device work of h (a hipStream_t; NULL = null stream).

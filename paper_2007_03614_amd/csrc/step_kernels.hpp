@@ -29,7 +29,9 @@ constexpr int kNT = 256;                 // threads per workgroup (4 waves)
 constexpr int kWaves = kNT / 64;
 constexpr int kTileWindowMax = 256;      // a tile = the edges whose first slot lies in a window of
 constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256)
-constexpr int kTileCapLds = 512;         // tiles up to this size are staged in LDS
+constexpr int kTileCapLds = 384;         // tiles up to this size are staged in LDS (4 workgroups per CU)
+constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
+constexpr int kTileDrawTasks = 128;      // listed Philox blocks per tile round (more are computed in place)
 constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
@@ -957,9 +959,9 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ int wsh[kWaves];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
-    __shared__ uint2 dtask[kNT];
+    __shared__ uint2 dtask[kTileDrawTasks];
     __shared__ int dcount[2];
-    const DrawQ dq{dtask, dcount, kNT};
+    const DrawQ dq{dtask, dcount, kTileDrawTasks};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     const int t = d.ctl->t_a, par = t & 1;
@@ -976,12 +978,12 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
-    // tile window: fixed by the schedule, or (0) the smallest of 64, 128,
-    // 256 slots whose tiles fit in one round of resident workgroups
+    // tile window: fixed by the schedule, or (0) the smallest of 64 and 128
+    // slots whose tiles fit in one round of resident workgroups
     int W = d.tile_window;
     if (W == 0) {
         W = kTileWindowMin;
-        while (W < kTileWindowMax && (n + W - 1) / W > d.tile_target) W *= 2;
+        while (W < kTileWindowAuto && (n + W - 1) / W > d.tile_target) W *= 2;
     }
     const int ntile = (n + W - 1) / W;
     const int32_t* edge = d.s[par].edge;
