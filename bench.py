@@ -10,9 +10,13 @@ device memory when the timed region starts.
 
 value = vehicle-updates/s = sum over the timed steps of the vehicles active at
 each step's start, divided by the device time of those steps (HIP events on
-the simulation's stream).  The roofline object covers the dominant kernel
-(k_tile_step): algorithmic bytes = 48 B per vehicle-update (read and write
-of the 24-byte sorted vehicle record), over its summed event-measured time.
+the simulation's stream around sim_step, which replays one captured graph per
+step).  The same steps are then run again kernel by kernel between HIP
+events to time each kernel.  The roofline object covers the tile kernels
+(k_tile_step, plus k_tile_big for tiles above one workgroup's LDS), which do
+Phases 1-2 of every vehicle: algorithmic bytes = 48 B per vehicle-update
+(read and write of the 24-byte sorted vehicle record), over their summed
+event-measured time.
 """
 import argparse
 import json
@@ -43,28 +47,37 @@ def kernel_source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def traffic_from(fetch_json: str, write_json: str, kernel: str = "k_tile_step",
+def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step", "k_tile_big"),
                  probe_mib: int = 256) -> dict:
-    """HBM bytes per dispatch of `kernel` from two --pmc summaries (FETCH_SIZE,
-    WRITE_SIZE in KiB per dispatch), each scaled by what the same counter
-    reads for the copy probe (torch's add of probe_mib MiB: reads and writes
-    probe_mib MiB each)."""
+    """HBM bytes per step of the tile kernels (each launched once per step)
+    from two --pmc summaries (FETCH_SIZE, WRITE_SIZE in KiB per dispatch),
+    each counter scaled by what it reads for the copy probe (torch's add of
+    probe_mib MiB: reads and writes probe_mib MiB each)."""
     f = json.load(open(fetch_json))["kernels"]
     w = json.load(open(write_json))["kernels"]
 
-    def pick(d, key):
-        ks = [k for k in d if kernel + "(" in k]
-        probe = [k for k in d if "add" in k.lower() and "fill" not in k.lower() and key in d[k]]
-        if len(ks) != 1 or len(probe) != 1:
-            raise SystemExit(f"cannot identify kernel/probe in summary: {ks} {probe}")
-        return d[ks[0]][key], d[probe[0]][key], probe[0]
+    def probe(d, key):
+        p = [k for k in d if "add" in k.lower() and "fill" not in k.lower() and key in d[k]]
+        if len(p) != 1:
+            raise SystemExit(f"cannot identify the copy probe in summary: {p}")
+        return d[p[0]][key], p[0]
 
-    kf, pf, pname = pick(f, "FETCH_SIZE")
-    kw, pw, _ = pick(w, "WRITE_SIZE")
+    def per_kernel(d, key):
+        out = {}
+        for kn in kernels:
+            ks = [k for k in d if kn + "(" in k]
+            if len(ks) != 1:
+                raise SystemExit(f"cannot identify {kn} in summary: {ks}")
+            out[kn] = d[ks[0]][key]
+        return out
+
+    pf, pname = probe(f, "FETCH_SIZE")
+    pw, _ = probe(w, "WRITE_SIZE")
+    kf, kw = per_kernel(f, "FETCH_SIZE"), per_kernel(w, "WRITE_SIZE")
     known = probe_mib * 1024.0
     fs, ws = known / pf, known / pw
-    return {"workload": "perturbed_grid_ring", "kernel": kernel, "sources": kernel_source_digest(),
-            "bytes_per_launch": 1024.0 * (kf * fs + kw * ws),
+    return {"workload": "perturbed_grid_ring", "kernels": list(kernels), "sources": kernel_source_digest(),
+            "bytes_per_step": 1024.0 * sum(kf[k] * fs + kw[k] * ws for k in kernels),
             "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
             "probe": pname[:80], "probe_fetch_kib": pf, "probe_write_kib": pw,
             "fetch_scale": fs, "write_scale": ws}
@@ -225,7 +238,6 @@ def main():
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
     ap.add_argument("--cpu-steps", type=int, default=3600, help="oracle sample length (0: skip)")
-    ap.add_argument("--graph", action="store_true", help="also time the captured-graph path")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB before the timed region "
                          "(a known-size reference for hardware byte counters)")
@@ -269,37 +281,39 @@ def main():
 
     # warm-up on its own handle (kernels, graph, caches), then a fresh handle
     warm = M.Sim(w, stream=stream)
-    warm.step_timed(args.warmup)
+    warm.step(args.warmup)
     warm.close()
     sim = M.Sim(w, stream=stream)
     before = sim.counters()["active_sum"]
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
-    kernel_ms, total_ms = sim.step_timed(args.steps)
+    e0.record(stream)
+    sim.step(args.steps)                 # the production path: one captured graph per step
+    e1.record(stream)
     torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
     upd = sim.counters()["active_sum"] - before
+    sim.close()
     value = upd / (total_ms / 1e3)
 
-    extra = {}
-    if args.graph:
-        g = M.Sim(w, stream=stream)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record(stream)
-        g.step(args.steps)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        gms = e0.elapsed_time(e1)
-        extra["graph_path"] = {"ms_per_step": gms / args.steps, "value": upd / (gms / 1e3)}
-        g.close()
+    # the same steps again, kernel by kernel between HIP events on the same
+    # stream, for the duration of each kernel (results are identical)
+    timed = M.Sim(w, stream=stream)
+    torch.cuda.synchronize()
+    kernel_ms, event_total_ms = timed.step_timed(args.steps)
+    assert timed.counters()["active_sum"] == upd
+    timed.close()
 
-    k1 = kernel_ms["k_tile_step"]
-    achieved = BYTES_PER_UPDATE * upd / (k1 / 1e3) / 1e9
+    # roofline of the tile kernels (Phases 1-2 of every vehicle: k_tile_step,
+    # and k_tile_big for tiles above the LDS of one workgroup), per step
+    tile_ms = kernel_ms["k_tile_step"] + kernel_ms["k_tile_big"]
+    achieved = BYTES_PER_UPDATE * upd / (tile_ms / 1e3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("workload") == args.workload and tr.get("sources") == kernel_source_digest():
-            traffic = tr.get("bytes_per_launch")
+            traffic = tr.get("bytes_per_step")
     line = {
         "metric": "vehicle-updates/sec (1 GPU)",
         "value": value,
@@ -316,11 +330,12 @@ def main():
         "config": {"workload": args.workload, "vehicles": w.n_vehicles, "edges": w.net.n_edges,
                    "lanes": int(w.net.lanes.sum()), "dt_s": 0.5, "steps": args.steps,
                    "vehicle_updates": int(upd)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic},
-        "kernel_ms": {k: round(v, 3) for k, v in kernel_ms.items()},
+        "roofline": {"bound": "hbm", "kernel": "k_tile_step + k_tile_big", "achieved": achieved,
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "tile_us_per_step": 1e3 * tile_ms / args.steps},
+        "kernel_us_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in kernel_ms.items()},
+        "event_path_ms_per_step": event_total_ms / args.steps,
     }
-    line.update(extra)
     if args.cpu_steps > 0:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(line), flush=True)
