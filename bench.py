@@ -237,7 +237,9 @@ def main():
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
-    ap.add_argument("--cpu-steps", type=int, default=3600, help="oracle sample length (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=7200, help="oracle sample length (0: skip)")
+    ap.add_argument("--progress", type=int, default=0, metavar="STEPS",
+                    help="print a line every STEPS steps (for profiler runs; adds synchronizations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="run one plain device copy of this many MiB before the timed region "
                          "(a known-size reference for hardware byte counters)")
@@ -288,7 +290,13 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    sim.step(args.steps)                 # the production path: one captured graph per step
+    if args.progress:                    # profiling runs only: these syncs cost time
+        for k0 in range(0, args.steps, args.progress):
+            sim.step(min(args.progress, args.steps - k0))
+            torch.cuda.synchronize()
+            print(f"graph path: step {k0 + min(args.progress, args.steps - k0)}", flush=True)
+    else:
+        sim.step(args.steps)             # the production path: one captured graph per step
     e1.record(stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
@@ -300,7 +308,15 @@ def main():
     # stream, for the duration of each kernel (results are identical)
     timed = M.Sim(w, stream=stream)
     torch.cuda.synchronize()
-    kernel_ms, event_total_ms = timed.step_timed(args.steps)
+    if args.progress:
+        kernel_ms, event_total_ms = None, 0.0
+        for k0 in range(0, args.steps, args.progress):
+            km, tm = timed.step_timed(min(args.progress, args.steps - k0))
+            kernel_ms = km if kernel_ms is None else {k: kernel_ms[k] + km[k] for k in km}
+            event_total_ms += tm
+            print(f"event path: step {k0 + min(args.progress, args.steps - k0)}", flush=True)
+    else:
+        kernel_ms, event_total_ms = timed.step_timed(args.steps)
     assert timed.counters()["active_sum"] == upd
     timed.close()
 
