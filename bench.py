@@ -238,6 +238,9 @@ def main():
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
     ap.add_argument("--cpu-steps", type=int, default=7200, help="oracle sample length (0: skip)")
+    ap.add_argument("--kernels-only", action="store_true",
+                    help="skip the graph-replayed pass (hardware-counter runs); value then comes from the "
+                         "kernel-by-kernel pass")
     ap.add_argument("--progress", type=int, default=0, metavar="STEPS",
                     help="print a line every STEPS steps (for profiler runs; adds synchronizations)")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -290,7 +293,9 @@ def main():
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record(stream)
-    if args.progress:                    # profiling runs only: these syncs cost time
+    if args.kernels_only:                # counter runs: the event-timed pass below is enough
+        pass
+    elif args.progress:                  # profiling runs only: these syncs cost time
         for k0 in range(0, args.steps, args.progress):
             sim.step(min(args.progress, args.steps - k0))
             torch.cuda.synchronize()
@@ -302,7 +307,6 @@ def main():
     total_ms = e0.elapsed_time(e1)
     upd = sim.counters()["active_sum"] - before
     sim.close()
-    value = upd / (total_ms / 1e3)
 
     # the same steps again, kernel by kernel between HIP events on the same
     # stream, for the duration of each kernel (results are identical)
@@ -317,8 +321,12 @@ def main():
             print(f"event path: step {k0 + min(args.progress, args.steps - k0)}", flush=True)
     else:
         kernel_ms, event_total_ms = timed.step_timed(args.steps)
+    if args.kernels_only:
+        upd = timed.counters()["active_sum"]
+        total_ms = event_total_ms
     assert timed.counters()["active_sum"] == upd
     timed.close()
+    value = upd / (total_ms / 1e3)
 
     # roofline of the tile kernels (Phases 1-2 of every vehicle: k_tile_step,
     # and k_tile_big for tiles above the LDS of one workgroup), per step
