@@ -267,7 +267,6 @@ void for_each_state_piece(sim_handle* h, F&& f) {
     f((void*)d.rear, sizeof(LaneRear) * NL);
     f((void*)d.qhead, 4 * ((size_t)h->nq + 1));
     f((void*)d.qhd, sizeof(int2) * (size_t)std::max(h->nq, 1));
-    f((void*)d.cnt, 4 * E);
     f((void*)d.tt_sum, 8 * E);
     f((void*)d.tt_cnt, 8 * E);
     f((void*)d.ctl, sizeof(Ctl));
@@ -294,8 +293,6 @@ void load_state(sim_handle* h, const void* src, int t) {
         HIP_OK(hipMemcpyAsync(p, (const char*)src + o, b, hipMemcpyDeviceToDevice, h->stream));
         o += (b + 255) & ~(size_t)255;
     });
-    // first-request stamps only ever grow: reset them for a re-run
-    HIP_OK(hipMemsetAsync(h->d.req_stamp, 0xFF, sizeof(int) * h->n_edges, h->stream));
     h->t = t;
 }
 
@@ -392,10 +389,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.lim = h->upload(net->speed_limit_mps, E);
             d.lanes = h->upload(h->lanes.data(), E);
             d.lane_base = h->upload(h->lane_base.data(), E + 1);
-            std::vector<int> lane_edge(NL);
-            for (int e = 0; e < E; ++e)
-                for (int l = 0; l < h->lanes[e]; ++l) lane_edge[h->lane_base[e] + l] = e;
-            d.lane_edge = h->upload(lane_edge.data(), NL);
             // ---- classes (den = 2 sqrt(ab), rounded once in binary32)
             std::vector<ClassParams> cp(16);
             h->len_c.assign(p->n_classes, 0.f);
@@ -548,9 +541,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.enter_stamp = h->dev<int>(NL);
             d.lane_rel = h->dev<int>(NL);
             d.lane_newcnt = h->dev<int>(NL);
-            d.cnt = h->dev<int>(E);
-            d.entries = h->dev<int>(E);
-            d.req_stamp = h->dev<int>(E);
             d.edge_rel = h->dev<int>(E);
             d.blk_sum = h->dev<int>(h->n_blk);
             d.blk_off = h->dev<int>(h->n_blk);
@@ -567,9 +557,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * NL));
             HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
-            HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * E));
-            HIP_OK(hipMemset(d.cnt, 0, sizeof(int) * E));
-            HIP_OK(hipMemset(d.entries, 0, sizeof(int) * E));
             HIP_OK(hipMemset(d.tt_sum, 0, sizeof(double) * E));
             HIP_OK(hipMemset(d.tt_cnt, 0, sizeof(unsigned long long) * E));
             HIP_OK(hipMemset(d.ctl, 0, sizeof(Ctl)));
@@ -805,7 +792,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         const int na = (int)act.size(), t = in->t, par = t & 1;
         std::vector<float> sx(na), sv(na);
         std::vector<uint32_t> svid(na), smeta(na);
-        std::vector<int32_t> sedge(na), snxt(na), cnt(h->n_edges, 0);
+        std::vector<int32_t> sedge(na), snxt(na);
         std::vector<LaneRear> rear(h->n_lanes);
         for (auto& r : rear) r = LaneRear{0.f, 0.f, -1, 0u};
         for (int k = 0; k < na; ++k) {
@@ -819,7 +806,6 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
             snxt[k] = nx;
             smeta[k] = m_make(in->lane[i], in->mand[i] != 0, in->held_since[i] >= 0, in->ww[i], h->cls[i],
                               h->mask_of(e, nx));
-            cnt[e]++;
             const bool last = (k + 1 == na) || act[k + 1].edge != e || act[k + 1].lane != act[k].lane;
             if (last) rear[h->lane_base[e] + act[k].lane] = LaneRear{in->x[i] - h->len_c[h->cls[i]], in->v[i], t, (uint32_t)i};
         }
@@ -873,15 +859,12 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
                                                    : make_int2(INT_MAX, -1);
             HIP_OK(hipMemcpy(d.qhd, qhd.data(), sizeof(int2) * qhd.size(), hipMemcpyHostToDevice));
         }
-        HIP_OK(hipMemcpy(d.cnt, cnt.data(), 4 * (size_t)h->n_edges, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d.rear, rear.data(), sizeof(LaneRear) * h->n_lanes, hipMemcpyHostToDevice));
         HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * h->n_lanes));
         HIP_OK(hipMemset(d.outbox, 0xFF, sizeof(Outbox) * h->n_lanes));
         HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * h->n_lanes));
         HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
-        HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * h->n_edges));
-        HIP_OK(hipMemset(d.entries, 0, sizeof(int) * h->n_edges));
         Ctl c{};
         c.t_a = t;
         c.t_b = t;

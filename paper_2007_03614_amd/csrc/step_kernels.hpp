@@ -8,14 +8,18 @@
 // stamped with the step they are valid for), the rear after the move
 // (admission), and the post-lane-change run of each lane (scatter).
 //
-// One step = 5 launches, all reading the step number from device memory, so
-// a captured graph of one step can be replayed for every step:
+// One step = 5 launches (6 on networks above 262,144 edges), all reading the
+// step number from device memory, so a captured graph of one step can be
+// replayed for every step:
 //   k_tile_step   Phases 1-2 per tile of whole edges, staged in LDS
-//   k_tile_big    the same for tiles above 512 vehicles (1,024 threads)
+//   k_tile_big    the same for tiles above 384 vehicles (1,024 threads)
 //   k_admit       eligibility + atomicMin of a 64-bit priority key per lane
-//   k_commit      per edge: winners, losers, arrivals, travel-time sums, new
-//                 lane/edge counts and offsets; departures; block-sum scan
-//   k_scatter     write the next layout and the next look-ahead table
+//   k_commit      eight threads per edge, one per lane: winners, losers,
+//                 arrivals, departures, travel-time sums, new lane counts and
+//                 edge offsets within the workgroup
+//   (k_blkscan    offsets of the commit workgroups, on large networks)
+//   k_scatter     offsets of the commit workgroups (in LDS), the next layout
+//                 and the next look-ahead table; the step counter advances
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -32,10 +36,11 @@ constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parame
 constexpr int kTileCapLds = 384;         // tiles up to this size are staged in LDS (4 workgroups per CU)
 constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 128;      // listed Philox blocks per tile round (more are computed in place)
-constexpr int kEdgeBlock = 256;          // edges per workgroup in the commit (one per thread)
+constexpr int kCommitLanes = 8;         // threads per edge in k_commit (an edge has at most 8 lanes)
+constexpr int kEdgeBlock = kNT / kCommitLanes;   // edges per commit workgroup
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
-constexpr int kScanLdsMax = 4096;        // edge blocks whose offsets k_scatter scans in LDS (16 KiB)
+constexpr int kScanLdsMax = 8192;        // edge blocks whose offsets k_scatter scans in LDS (32 KiB)
 constexpr int kCounterCopies = 32;       // each counter is spread over 32 slots (fewer colliding atomics)
 
 // ---- vehicle meta word ---------------------------------------------------
@@ -189,13 +194,9 @@ struct Dev {
     unsigned long long* win;
     int* exit_stamp;
     int* enter_stamp;
-    const int* lane_edge;       // edge of each global lane
     int* lane_rel;              // next layout: lane start relative to its edge
     int* lane_newcnt;
     // per edge
-    int* cnt;
-    int* entries;               // claimed lanes of the edge this step
-    int* req_stamp;
     int* edge_rel;              // next layout: edge start relative to its block
     int* blk_sum;
     int* blk_off;
@@ -943,7 +944,6 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                         ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
                     }
                     d.outbox[gl] = ob;
-                    d.req_stamp[el >> 4] = t;   // the edge has requests this step
                 }
             }
         }
@@ -1074,15 +1074,11 @@ __device__ inline bool transfer_eligible(const Dev& d, const Outbox& ob, int t) 
 }
 
 // An eligible request lowers the lane's 64-bit key with atomicMin; the
-// smallest key wins whatever the order of the atomics.  The request that
-// finds the lane unclaimed also counts one entry for the lane's edge (exactly
-// one request per claimed lane sees the reset value).
+// smallest key wins whatever the order of the atomics.  The lane is marked
+// claimed for this step.
 __device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t) {
-    const unsigned long long old = atomicMin(&d.win[gl], key);
-    if (old == ~0ull) {
-        d.enter_stamp[gl] = t;
-        atomicAdd(&d.entries[d.lane_edge[gl]], 1);
-    }
+    atomicMin(&d.win[gl], key);
+    d.enter_stamp[gl] = t;   // every claimant stores the same step
 }
 
 // One item per lane (its front may have asked to leave the edge this step)
@@ -1113,113 +1109,14 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
     }
 }
 
-// Outcome of the end-of-edge requests of edge e: arrivals, admitted
-// transfers and held losers; the travel times of the vehicles leaving e are
-// added in ascending id.  Returns the number of exits and, in winmask, the
-// lanes whose front won a transfer (their entry records are written by
-// write_entries once the wavefront has reserved the slots).
-__device__ inline void commit_edge(const Dev& d, const Slots& S, int e, int t, CounterAcc& acc, int& nex,
-                                   unsigned& exmask, unsigned& winmask) {
-    const int base = d.lane_base[e];
-    uint32_t ex_vid[8];
-    float ex_phi[8];
-    nex = 0;
-    exmask = 0;
-    winmask = 0;
-    for (int l = 0; l < d.lanes[e]; ++l) {
-        const Outbox ob = d.outbox[base + l];
-        if (ob.stamp != t) continue;
-        const uint32_t m = S.meta[ob.slot];
-        if (d.trace) {
-            const bool w2 = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
-            d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + ob.slot].kb |=
-                (ob.target < 0 ? TB_ARRIVE : (w2 ? TB_EXIT : TB_HELD)) << 8;
-        }
-        if (ob.target < 0) {                       // arrival at the route end
-            d.status[ob.vid] = kArrived;
-            d.fin_x[ob.vid] = S.x[ob.slot];
-            d.fin_v[ob.vid] = S.v[ob.slot];
-            d.fin_meta[ob.vid] = m;
-            d.exit_stamp[base + l] = t;
-            exmask |= 1u << l;
-            ex_vid[nex] = ob.vid;
-            ex_phi[nex] = ob.phi;
-            nex++;
-            acc.c[cArrived]++;
-            continue;
-        }
-        const bool won = ob.elig && d.win[ob.target] == ob.key;
-        if (won) {
-            if (!lane_allowed(m, S.nxt[ob.slot], l)) acc.c[cWaivedExits]++;
-            d.exit_stamp[base + l] = t;
-            exmask |= 1u << l;
-            winmask |= 1u << l;
-            ex_vid[nex] = ob.vid;
-            ex_phi[nex] = ob.phi;
-            nex++;
-            acc.c[cTransfers]++;
-        } else {                                   // held at the stop line
-            S.x[ob.slot] = d.L[e];
-            S.v[ob.slot] = 0.0f;
-            S.meta[ob.slot] = m | (1u << 5);
-            if (d.held_since[ob.vid] < 0) d.held_since[ob.vid] = t;
-            acc.c[cHolds]++;
-        }
-    }
-    for (int a = 1; a < nex; ++a) {                // insertion sort by vehicle id
-        const uint32_t kv = ex_vid[a];
-        const float kp = ex_phi[a];
-        int b2 = a - 1;
-        while (b2 >= 0 && ex_vid[b2] > kv) {
-            ex_vid[b2 + 1] = ex_vid[b2];
-            ex_phi[b2 + 1] = ex_phi[b2];
-            --b2;
-        }
-        ex_vid[b2 + 1] = kv;
-        ex_phi[b2 + 1] = kp;
-    }
-    double sum = d.tt_sum[e];
-    for (int a = 0; a < nex; ++a) {
-        const uint32_t vid = ex_vid[a];
-        const double tau = ((double)t + (double)ex_phi[a]) * (double)d.dt;
-        sum += tau - d.tau_in[vid];
-        if (d.status[vid] == kArrived) d.t_arr[vid] = tau;
-        else d.tau_in[vid] = tau;
-    }
-    d.tt_sum[e] = sum;
-    d.tt_cnt[e] += (unsigned long long)nex;
-}
-
-// entry records of the transfers that won, at slots k0, k0 + 1, ...
-__device__ inline void write_entries(const Dev& d, int e, unsigned winmask, int k0) {
-    const int base = d.lane_base[e];
-    int k = k0;
-    for (int l = 0; l < 8; ++l) {
-        if (!((winmask >> l) & 1u)) continue;
-        const Outbox ob = d.outbox[base + l];
-        const int kk = d.cursor[ob.vid] + 1;     // route index of the next edge ob.nxt
-        d.cursor[ob.vid] = kk;
-        const int64_t r0 = d.roff[ob.vid];
-        const int64_t pos = r0 + kk + 1;
-        const int nn = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
-        EntryRec r;
-        r.x = ob.xp;
-        r.v = ob.v;
-        r.vid = ob.vid;
-        r.edge = ob.nxt;
-        r.gl = ob.target;
-        r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)(ob.tl_cls >> 8), d.rmask[r0 + kk]);
-        r.nxt = nn;
-        r.pad = 0;
-        d.held_since[ob.vid] = -1;
-        d.ent[k++] = r;
-    }
-}
-
-// One thread per edge: commit of its end-of-edge requests, admission of the
-// due heads of its departure queues, new lane and edge counts, offsets in
-// the workgroup.  The last workgroup to finish scans the workgroup sums and
-// adds the refused departures of the step to their counter.
+// One thread per lane slot: eight threads per edge (an edge has at most 8
+// lanes), so the lanes of an edge are committed in parallel and the edge's
+// sums are reduced across its eight threads with shuffles.  A lane thread:
+//   * settles its front's end-of-edge request: arrival, admitted transfer
+//     (an entry record on the next edge), or held at the stop line;
+//   * inserts the departure whose key won its lane;
+//   * counts its vehicles for the next layout.
+// The edge's travel-time sum adds the exits in ascending vehicle id.
 __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     __shared__ unsigned shc[cNumCounters];
     __shared__ Scan4 wsh4[kWaves];
@@ -1229,61 +1126,159 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     const Slots S = d.s[par];
     CounterAcc acc;
     acc.zero();
-    const int e = blockIdx.x * kEdgeBlock + threadIdx.x;
-    int c = 0;
-    unsigned winmask = 0;
-    int ins_vid[8], ins_gl[8];
-    int nins = 0;
+    const int l = (int)(threadIdx.x & (kCommitLanes - 1));
+    const int e = blockIdx.x * kEdgeBlock + (int)(threadIdx.x / kCommitLanes);
+    int nl = 0, base = 0;
     if (e < d.n_edges) {
-        int nex = 0;
-        unsigned exmask = 0;
-        if (d.req_stamp[e] == t) commit_edge(d, S, e, t, acc, nex, exmask, winmask);
-        c = d.cnt[e] - nex + d.entries[e];
-        d.cnt[e] = c;
-        d.entries[e] = 0;
-        if (c > 0) {
-            int o = 0;
-            const int base = d.lane_base[e];
-            for (int l = 0; l < d.lanes[e]; ++l) {
-                const int gl = base + l;
-                const LanePost p = d.post[gl];
-                int nc = (p.stamp == t) ? p.cnt : 0;
-                if ((exmask >> l) & 1u) nc -= 1;
-                if (d.enter_stamp[gl] == t) {   // the lane was claimed: by a departure if the key says so
-                    nc += 1;
-                    const unsigned long long w = d.win[gl];
-                    if (w >> 63) {
-                        ins_vid[nins] = (int)(uint32_t)w;
-                        ins_gl[nins++] = gl;
-                    }
-                }
-                d.lane_rel[gl] = o;
-                d.lane_newcnt[gl] = nc;
-                o += nc;
+        nl = d.lanes[e];
+        base = d.lane_base[e];
+    }
+    const bool lane_ok = l < nl;
+    const int gl = base + l;
+
+    // loads of this lane, independent of each other
+    Outbox ob;
+    ob.stamp = -1;
+    int pcnt = 0;
+    bool claimed = false;
+    unsigned long long w = ~0ull;
+    if (lane_ok) {
+        ob = d.outbox[gl];
+        const LanePost p = d.post[gl];
+        pcnt = p.stamp == t ? p.cnt : 0;
+        claimed = d.enter_stamp[gl] == t;
+        w = d.win[gl];
+    }
+    const bool req = lane_ok && ob.stamp == t;
+
+    // the front's request
+    bool exits = false, won = false, arrived = false;
+    double dtt = 0.0, tau = 0.0;
+    int kk = 0;
+    int64_t r0 = 0;
+    if (req) {
+        const uint32_t m = S.meta[ob.slot];
+        const double tin = d.tau_in[ob.vid];
+        if (ob.target >= 0) {                      // prefetch the route for an entry record
+            kk = d.cursor[ob.vid] + 1;
+            r0 = d.roff[ob.vid];
+        }
+        won = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
+        if (d.trace)
+            d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + ob.slot].kb |=
+                (ob.target < 0 ? TB_ARRIVE : (won ? TB_EXIT : TB_HELD)) << 8;
+        if (ob.target < 0) {                       // arrival at the route end
+            arrived = exits = true;
+            d.status[ob.vid] = kArrived;
+            d.fin_x[ob.vid] = S.x[ob.slot];
+            d.fin_v[ob.vid] = S.v[ob.slot];
+            d.fin_meta[ob.vid] = m;
+            acc.c[cArrived]++;
+        } else if (won) {
+            exits = true;
+            if (!lane_allowed(m, ob.nxt, l)) acc.c[cWaivedExits]++;
+            acc.c[cTransfers]++;
+        } else {                                   // held at the stop line
+            S.x[ob.slot] = d.L[e];
+            S.v[ob.slot] = 0.0f;
+            S.meta[ob.slot] = m | (1u << 5);
+            if (d.held_since[ob.vid] < 0) d.held_since[ob.vid] = t;
+            acc.c[cHolds]++;
+        }
+        if (exits) {
+            d.exit_stamp[gl] = t;
+            tau = ((double)t + (double)ob.phi) * (double)d.dt;
+            dtt = tau - tin;
+        }
+    }
+
+    // travel times of the edge's exits, added in ascending vehicle id by the
+    // edge's first thread
+    {
+        const uint32_t key = exits ? ob.vid : 0xFFFFFFFFu;
+        uint32_t kv[kCommitLanes];
+        double kd[kCommitLanes];
+#pragma unroll
+        for (int j = 0; j < kCommitLanes; ++j) {
+            kv[j] = (uint32_t)__shfl((int)key, j, kCommitLanes);
+            kd[j] = __shfl(dtt, j, kCommitLanes);
+        }
+        if (l == 0 && e < d.n_edges) {
+            int nex = 0;
+            double sum = d.tt_sum[e];
+            uint32_t last = 0;
+            bool first = true;
+            for (int r = 0; r < kCommitLanes; ++r) {   // selection in id order (ids are distinct)
+                int best = -1;
+#pragma unroll
+                for (int j = 0; j < kCommitLanes; ++j)
+                    if (kv[j] != 0xFFFFFFFFu && (first || kv[j] > last) && (best < 0 || kv[j] < kv[best])) best = j;
+                if (best < 0) break;
+                sum += kd[best];
+                last = kv[best];
+                first = false;
+                ++nex;
+            }
+            if (nex) {
+                d.tt_sum[e] = sum;
+                d.tt_cnt[e] += (unsigned long long)nex;
             }
         }
     }
-    int k = wave_reserve(&d.ctl->n_ent[par], __popc(winmask) + nins);
-    if (winmask) {
-        write_entries(d, e, winmask, k);
-        k += __popc(winmask);
+    if (exits) {
+        if (arrived) d.t_arr[ob.vid] = tau;
+        else d.tau_in[ob.vid] = tau;
     }
-    for (int a = 0; a < nins; ++a) {
-        const int vid = ins_vid[a], g = ins_gl[a];
-        const int4 vq = d.vq[vid];               // vid is the head of queue vq.x
+
+    // the departure whose key won this lane (the winning key of a claimed lane)
+    const bool ins = lane_ok && claimed && (w >> 63);
+    const int ins_vid = ins ? (int)(uint32_t)w : 0;
+
+    // next layout: this lane's count, its offset in the edge, the edge's count
+    const int nc = pcnt - (exits ? 1 : 0) + (claimed ? 1 : 0);
+    int inc = nc;
+#pragma unroll
+    for (int dd = 1; dd < kCommitLanes; dd <<= 1) {
+        const int o = __shfl_up(inc, dd, kCommitLanes);
+        if (l >= dd) inc += o;
+    }
+    const int c = __shfl(inc, kCommitLanes - 1, kCommitLanes);   // vehicles of the edge
+    if (lane_ok) {
+        d.lane_rel[gl] = inc - nc;
+        d.lane_newcnt[gl] = nc;
+    }
+
+    // entry records: a transfer won out of this lane, a departure into it
+    int k = wave_reserve(&d.ctl->n_ent[par], (won ? 1 : 0) + (ins ? 1 : 0));
+    if (won) {
+        const int64_t pos = r0 + kk + 1;           // route index of the edge after ob.nxt
+        EntryRec r;
+        r.x = ob.xp;
+        r.v = ob.v;
+        r.vid = ob.vid;
+        r.edge = ob.nxt;
+        r.gl = ob.target;
+        r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)(ob.tl_cls >> 8), d.rmask[r0 + kk]);
+        r.nxt = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
+        r.pad = 0;
+        d.cursor[ob.vid] = kk;
+        d.held_since[ob.vid] = -1;
+        d.ent[k++] = r;
+    }
+    if (ins) {
+        const int vid = ins_vid;
+        const int4 vq = d.vq[vid];                 // vid is the head of queue vq.x
+        const int64_t q0 = d.roff[vid];
         d.qhead[vq.x] = vq.y + 1;
         d.qhd[vq.x] = vq.z >= 0 ? make_int2(vq.w, vq.z) : make_int2(INT_MAX, -1);
-        const int64_t r0 = d.roff[vid];
-        const int e0 = d.redges[r0];
-        const int nn = (r0 + 1 < d.roff[vid + 1]) ? d.redges[r0 + 1] : -1;
         EntryRec r;
         r.x = 0.0f;
         r.v = 0.0f;
         r.vid = (uint32_t)vid;
-        r.edge = e0;
-        r.gl = g;
-        r.meta = m_make(g - d.lane_base[e0], false, false, 0, d.cls[vid], d.rmask[r0]);
-        r.nxt = nn;
+        r.edge = e;                                // the queue's lane is on the first route edge
+        r.gl = gl;
+        r.meta = m_make(l, false, false, 0, d.cls[vid], d.rmask[q0]);
+        r.nxt = (q0 + 1 < d.roff[vid + 1]) ? d.redges[q0 + 1] : -1;
         r.pad = 0;
         d.status[vid] = kActive;
         d.cursor[vid] = 0;
@@ -1292,9 +1287,11 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         d.ent[k++] = r;
         acc.c[cDeparted]++;
     }
-    Scan4 run = wg_exclusive_scan4(Scan4{c, -1, -1, -1}, wsh4);
-    if (e < d.n_edges) d.edge_rel[e] = run.s;
-    if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = run.s + c;
+
+    // offsets of the edges in the workgroup (one value per edge, at its lane 0)
+    Scan4 run = wg_exclusive_scan4(Scan4{l == 0 ? c : 0, -1, -1, -1}, wsh4);
+    if (l == 0 && e < d.n_edges) d.edge_rel[e] = run.s;
+    if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = run.s + (l == 0 ? c : 0);
     flush_counters_lds(d, acc, shc);   // ends with a barrier: shc is complete
     if (threadIdx.x == 0 && shc[cDeparted]) atomicAdd(&d.ctl->n_departed, (int)shc[cDeparted]);
 }
