@@ -524,7 +524,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 d.s[b].meta = h->dev<uint32_t>(NV);
                 d.s[b].nxt = h->dev<int32_t>(NV);
             }
-            d.ent = h->dev<EntryRec>(std::min<size_t>(NV, (size_t)NL + 1));
+            d.ent = h->dev<EntryRec>(NL);
             d.status = h->dev<uint8_t>(NV);
             d.cursor = h->dev<int>(NV);
             d.held_since = h->dev<int>(NV);
@@ -737,8 +737,8 @@ sim_status sim_read_state(sim_handle* h, sim_state* o) {
             if (o->t_arr) o->t_arr[i] = tar[i];
         }
         if (o->counters) {
-            unsigned long long cc[cNumCounters * kCounterCopies];
-            HIP_OK(hipMemcpy(cc, d.counters, sizeof(cc), hipMemcpyDeviceToHost));
+            std::vector<unsigned long long> cc((size_t)cNumCounters * kCounterCopies);
+            HIP_OK(hipMemcpy(cc.data(), d.counters, 8 * cc.size(), hipMemcpyDeviceToHost));
             for (int k = 0; k < cNumCounters; ++k) {
                 unsigned long long v = 0;
                 for (int q = 0; q < kCounterCopies; ++q) v += cc[k * kCounterCopies + q];
@@ -872,9 +872,9 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         c.n_departed = departed;
         HIP_OK(hipMemcpy(d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice));
         if (in->counters) {
-            unsigned long long cc[cNumCounters * kCounterCopies] = {};
-            for (int k = 0; k < cNumCounters; ++k) cc[k * kCounterCopies] = (unsigned long long)in->counters[k];
-            HIP_OK(hipMemcpy(d.counters, cc, sizeof(cc), hipMemcpyHostToDevice));
+            std::vector<unsigned long long> cc((size_t)cNumCounters * kCounterCopies, 0ull);
+            for (int k = 0; k < cNumCounters; ++k) cc[(size_t)k * kCounterCopies] = (unsigned long long)in->counters[k];
+            HIP_OK(hipMemcpy(d.counters, cc.data(), 8 * cc.size(), hipMemcpyHostToDevice));
         }
         HIP_OK(hipDeviceSynchronize());
         h->t = t;

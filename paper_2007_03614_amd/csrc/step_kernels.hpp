@@ -41,7 +41,7 @@ constexpr int kEdgeBlock = kNT / kCommitLanes;   // edges per commit workgroup
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
 constexpr int kScanLdsMax = 8192;        // edge blocks whose offsets k_scatter scans in LDS (32 KiB)
-constexpr int kCounterCopies = 32;       // each counter is spread over 32 slots (fewer colliding atomics)
+constexpr int kCounterCopies = 1024;     // each counter is spread over 1,024 slots (few colliding atomics)
 
 // ---- vehicle meta word ---------------------------------------------------
 // bits 0-3 lane | 4 mandatory | 5 held at stop line | 8-14 wrong-lane wait |
@@ -73,11 +73,10 @@ struct Ctl {
     int t_a;
     int t_b;
     int n_act[2];
-    int n_ent[2];
     int n_big[2];     // tiles above kTileCapLds, listed for k_tile_big
     int err;          // non-zero: a layout bound check failed (see kErr*)
     int n_departed;   // vehicles admitted from the departure queues so far
-    int pad[5];
+    int pad[7];
 };
 
 enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
@@ -203,8 +202,7 @@ struct Dev {
     int n_blk;
     double* tt_sum;
     unsigned long long* tt_cnt;
-    // lists
-    EntryRec* ent;
+    EntryRec* ent;              // per lane: the record entering it this step (where enter_stamp == t)
     // big tiles: (first, end) slot pairs, and global scratch for single
     // edges beyond the LDS of a workgroup
     int* big_list;
@@ -381,37 +379,6 @@ struct CounterAcc {
         for (int k = 0; k < cNumCounters; ++k) c[k] = 0;
     }
 };
-
-// Append to a device list with one atomic per wavefront: the active lanes
-// that pass `flag` get consecutive indices.  Every lane active at the call
-// must make it (the ballot covers exactly them).
-__device__ inline int wave_append(int* counter, bool flag) {
-    const unsigned long long mask = __ballot(flag);
-    if (!flag) return -1;
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(counter, __popcll(mask));
-    base = __shfl(base, leader, 64);
-    return base + __popcll(mask & ((1ull << lane) - 1ull));
-}
-
-// Reserve `cnt` consecutive slots per lane, one atomic per wavefront (all
-// 64 lanes of the wave must make the call).
-__device__ inline int wave_reserve(int* counter, int cnt) {
-    const int lane = threadIdx.x & 63;
-    int inc = cnt;
-#pragma unroll
-    for (int dd = 1; dd < 64; dd <<= 1) {
-        const int o = __shfl_up(inc, dd, 64);
-        if (lane >= dd) inc += o;
-    }
-    const int total = __shfl(inc, 63, 64);
-    int base = 0;
-    if (lane == 63 && total > 0) base = atomicAdd(counter, total);
-    base = __shfl(base, 63, 64);
-    return base + inc - cnt;
-}
 
 // counters: per-thread registers -> LDS atomics -> one global atomic each
 __device__ inline void flush_counters_lds(const Dev& d, const CounterAcc& acc, unsigned* shc) {
@@ -973,7 +940,6 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         // the later kernels of this step read t_b; lists of the next step
         // are unused during this one
         d.ctl->t_b = t;
-        d.ctl->n_ent[par ^ 1] = 0;
         d.ctl->n_big[par ^ 1] = 0;
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
@@ -1248,8 +1214,8 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         d.lane_newcnt[gl] = nc;
     }
 
-    // entry records: a transfer won out of this lane, a departure into it
-    int k = wave_reserve(&d.ctl->n_ent[par], (won ? 1 : 0) + (ins ? 1 : 0));
+    // entry records, one per claimed lane, stored at that lane: a transfer
+    // won out of this lane (at its target), a departure into this lane
     if (won) {
         const int64_t pos = r0 + kk + 1;           // route index of the edge after ob.nxt
         EntryRec r;
@@ -1263,7 +1229,7 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         r.pad = 0;
         d.cursor[ob.vid] = kk;
         d.held_since[ob.vid] = -1;
-        d.ent[k++] = r;
+        d.ent[ob.target] = r;
     }
     if (ins) {
         const int vid = ins_vid;
@@ -1284,7 +1250,7 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         d.cursor[vid] = 0;
         d.held_since[vid] = -1;
         d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
-        d.ent[k++] = r;
+        d.ent[gl] = r;
         acc.c[cDeparted]++;
     }
 
@@ -1353,7 +1319,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     __shared__ int tot;
     const int t = d.ctl->t_b, par = t & 1;
     const int nold = d.ctl->n_act[par];
-    const int nent = d.ctl->n_ent[par];
+    const int nl = d.n_lanes_total;
     const int* boff;
     int nnew;
     if (kLds) {
@@ -1365,7 +1331,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         nnew = d.ctl->n_act[par ^ 1];
     }
     const Slots A = d.s[par], B = d.s[par ^ 1];
-    for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nent; i += gridDim.x * kNT) {
+    for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nl; i += gridDim.x * kNT) {
         float x, v;
         uint32_t vid, meta;
         int edge, nxt, gl, nr;
@@ -1388,9 +1354,10 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             v = A.v[i];
             vid = A.vid[i];
             nxt = A.nxt[i];
-        } else {
-            const EntryRec r = d.ent[i - nold];
-            gl = r.gl;
+        } else {                                  // a lane claimed this step takes its entry
+            gl = i - nold;
+            if (d.enter_stamp[gl] != t) continue;
+            const EntryRec r = d.ent[gl];
             nr = d.lane_newcnt[gl] - 1;           // the entry is the new rear
             is_rear = true;
             x = r.x;
