@@ -1075,6 +1075,25 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
     }
 }
 
+// Sort eight (key, value) pairs by key, ascending, with the 19-comparator
+// network for eight inputs (Knuth, TAOCP vol. 3, 5.3.4); every index is a
+// constant, so the pairs stay in registers.
+__device__ inline void sort8_by_key(uint32_t* k, double* v) {
+    constexpr int kPairs[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
+                                   {0, 4}, {3, 7}, {1, 5}, {2, 6}, {1, 4}, {3, 6}, {2, 4}, {3, 5}, {3, 4}};
+#pragma unroll
+    for (int p = 0; p < 19; ++p) {
+        const int i = kPairs[p][0], j = kPairs[p][1];
+        const bool sw = k[i] > k[j];
+        const uint32_t ki = sw ? k[j] : k[i], kj = sw ? k[i] : k[j];
+        const double vi = sw ? v[j] : v[i], vj = sw ? v[i] : v[j];
+        k[i] = ki;
+        k[j] = kj;
+        v[i] = vi;
+        v[j] = vj;
+    }
+}
+
 // One thread per lane slot: eight threads per edge (an edge has at most 8
 // lanes), so the lanes of an edge are committed in parallel and the edge's
 // sums are reduced across its eight threads with shuffles.  A lane thread:
@@ -1159,36 +1178,32 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     }
 
     // travel times of the edge's exits, added in ascending vehicle id by the
-    // edge's first thread
+    // edge's first thread: the eight (id, time) pairs of the edge are sorted
+    // by a 19-comparator network with fixed register indices
     {
-        const uint32_t key = exits ? ob.vid : 0xFFFFFFFFu;
         uint32_t kv[kCommitLanes];
         double kd[kCommitLanes];
+        const uint32_t key = exits ? ob.vid : 0xFFFFFFFFu;
 #pragma unroll
         for (int j = 0; j < kCommitLanes; ++j) {
             kv[j] = (uint32_t)__shfl((int)key, j, kCommitLanes);
             kd[j] = __shfl(dtt, j, kCommitLanes);
         }
-        if (l == 0 && e < d.n_edges) {
-            int nex = 0;
-            double sum = d.tt_sum[e];
-            uint32_t last = 0;
-            bool first = true;
-            for (int r = 0; r < kCommitLanes; ++r) {   // selection in id order (ids are distinct)
-                int best = -1;
+        bool any = false;
 #pragma unroll
-                for (int j = 0; j < kCommitLanes; ++j)
-                    if (kv[j] != 0xFFFFFFFFu && (first || kv[j] > last) && (best < 0 || kv[j] < kv[best])) best = j;
-                if (best < 0) break;
-                sum += kd[best];
-                last = kv[best];
-                first = false;
-                ++nex;
-            }
-            if (nex) {
-                d.tt_sum[e] = sum;
-                d.tt_cnt[e] += (unsigned long long)nex;
-            }
+        for (int j = 0; j < kCommitLanes; ++j) any = any || kv[j] != 0xFFFFFFFFu;
+        if (l == 0 && any) {
+            sort8_by_key(kv, kd);
+            double sum = d.tt_sum[e];
+            int nex = 0;
+#pragma unroll
+            for (int j = 0; j < kCommitLanes; ++j)
+                if (kv[j] != 0xFFFFFFFFu) {
+                    sum += kd[j];
+                    ++nex;
+                }
+            d.tt_sum[e] = sum;
+            d.tt_cnt[e] += (unsigned long long)nex;
         }
     }
     if (exits) {
