@@ -79,7 +79,7 @@ struct Ctl {
     int pad[7];
 };
 
-enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
+enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8, kErrTileBounds = 16 };
 
 struct Slots {
     float* x;
@@ -208,6 +208,8 @@ struct Dev {
     int* big_list;
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
+    int* tile_start[2];         // per window: first slot of the window that starts an edge, or INT_MAX
+    int tile_slots;             // entries of each tile_start array
     // traced re-run: record of step t at trace[(t - trace_t0) * trace_stride + slot]
     TraceRec* trace;
     int trace_t0;
@@ -484,28 +486,56 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     const int tid = threadIdx.x;
     const int dir = (t % 2 == 0) ? -1 : 1;
 
-    // load S_t (coalesced)
+    // Phase 1 keeps its scratch in arrays that the scans fill later.  Few
+    // vehicles need a Philox draw, and a block costs thousands of cycles, so
+    // a wavefront in which one lane draws would make the other 63 wait.
+    // Instead the draws are listed as tasks and computed by the whole
+    // workgroup at once, in two rounds: the uniforms of Eq. (2), listed while
+    // S_t is loaded, then the noise of Eqs. (3)-(4), whose need depends on the
+    // mandatory flag.
+    int* const u1 = b.lastm;                      // Eq. (2) uniform words (scratch until the scans)
+    int* const na = b.lasts;                      // noise word sums, leading side
+    int* const nb = b.mpref;                      // noise word sums, lagging side
+    float* const Ga = b.xn;                       // gaps and critical gaps of pending decisions
+    float* const ca = (float*)b.fl;               // (scratch until Phase 2)
+    float* const Gb = (float*)b.pel;
+    float* const cb = (float*)b.inv;
+
+    // load S_t (coalesced) and list the Eq. (2) draws
     for (int q = tid; q < n; q += NT) {
         const int s = a0 + q;
         const uint32_t m = S.meta[s];
         const int e = S.edge[s], f = S.nxt[s];
-        b.x[q] = S.x[s];
+        const float x = S.x[s];
+        b.x[q] = x;
         b.v[q] = S.v[s];
         b.vid[q] = S.vid[s];
         b.el[q] = ((uint32_t)e << 4) | (uint32_t)m_lane(m);
         b.meta[q] = m;
         b.nxt[q] = f;
-        b.L[q] = d.L[e];
+        const float L = d.L[e];
+        b.L[q] = L;
         b.lim[q] = d.lim[e];
         b.lbe[q] = d.lane_base[e];
         b.lanes2[q] = (uint32_t)d.lanes[e] | ((f >= 0 ? (uint32_t)d.lanes[f] : 0u) << 8);
         b.lbf[q] = f >= 0 ? d.lane_base[f] : 0;
         const uint32_t id = S.vid[s];
         b.alpha[q] = d.alpha[id];
-        b.rid[q] = d.rid[id];
+        const uint32_t rid = d.rid[id];
+        b.rid[q] = rid;
+        u1[q] = 0;
+        na[q] = 0;
+        nb[q] = 0;
+        if (!m_held(m) && !m_mand(m) && !lane_allowed(m, f, m_lane(m))) {   // Eq. (2) may trigger
+            const float dd = L - x;
+            if (dd > kX0) {
+                const float dm = dd - kX0;
+                if (dm * dm < kZCut) draw_task(dq, 0, rid, q, 1, 0, u1, d.seed, t);
+            }
+        }
     }
-    if (tid < 2) dq.n[tid] = 0;
     __syncthreads();
+    draw_run<NT>(dq, 0, d.seed, t, u1, na, nb);
 
     // ---- runs of S_t (tile order: edge, lane, then x and id descending)
     {
@@ -537,36 +567,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
     const int nruns = *b.nruns;
 
-    // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t.
-    // Few vehicles need a Philox draw, and a block costs thousands of
-    // cycles, so a wavefront in which one lane draws would make the other 63
-    // wait.  Instead the draws are listed as tasks and computed by the whole
-    // workgroup at once, in two rounds: the uniforms of Eq. (2), then the
-    // noise of Eqs. (3)-(4), whose need depends on the mandatory flag.
-    int* const u1 = b.lastm;                      // Eq. (2) uniform words (scratch until the scans)
-    int* const na = b.lasts;                      // noise word sums, leading side
-    int* const nb = b.mpref;                      // noise word sums, lagging side
-    float* const Ga = b.xn;                       // gaps and critical gaps of pending decisions
-    float* const ca = (float*)b.fl;               // (scratch until Phase 2)
-    float* const Gb = (float*)b.pel;
-    float* const cb = (float*)b.inv;
-    for (int q = tid; q < n; q += NT) {
-        u1[q] = 0;
-        na[q] = 0;
-        nb[q] = 0;
-        const uint32_t m = b.meta[q];
-        if (m_held(m) || m_mand(m)) continue;
-        const int l = (int)(b.el[q] & 15u);
-        if (lane_allowed(m, b.nxt[q], l)) continue;
-        const float dd = b.L[q] - b.x[q];
-        if (dd <= kX0) continue;
-        const float dm = dd - kX0;
-        if (dm * dm < kZCut) draw_task(dq, 0, b.rid[q], q, 1, 0, u1, d.seed, t);
-    }
-    __syncthreads();
-    draw_run<NT>(dq, 0, d.seed, t, u1, na, nb);
-    __syncthreads();
-
+    // ---- Phase 1: lane-change decisions (Eqs. (2)-(4)) against S_t
     for (int q = tid; q < n; q += NT) {
         uint32_t m = b.meta[q];
         int moved = 0, pos = 0;
@@ -665,6 +666,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
     draw_run<NT>(dq, 1, d.seed, t, u1, na, nb);
     __syncthreads();
+    if (tid < 2) dq.n[tid] = 0;   // lists of the next tile (several barriers away)
 
     for (int q = tid; q < n; q += NT) {
         const int code = b.moved[q];
@@ -918,18 +920,50 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
 }
 
+// Tile window of a step with n active vehicles: fixed by the schedule, or
+// (0) the smallest of 64 and 128 slots whose tiles fit in one round of
+// resident workgroups.
+__device__ inline int tile_window(const Dev& d, int n) {
+    int W = d.tile_window;
+    if (W == 0) {
+        W = kTileWindowMin;
+        while (W < kTileWindowAuto && (n + W - 1) / W > d.tile_target) W *= 2;
+    }
+    return W;
+}
+
+// A tile is the set of edges whose first slot lies in one window of W slots.
+// The first edge start of every window of the next layout is marked by the
+// scatter kernel as it writes that layout; this kernel marks them from the
+// current layout instead (after a state write or a schedule change).
+__global__ void __launch_bounds__(kNT) k_tile_bounds(Dev d) {
+    const int t = d.ctl->t_a, par = t & 1;
+    const int n = d.ctl->n_act[par];
+    const int W = tile_window(d, n);
+    const int32_t* edge = d.s[par].edge;
+    for (int k = blockIdx.x * kNT + threadIdx.x; k < d.tile_slots; k += gridDim.x * kNT) {
+        int a0 = INT_MAX;
+        for (int s = k * W; s < min(n, (k + 1) * W); ++s)
+            if (s == 0 || edge[s] != edge[s - 1]) {
+                a0 = s;
+                break;
+            }
+        d.tile_start[par][k] = a0;
+    }
+}
+
 // Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
 // tiles go to a list for k_tile_big.
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kWaves];
-    __shared__ int wsh[kWaves];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
     __shared__ uint2 dtask[kTileDrawTasks];
     __shared__ int dcount[2];
     const DrawQ dq{dtask, dcount, kTileDrawTasks};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     const int t = d.ctl->t_a, par = t & 1;
     const int n = d.ctl->n_act[par];
@@ -944,21 +978,27 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
-    // tile window: fixed by the schedule, or (0) the smallest of 64 and 128
-    // slots whose tiles fit in one round of resident workgroups
-    int W = d.tile_window;
-    if (W == 0) {
-        W = kTileWindowMin;
-        while (W < kTileWindowAuto && (n + W - 1) / W > d.tile_target) W *= 2;
-    }
+    const int W = tile_window(d, n);
     const int ntile = (n + W - 1) / W;
-    const int32_t* edge = d.s[par].edge;
+    const int* ts = d.tile_start[par];
+    {   // windows of the next step start unmarked (the scatter marks them)
+        int* nx = d.tile_start[par ^ 1];
+        for (int k = blockIdx.x * kNT + threadIdx.x; k < d.tile_slots; k += gridDim.x * kNT) nx[k] = INT_MAX;
+    }
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
-        const int w0 = k * W, w1 = min(n, w0 + W);
-        const int a0 = first_edge_start<kNT>(edge, w0, w1, wsh);
-        if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
-        const int a1 = first_edge_start<kNT>(edge, w1, n, wsh);
+        const int a0 = ts[k];
+        if (a0 == INT_MAX) continue;   // window inside one long edge: handled by an earlier tile
+        int a1 = n;
+        for (int k2 = k + 1; k2 < ntile; ++k2)
+            if (ts[k2] != INT_MAX) {
+                a1 = ts[k2];
+                break;
+            }
         const int cnt = a1 - a0;
+        if (a0 < k * W || a0 >= min(n, (k + 1) * W) || cnt <= 0) {   // marks inconsistent with the layout
+            if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileBounds);
+            continue;
+        }
         if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
             if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileTooBig);
             continue;
@@ -987,6 +1027,7 @@ __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
     __shared__ int dcount[2];
     const DrawQ dq{dtask, dcount, kBigNT};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     __syncthreads();
     const int t = d.ctl->t_a, par = t & 1;
@@ -1346,6 +1387,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         nnew = d.ctl->n_act[par ^ 1];
     }
     const Slots A = d.s[par], B = d.s[par ^ 1];
+    const int wnext = tile_window(d, nnew);
     for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nl; i += gridDim.x * kNT) {
         float x, v;
         uint32_t vid, meta;
@@ -1394,6 +1436,8 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         B.edge[dst] = edge;
         B.meta[dst] = meta;
         B.nxt[dst] = nxt;
+        if (d.lane_rel[gl] + nr == 0)   // first slot of its edge: mark the window of the next step
+            atomicMin(&d.tile_start[par ^ 1][dst / wnext], dst);
         if (is_rear) {
             LaneRear lr;
             lr.xm = x - d.cp[m_cls(meta)].len;
