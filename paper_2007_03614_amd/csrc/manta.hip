@@ -243,14 +243,6 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     }
 }
 
-// Mark the first edge start of every tile window of the current layout (after
-// the layout or the tile window changed outside the step kernels).
-void mark_tiles(sim_handle* h) {
-    const int g = std::max(1, std::min(1024, (h->d.tile_slots + kNT - 1) / kNT));
-    hipLaunchKernelGGL(k_tile_bounds, dim3(g), dim3(kNT), 0, h->stream, h->d);
-    HIP_OK(hipGetLastError());
-}
-
 // The dynamic state at a step boundary, as (device pointer, bytes) pieces.
 template <class F>
 void for_each_state_piece(sim_handle* h, F&& f) {
@@ -277,8 +269,6 @@ void for_each_state_piece(sim_handle* h, F&& f) {
     f((void*)d.qhd, sizeof(int2) * (size_t)std::max(h->nq, 1));
     f((void*)d.tt_sum, 8 * E);
     f((void*)d.tt_cnt, 8 * E);
-    f((void*)d.tile_start[0], 4 * (size_t)d.tile_slots);
-    f((void*)d.tile_start[1], 4 * (size_t)d.tile_slots);
     f((void*)d.ctl, sizeof(Ctl));
     f((void*)d.counters, sizeof(unsigned long long) * cNumCounters * kCounterCopies);
 }
@@ -560,11 +550,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.counters = h->dev<unsigned long long>(cNumCounters * kCounterCopies);
             d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindowMin + 2));
             d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big_max);
-            d.tile_slots = (int)((NV + kTileWindowMin - 1) / kTileWindowMin + 2);
-            {
-                std::vector<int> unmarked((size_t)d.tile_slots, INT_MAX);
-                for (int b = 0; b < 2; ++b) d.tile_start[b] = h->upload(unmarked.data(), unmarked.size());
-            }
             // ---- initial values
             HIP_OK(hipMemset(d.rear, 0xFF, sizeof(LaneRear) * NL));
             HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * NL));
@@ -886,7 +871,6 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         c.n_act[par] = na;
         c.n_departed = departed;
         HIP_OK(hipMemcpy(d.ctl, &c, sizeof(Ctl), hipMemcpyHostToDevice));
-        mark_tiles(h);
         if (in->counters) {
             std::vector<unsigned long long> cc((size_t)cNumCounters * kCounterCopies, 0ull);
             for (int k = 0; k < cNumCounters; ++k) cc[(size_t)k * kCounterCopies] = (unsigned long long)in->counters[k];
@@ -1120,7 +1104,6 @@ bool set_schedule(sim_handle* h, int w, int g1, int g2, int g3, int g4) {
     h->g_big = g2;
     h->g_items = g3;
     h->g_scatter = g4;
-    mark_tiles(h);   // the windows of the current layout under the new tile window
     return true;
 }
 }  // namespace

@@ -79,7 +79,7 @@ struct Ctl {
     int pad[7];
 };
 
-enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8, kErrTileBounds = 16 };
+enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
 
 struct Slots {
     float* x;
@@ -208,8 +208,6 @@ struct Dev {
     int* big_list;
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
-    int* tile_start[2];         // per window: first slot of the window that starts an edge, or INT_MAX
-    int tile_slots;             // entries of each tile_start array
     // traced re-run: record of step t at trace[(t - trace_t0) * trace_stride + slot]
     TraceRec* trace;
     int trace_t0;
@@ -932,31 +930,12 @@ __device__ inline int tile_window(const Dev& d, int n) {
     return W;
 }
 
-// A tile is the set of edges whose first slot lies in one window of W slots.
-// The first edge start of every window of the next layout is marked by the
-// scatter kernel as it writes that layout; this kernel marks them from the
-// current layout instead (after a state write or a schedule change).
-__global__ void __launch_bounds__(kNT) k_tile_bounds(Dev d) {
-    const int t = d.ctl->t_a, par = t & 1;
-    const int n = d.ctl->n_act[par];
-    const int W = tile_window(d, n);
-    const int32_t* edge = d.s[par].edge;
-    for (int k = blockIdx.x * kNT + threadIdx.x; k < d.tile_slots; k += gridDim.x * kNT) {
-        int a0 = INT_MAX;
-        for (int s = k * W; s < min(n, (k + 1) * W); ++s)
-            if (s == 0 || edge[s] != edge[s - 1]) {
-                a0 = s;
-                break;
-            }
-        d.tile_start[par][k] = a0;
-    }
-}
-
 // Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
 // tiles go to a list for k_tile_big.
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kWaves];
+    __shared__ int wsh[kWaves];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
     __shared__ uint2 dtask[kTileDrawTasks];
@@ -978,27 +957,16 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
+    // a tile is the set of edges whose first slot lies in one window
     const int W = tile_window(d, n);
     const int ntile = (n + W - 1) / W;
-    const int* ts = d.tile_start[par];
-    {   // windows of the next step start unmarked (the scatter marks them)
-        int* nx = d.tile_start[par ^ 1];
-        for (int k = blockIdx.x * kNT + threadIdx.x; k < d.tile_slots; k += gridDim.x * kNT) nx[k] = INT_MAX;
-    }
+    const int32_t* edge = d.s[par].edge;
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
-        const int a0 = ts[k];
-        if (a0 == INT_MAX) continue;   // window inside one long edge: handled by an earlier tile
-        int a1 = n;
-        for (int k2 = k + 1; k2 < ntile; ++k2)
-            if (ts[k2] != INT_MAX) {
-                a1 = ts[k2];
-                break;
-            }
+        const int w0 = k * W, w1 = min(n, w0 + W);
+        const int a0 = first_edge_start<kNT>(edge, w0, w1, wsh);
+        if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
+        const int a1 = first_edge_start<kNT>(edge, w1, n, wsh);
         const int cnt = a1 - a0;
-        if (a0 < k * W || a0 >= min(n, (k + 1) * W) || cnt <= 0) {   // marks inconsistent with the layout
-            if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileBounds);
-            continue;
-        }
         if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
             if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileTooBig);
             continue;
@@ -1387,7 +1355,6 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         nnew = d.ctl->n_act[par ^ 1];
     }
     const Slots A = d.s[par], B = d.s[par ^ 1];
-    const int wnext = tile_window(d, nnew);
     for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nl; i += gridDim.x * kNT) {
         float x, v;
         uint32_t vid, meta;
@@ -1436,8 +1403,6 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         B.edge[dst] = edge;
         B.meta[dst] = meta;
         B.nxt[dst] = nxt;
-        if (d.lane_rel[gl] + nr == 0)   // first slot of its edge: mark the window of the next step
-            atomicMin(&d.tile_start[par ^ 1][dst / wnext], dst);
         if (is_rear) {
             LaneRear lr;
             lr.xm = x - d.cp[m_cls(meta)].len;
