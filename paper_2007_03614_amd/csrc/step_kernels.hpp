@@ -1123,9 +1123,15 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     const int l = (int)(threadIdx.x & (kCommitLanes - 1));
     const int e = blockIdx.x * kEdgeBlock + (int)(threadIdx.x / kCommitLanes);
     int nl = 0, base = 0;
+    double tts = 0.0;                              // the edge's travel-time sum and count (lane 0)
+    unsigned long long ttc = 0;
     if (e < d.n_edges) {
         nl = d.lanes[e];
         base = d.lane_base[e];
+        if (l == 0) {
+            tts = d.tt_sum[e];
+            ttc = d.tt_cnt[e];
+        }
     }
     const bool lane_ok = l < nl;
     const int gl = base + l;
@@ -1151,7 +1157,10 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     int kk = 0;
     int64_t r0 = 0;
     if (req) {
+        // every load of this request first, then the decisions and stores
         const uint32_t m = S.meta[ob.slot];
+        const float xs = S.x[ob.slot], vs = S.v[ob.slot];
+        const int hs = d.held_since[ob.vid];
         const double tin = d.tau_in[ob.vid];
         if (ob.target >= 0) {                      // prefetch the route for an entry record
             kk = d.cursor[ob.vid] + 1;
@@ -1164,8 +1173,8 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         if (ob.target < 0) {                       // arrival at the route end
             arrived = exits = true;
             d.status[ob.vid] = kArrived;
-            d.fin_x[ob.vid] = S.x[ob.slot];
-            d.fin_v[ob.vid] = S.v[ob.slot];
+            d.fin_x[ob.vid] = xs;
+            d.fin_v[ob.vid] = vs;
             d.fin_meta[ob.vid] = m;
             acc.c[cArrived]++;
         } else if (won) {
@@ -1176,7 +1185,7 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
             S.x[ob.slot] = d.L[e];
             S.v[ob.slot] = 0.0f;
             S.meta[ob.slot] = m | (1u << 5);
-            if (d.held_since[ob.vid] < 0) d.held_since[ob.vid] = t;
+            if (hs < 0) d.held_since[ob.vid] = t;
             acc.c[cHolds]++;
         }
         if (exits) {
@@ -1203,7 +1212,7 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
         for (int j = 0; j < kCommitLanes; ++j) any = any || kv[j] != 0xFFFFFFFFu;
         if (l == 0 && any) {
             sort8_by_key(kv, kd);
-            double sum = d.tt_sum[e];
+            double sum = tts;
             int nex = 0;
 #pragma unroll
             for (int j = 0; j < kCommitLanes; ++j)
@@ -1212,7 +1221,7 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
                     ++nex;
                 }
             d.tt_sum[e] = sum;
-            d.tt_cnt[e] += (unsigned long long)nex;
+            d.tt_cnt[e] = ttc + (unsigned long long)nex;
         }
     }
     if (exits) {
@@ -1341,6 +1350,8 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     __shared__ int soff[kLds ? kScanLdsMax : 1];
     __shared__ Scan4 wsh4[kWaves];
     __shared__ int tot;
+    __shared__ float slen[16];                    // vehicle length per class
+    if (threadIdx.x < 16) slen[threadIdx.x] = d.cp[threadIdx.x].len;
     const int t = d.ctl->t_b, par = t & 1;
     const int nold = d.ctl->n_act[par];
     const int nl = d.n_lanes_total;
@@ -1353,6 +1364,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     } else {
         boff = d.blk_off;
         nnew = d.ctl->n_act[par ^ 1];
+        __syncthreads();                          // slen
     }
     const Slots A = d.s[par], B = d.s[par ^ 1];
     for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nl; i += gridDim.x * kNT) {
@@ -1361,28 +1373,32 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         int edge, nxt, gl, nr;
         bool is_rear;
         if (i < nold) {
-            meta = A.meta[i];
+            meta = A.meta[i];                     // the whole record first, then its lane
             edge = A.edge[i];
+            x = A.x[i];
+            v = A.v[i];
+            vid = A.vid[i];
+            nxt = A.nxt[i];
             gl = d.lane_base[edge] + m_lane(meta);
             const LanePost lp = d.post[gl];
+            const int ex = d.exit_stamp[gl] == t ? 1 : 0;
+            const int ncnt = d.lane_newcnt[gl];
+            const bool entered = d.enter_stamp[gl] == t;
             if (lp.stamp != t) {
                 atomicOr(&d.ctl->err, kErrScatter);
                 continue;
             }
             const int r = i - lp.start;
-            const int ex = d.exit_stamp[gl] == t ? 1 : 0;
             if (ex && r == 0) continue;           // the lane's front left the edge
             nr = r - ex;
-            is_rear = (nr == d.lane_newcnt[gl] - 1) && (d.enter_stamp[gl] != t);
-            x = A.x[i];
-            v = A.v[i];
-            vid = A.vid[i];
-            nxt = A.nxt[i];
+            is_rear = (nr == ncnt - 1) && !entered;
         } else {                                  // a lane claimed this step takes its entry
             gl = i - nold;
-            if (d.enter_stamp[gl] != t) continue;
+            const bool entered = d.enter_stamp[gl] == t;
             const EntryRec r = d.ent[gl];
-            nr = d.lane_newcnt[gl] - 1;           // the entry is the new rear
+            const int ncnt = d.lane_newcnt[gl];
+            if (!entered) continue;
+            nr = ncnt - 1;                        // the entry is the new rear
             is_rear = true;
             x = r.x;
             v = r.v;
@@ -1405,7 +1421,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
         B.nxt[dst] = nxt;
         if (is_rear) {
             LaneRear lr;
-            lr.xm = x - d.cp[m_cls(meta)].len;
+            lr.xm = x - slen[m_cls(meta)];
             lr.v = v;
             lr.stamp = t + 1;
             lr.vid = vid;
