@@ -157,7 +157,9 @@ def bench_ensemble(args, M, torch, stream):
     upd = c["active_sum"]
     ens.close()
     seq_ms, seq_upd = 0.0, 0
-    for n, red in scen:
+    for k, (n, red) in enumerate(scen):
+        if k % 8 == 0:
+            print(f"sequential handles: {k}/{len(scen)}", file=sys.stderr, flush=True)
         solo = M.Sim(W.scenario_workload(master, n, red), stream=stream)
         torch.cuda.synchronize()
         e0.record(stream)
