@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 BYTES_PER_UPDATE = 48
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_tile_step_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernels_traffic_perturbed_grid_ring.json")
 
 
 def kernel_source_digest() -> str:
