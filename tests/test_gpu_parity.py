@@ -198,6 +198,8 @@ def test_big_tiles_inside_the_tile_kernel(M, tmp_path):
     a, b = ref.state(), fused.state()
     for k in a:
         assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
+    km, _ = fused.step_timed(5)
+    assert km["k_tile_big"] < 1e-3
 
 
 def test_parity_scaled_config2(M, oracle_mod):
