@@ -219,7 +219,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     const bool lds_scan = h->n_blk <= kScanLdsMax;
     if (!ev) {
         hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
-        if (h->g_big > 0) hipLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, d);
+        hipLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, d);
         hipLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, d);
         hipLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, d);
         if (lds_scan) {
@@ -231,12 +231,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
         return;
     }
     hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
-    if (h->g_big > 0) {
-        hipExtLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
-    } else {   // big tiles run inside k_tile_step: an empty interval
-        HIP_OK(hipEventRecord(ev[2], s));
-        HIP_OK(hipEventRecord(ev[3], s));
-    }
+    hipExtLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     hipExtLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, ev[4], ev[5], 0, d);
     if (lds_scan) {
         hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[6], ev[7], 0, d);
@@ -1103,15 +1098,7 @@ sim_status sim_get_schedule(const sim_handle* h, int32_t* sched) {
 namespace {
 bool set_schedule(sim_handle* h, int w, int g1, int g2, int g3, int g4) {
     if (w != 0 && (w < kTileWindowMin || w > kTileWindowMax || (w & (w - 1)) != 0)) return false;
-    if (g1 < 1 || g1 > 1024 || g2 < 0 || g2 > h->g_big_max || g3 < 1 || g4 < 1 || g4 > h->g_scatter_max)
-        return false;
-    if (g2 == 0) {   // big tiles inside the tile kernel: scratch for every tile workgroup
-        const size_t bytes = tile_bytes(h->d.big_cap) * (size_t)1024;
-        if (bytes > kTileScratchMax) return false;
-        if (!h->d.tile_scratch) h->d.tile_scratch = h->dev<char>(bytes);
-    } else {
-        h->d.tile_scratch = nullptr;
-    }
+    if (g1 < 1 || g2 < 1 || g2 > h->g_big_max || g3 < 1 || g4 < 1 || g4 > h->g_scatter_max) return false;
     h->d.tile_window = w;
     h->g_tile = g1;
     h->g_big = g2;
@@ -1166,11 +1153,11 @@ sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
         std::vector<Cand> cands;
         for (int w : {0, 64, 128, 256})
             for (int g1 : {512, 1024})
-                for (int g2 : {0, 32, 256})
+                for (int g2 : {32, 256})
                     for (int g4 : {1024, 4096}) {
                         const int g1c = std::max(1, std::min(g1, (N + (w ? w : kTileWindowMin) - 1) /
                                                                      (w ? w : kTileWindowMin)));
-                        const int g2c = g2 == 0 ? 0 : std::max(1, std::min(g2, h->g_big_max));
+                        const int g2c = std::max(1, std::min(g2, h->g_big_max));
                         const int g4c = std::max(1, std::min(g4, h->g_scatter_max));
                         bool dup = false;
                         for (auto& c : cands) dup = dup || (c.w == w && c.g1 == g1c && c.g2 == g2c && c.g4 == g4c);

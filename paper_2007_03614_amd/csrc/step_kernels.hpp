@@ -40,7 +40,6 @@ constexpr int kCommitLanes = 8;         // threads per edge in k_commit (an edge
 constexpr int kEdgeBlock = kNT / kCommitLanes;   // edges per commit workgroup
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
-constexpr size_t kTileScratchMax = (size_t)1 << 30;   // global scratch of in-kernel big tiles (1 GiB)
 constexpr int kScanLdsMax = 8192;        // edge blocks whose offsets k_scatter scans in LDS (32 KiB)
 constexpr int kCounterCopies = 1024;     // each counter is spread over 1,024 slots (few colliding atomics)
 
@@ -207,9 +206,6 @@ struct Dev {
     // big tiles: (first, end) slot pairs, and global scratch for single
     // edges beyond the LDS of a workgroup
     int* big_list;
-    char* tile_scratch;         // non-null: the tile workgroups process big tiles themselves, from
-                                // this global scratch (tile_bytes(big_cap) per workgroup), and
-                                // k_tile_big is not launched
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
     // traced re-run: record of step t at trace[(t - trace_t0) * trace_stride + slot]
@@ -977,9 +973,6 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         }
         if (cnt <= kTileCapLds) {
             process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
-        } else if (d.tile_scratch) {
-            char* mine = d.tile_scratch + (size_t)blockIdx.x * tile_bytes(d.big_cap);
-            process_tile<kNT>(d, carve(mine, d.big_cap), a0, cnt, t, par, acc, wsh4, scp, dq);
         } else if (threadIdx.x == 0) {
             const int q = atomicAdd(&d.ctl->n_big[par], 1);
             d.big_list[2 * q] = a0;

@@ -146,7 +146,13 @@ def test_parity_long_edge_two_classes(M, oracle_mod):
     assert o.counters()["lane_changes"] > 100
 
 
-def _dense_queue(n=2600):
+def test_parity_dense_queue_big_tiles(M, oracle_mod):
+    """A 16 km two-lane edge that starts as a dense queue of 2,600 vehicles
+    (7.5 m apart, speeds U[0, 6] m/s, written as the state at step 0).  As the
+    queue discharges (about 0.4 vehicles per step), the edge runs first from
+    the global-memory tile scratch (above 1,408 vehicles), then from the LDS
+    of the 1,024-thread kernel; the first steps brake hard (stop branch)."""
+    n = 2600
     w = W.single_edge_workload(length=16000.0, lanes=2, n_vehicles=n, depart_step=np.zeros(n, np.int32),
                                n_steps=0)
     rng = np.random.default_rng(3)
@@ -157,49 +163,11 @@ def _dense_queue(n=2600):
                 v=rng.uniform(0.0, 6.0, n).astype(np.float32), held_since=np.full(n, -1, np.int32),
                 mand=np.zeros(n, np.uint8), ww=np.zeros(n, np.int32), tau_in=np.zeros(n),
                 t_arr=np.full(n, -1.0), counters=None, t=0)
-    return w, init
-
-
-def test_parity_dense_queue_big_tiles(M, oracle_mod):
-    """A 16 km two-lane edge that starts as a dense queue of 2,600 vehicles
-    (7.5 m apart, speeds U[0, 6] m/s, written as the state at step 0).  As the
-    queue discharges (about 0.4 vehicles per step), the edge runs first from
-    the global-memory tile scratch (above 1,408 vehicles), then from the LDS
-    of the 1,024-thread kernel; the first steps brake hard (stop branch)."""
-    n = 2600
-    w, init = _dense_queue(n)
     g, o, bitwise = run_pair(M, oracle_mod, w, [1, 2, 10, 100, 400, 1000, 2000, 3000, 4000], init=init)
     assert bitwise
     c = o.counters()
     assert c["stop_branch"] > 0 and c["lane_changes"] > 0, c
     assert 384 < n - c["arrived"] < 1408, c   # started above the LDS of one workgroup, ends inside it
-
-
-def test_big_tiles_inside_the_tile_kernel(M, tmp_path):
-    """Schedule with no big-tile launch (big-tile workgroups 0): tiles above
-    the LDS of a workgroup then run inside k_tile_step from global scratch.
-    Results must equal the default schedule's bit for bit."""
-    w, init = _dense_queue()
-    ref = M.Sim(w)
-    ref.write_state(init)
-    ref.step(1500)
-    sched = ref.schedule()
-    assert sched[2] > 0
-    forced = [sched[0], sched[1], 0, sched[3], sched[4]]
-    key = f"manta-schedule E={w.net.n_edges} L={int(w.net.lanes.sum())} N={w.n_vehicles} S=1"
-    path = tmp_path / "sched.txt"
-    path.write_text(f"{key} -> {' '.join(map(str, forced))}\n")
-    fused = M.Sim(w)
-    fused.write_state(init)
-    fused.autotune(str(path))
-    assert fused.schedule() == forced
-    for cp in (1, 10, 500, 1500):
-        fused.step(cp - fused.state()["t"])
-    a, b = ref.state(), fused.state()
-    for k in a:
-        assert np.array_equal(np.asarray(a[k]), np.asarray(b[k])), k
-    km, _ = fused.step_timed(5)
-    assert km["k_tile_big"] < 1e-3
 
 
 def test_parity_scaled_config2(M, oracle_mod):
