@@ -35,7 +35,7 @@ constexpr int kTileWindowMax = 256;      // a tile = the edges whose first slot 
 constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256)
 constexpr int kTileCapLds = 384;         // tiles up to this size are staged in LDS (4 workgroups per CU)
 constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
-constexpr int kTileDrawTasks = 128;      // listed Philox blocks per tile round (more are computed in place)
+constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
 constexpr int kCommitLanes = 8;         // threads per edge in k_commit (an edge has at most 8 lanes)
 constexpr int kEdgeBlock = kNT / kCommitLanes;   // edges per commit workgroup
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
@@ -423,8 +423,8 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
 // sums are integers, so the order of the additions does not matter and the
 // result equals draw_uniform / draw_normal exactly.
 struct DrawQ {
-    uint2* task;   // [cap] {rid, q << 4 | stream << 2 | block}
-    int* n;        // [2] tasks listed in each round
+    uint32_t* task;   // [cap] q << 4 | stream << 2 | block
+    int* n;           // [2] tasks listed in each round
     int cap;
 };
 
@@ -438,18 +438,19 @@ __device__ inline uint32_t philox_words(uint64_t seed, int t, uint32_t rid, int 
 __device__ inline void draw_task(const DrawQ& dq, int round, uint32_t rid, int q, int stream, int blk, int* slot,
                                  uint64_t seed, int t) {
     const int k = atomicAdd(&dq.n[round], 1);
-    if (k < dq.cap) dq.task[k] = make_uint2(rid, ((uint32_t)q << 4) | ((uint32_t)stream << 2) | (uint32_t)blk);
+    if (k < dq.cap) dq.task[k] = ((uint32_t)q << 4) | ((uint32_t)stream << 2) | (uint32_t)blk;
     else atomicAdd(&slot[q], (int)philox_words(seed, t, rid, stream, blk));
 }
 
 template <int NT>
-__device__ inline void draw_run(const DrawQ& dq, int round, uint64_t seed, int t, int* u1, int* na, int* nb) {
+__device__ inline void draw_run(const DrawQ& dq, int round, uint64_t seed, int t, const uint32_t* rid, int* u1,
+                                int* na, int* nb) {
     const int nt = min(dq.n[round], dq.cap);
     for (int i = threadIdx.x; i < nt; i += NT) {
-        const uint2 tk = dq.task[i];
-        const int q = (int)(tk.y >> 4), st = (int)((tk.y >> 2) & 3u), blk = (int)(tk.y & 3u);
+        const uint32_t tk = dq.task[i];
+        const int q = (int)(tk >> 4), st = (int)((tk >> 2) & 3u), blk = (int)(tk & 3u);
         int* slot = st == 1 ? u1 : (st == 2 ? na : nb);
-        atomicAdd(&slot[q], (int)philox_words(seed, t, tk.x, st, blk));
+        atomicAdd(&slot[q], (int)philox_words(seed, t, rid[q], st, blk));
     }
 }
 
@@ -533,7 +534,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         }
     }
     __syncthreads();
-    draw_run<NT>(dq, 0, d.seed, t, u1, na, nb);
+    draw_run<NT>(dq, 0, d.seed, t, b.rid, u1, na, nb);
 
     // ---- runs of S_t (tile order: edge, lane, then x and id descending)
     {
@@ -662,7 +663,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.meta[q] = m;
     }
     __syncthreads();
-    draw_run<NT>(dq, 1, d.seed, t, u1, na, nb);
+    draw_run<NT>(dq, 1, d.seed, t, b.rid, u1, na, nb);
     __syncthreads();
     if (tid < 2) dq.n[tid] = 0;   // lists of the next tile (several barriers away)
 
@@ -938,7 +939,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ int wsh[kWaves];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
-    __shared__ uint2 dtask[kTileDrawTasks];
+    __shared__ uint32_t dtask[kTileDrawTasks];
     __shared__ int dcount[2];
     const DrawQ dq{dtask, dcount, kTileDrawTasks};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
@@ -991,9 +992,9 @@ __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
     __shared__ int wsh[kBigNT / 64];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
-    __shared__ uint2 dtask[kBigNT];
+    __shared__ uint32_t dtask[2 * kBigNT];
     __shared__ int dcount[2];
-    const DrawQ dq{dtask, dcount, kBigNT};
+    const DrawQ dq{dtask, dcount, 2 * kBigNT};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
