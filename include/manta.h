@@ -178,10 +178,10 @@ sim_status sim_ensemble_offsets(const sim_handle *h, int32_t *n_scen, int32_t *v
  * never depend on the schedule. */
 sim_status sim_autotune(sim_handle *h, const char *cache_path, int32_t steps_per_trial);
 
-/* Current schedule: [tile_window, tile_workgroups, big_tile_workgroups,
- * admit_workgroups, scatter_workgroups].  tile_window 0 (the default) picks
- * 64 or 128 slots at every step: the smallest whose tiles fit in one round
- * of the tile workgroups the device holds at once. */
+/* Current schedule, sched[4]: [tile_window, tile_workgroups,
+ * big_tile_and_admission_workgroups, scatter_workgroups].  tile_window 0 (the
+ * default) picks 64 or 128 slots at every step: the smallest whose tiles fit
+ * in one round of the tile workgroups the device holds at once. */
 sim_status sim_get_schedule(const sim_handle *h, int32_t *sched);
 
 /* Stream for all later device work of h (a hipStream_t; NULL = null stream).
@@ -200,8 +200,8 @@ sim_status sim_step(sim_handle *h, int32_t n);
  * identical to sim_step. */
 enum {
     SIM_K_TILE_STEP = 0,   /* lane changes, leaders, Eq. (1), integration */
-    SIM_K_TILE_BIG,        /* the same for tiles above 512 vehicles */
-    SIM_K_ADMIT,           /* intersection admission: eligibility + priority claim */
+    SIM_K_BIG_ADMIT,       /* the same for tiles above 384 vehicles, then intersection
+                              admission: eligibility + priority claim */
     SIM_K_COMMIT,          /* transfers, arrivals, departures, travel times, new counts */
     SIM_K_SCATTER,         /* next sorted layout and look-ahead table */
     SIM_N_KERNELS
@@ -231,6 +231,11 @@ sim_status sim_destroy(sim_handle *h);
 /* Message of the last failed call on h (or of the last failed sim_create when
  * h is NULL).  Valid until the next call on the same handle. */
 const char *sim_last_error(const sim_handle *h);
+
+/* Vehicle-updates done in tiles above one workgroup's LDS (inside
+ * k_big_admit) since the handle's state was last written; the rest were done
+ * by k_tile_step.  Synchronizes the handle's stream.  For measurement only. */
+sim_status sim_big_tile_updates(sim_handle *h, int64_t *updates);
 
 /* ------------------------------------------------------------------ diagnostics
  * Device-side evaluation of the arithmetic building blocks, for checking that

@@ -94,6 +94,8 @@ _lib.sim_ensemble_offsets.argtypes = [P, P, P]
 _lib.sim_ensemble_offsets.restype = I32
 _lib.sim_autotune.argtypes = [P, ctypes.c_char_p, I32]
 _lib.sim_autotune.restype = I32
+_lib.sim_big_tile_updates.argtypes = [P, P]
+_lib.sim_big_tile_updates.restype = I32
 _lib.sim_get_schedule.argtypes = [P, P]
 _lib.sim_get_schedule.restype = I32
 _lib.sim_backward.argtypes = [P, P, P]
@@ -105,11 +107,12 @@ _lib.sim_probe_philox.restype = I32
 _lib.sim_probe_draws.argtypes = [U64, P, P, P, P, P, I64]
 _lib.sim_probe_draws.restype = I32
 
-KERNELS = ["k_tile_step", "k_tile_big", "k_admit", "k_commit", "k_scatter"]
+KERNELS = ["k_tile_step", "k_big_admit", "k_commit", "k_scatter"]
 
 EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
             "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",
             "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_get_schedule", "sim_backward",
+            "sim_big_tile_updates",
             "sim_probe_fp32", "sim_probe_philox", "sim_probe_draws"]
 
 
@@ -267,8 +270,15 @@ class Sim:
         _check(_lib.sim_autotune(self._h, cp, int(steps_per_trial)), self._h)
         return self.schedule()
 
+    def big_tile_updates(self) -> int:
+        """Vehicle-updates done in tiles above one workgroup's LDS since the
+        state was last written (sim_big_tile_updates)."""
+        out = np.zeros(1, np.int64)
+        _check(_lib.sim_big_tile_updates(self._h, _p(out)), self._h)
+        return int(out[0])
+
     def schedule(self) -> list:
-        out = np.zeros(5, np.int32)
+        out = np.zeros(4, np.int32)
         _check(_lib.sim_get_schedule(self._h, _p(out)), self._h)
         return out.tolist()
 

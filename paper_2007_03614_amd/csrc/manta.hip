@@ -76,8 +76,8 @@ struct sim_handle {
     Dev d{};
     int t = 0;
     int n_veh = 0, n_edges = 0, n_lanes = 0, n_classes = 0;
-    int g_tile = 1, g_big = 1, g_items = 1, g_scatter = 1, n_blk = 1;
-    int g_big_max = 1, g_scatter_max = 1;
+    int g_tile = 1, g_big = 1, g_scatter = 1, n_blk = 1;
+    int g_big_min = 1, g_big_max = 1, g_scatter_max = 1;
     int n_scen = 1;
     std::vector<int32_t> veh_off;   // ensemble: vehicles of scenario k
     // differentiable form: a snapshot of the dynamic state every rec_every steps
@@ -219,8 +219,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     const bool lds_scan = h->n_blk <= kScanLdsMax;
     if (!ev) {
         hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
-        hipLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, d);
-        hipLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, d);
+        hipLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, d);
         hipLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, d);
         if (lds_scan) {
             hipLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, d);
@@ -231,15 +230,14 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
         return;
     }
     hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
-    hipExtLaunchKernelGGL(k_tile_big, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
-    hipExtLaunchKernelGGL(k_admit, dim3(h->g_items), b, 0, s, ev[4], ev[5], 0, d);
+    hipExtLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     if (lds_scan) {
-        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[6], ev[7], 0, d);
-        hipExtLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, ev[8], ev[9], 0, d);
+        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[4], ev[5], 0, d);
+        hipExtLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, ev[6], ev[7], 0, d);
     } else {   // the block scan is counted with commit
-        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[6], nullptr, 0, d);
-        hipExtLaunchKernelGGL(k_blkscan, dim3(1), dim3(kBigNT), 0, s, nullptr, ev[7], 0, d);
-        hipExtLaunchKernelGGL(k_scatter<false>, dim3(h->g_scatter), b, 0, s, ev[8], ev[9], 0, d);
+        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[4], nullptr, 0, d);
+        hipExtLaunchKernelGGL(k_blkscan, dim3(1), dim3(kBigNT), 0, s, nullptr, ev[5], 0, d);
+        hipExtLaunchKernelGGL(k_scatter<false>, dim3(h->g_scatter), b, 0, s, ev[6], ev[7], 0, d);
     }
 }
 
@@ -507,10 +505,18 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             }
             d.tile_window = 0;
             h->g_tile = std::max(1, std::min(1024, (N + kTileWindowMin - 1) / kTileWindowMin));
-            h->g_big_max = std::max(1, std::min(256, (N + kTileWindowMin - 1) / kTileWindowMin));
-            h->g_big = std::max(1, std::min(32, h->g_big_max));
+            {   // k_big_admit: every workgroup resident (its grid barrier), enough threads
+                // for one admission item each where that fits
+                int dev = 0, cus = 0, per_cu = 0;
+                HIP_OK(hipGetDevice(&dev));
+                HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_big_admit, kBigNT, 0));
+                h->g_big_max = std::max(1, cus * std::max(per_cu, 1));
+                const long long items = (long long)NL + (long long)h->nq;
+                h->g_big_min = (int)std::max(1LL, std::min<long long>(h->g_big_max, (items + kBigNT - 1) / kBigNT));
+                h->g_big = h->g_big_min;
+            }
             h->g_scatter_max = std::max(1, std::min(4096, (N + kNT - 1) / kNT));
-            h->g_items = std::max(1, std::min(512, (int)((NL + N + kNT - 1) / kNT)));
             h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
             h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
             d.n_blk = h->n_blk;
@@ -1090,19 +1096,17 @@ sim_status sim_get_schedule(const sim_handle* h, int32_t* sched) {
     sched[0] = h->d.tile_window;
     sched[1] = h->g_tile;
     sched[2] = h->g_big;
-    sched[3] = h->g_items;
-    sched[4] = h->g_scatter;
+    sched[3] = h->g_scatter;
     return SIM_OK;
 }
 
 namespace {
-bool set_schedule(sim_handle* h, int w, int g1, int g2, int g3, int g4) {
+bool set_schedule(sim_handle* h, int w, int g1, int g2, int g4) {
     if (w != 0 && (w < kTileWindowMin || w > kTileWindowMax || (w & (w - 1)) != 0)) return false;
-    if (g1 < 1 || g2 < 1 || g2 > h->g_big_max || g3 < 1 || g4 < 1 || g4 > h->g_scatter_max) return false;
+    if (g1 < 1 || g2 < h->g_big_min || g2 > h->g_big_max || g4 < 1 || g4 > h->g_scatter_max) return false;
     h->d.tile_window = w;
     h->g_tile = g1;
     h->g_big = g2;
-    h->g_items = g3;
     h->g_scatter = g4;
     return true;
 }
@@ -1116,12 +1120,12 @@ sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
         if (cache_path) {
             if (FILE* f = fopen(cache_path, "r")) {
                 char line[256];
-                int w, g1, g2, g3, g4;
+                int w, g1, g2, g4;
                 bool hit = false;
                 while (fgets(line, sizeof(line), f)) {
                     if (strncmp(line, key, strlen(key)) == 0 && line[strlen(key)] == ' ' &&
-                        sscanf(line + strlen(key), " -> %d %d %d %d %d", &w, &g1, &g2, &g3, &g4) == 5 &&
-                        set_schedule(h, w, g1, g2, g3, g4))
+                        sscanf(line + strlen(key), " -> %d %d %d %d", &w, &g1, &g2, &g4) == 4 &&
+                        set_schedule(h, w, g1, g2, g4))
                         hit = true;
                 }
                 fclose(f);
@@ -1146,30 +1150,29 @@ sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
         std::vector<unsigned long long> ttc(E);
         HIP_OK(hipMemcpy(tts.data(), h->d.tt_sum, 8 * E, hipMemcpyDeviceToHost));
         HIP_OK(hipMemcpy(ttc.data(), h->d.tt_cnt, 8 * E, hipMemcpyDeviceToHost));
-        const int w0 = h->d.tile_window, g10 = h->g_tile, g20 = h->g_big, g30 = h->g_items, g40 = h->g_scatter;
+        const int w0 = h->d.tile_window, g10 = h->g_tile, g20 = h->g_big, g40 = h->g_scatter;
         struct Cand {
-            int w, g1, g2, g3, g4;
+            int w, g1, g2, g4;
         };
         std::vector<Cand> cands;
         for (int w : {0, 64, 128, 256})
             for (int g1 : {512, 1024})
-                for (int g2 : {32, 256})
+                for (int g2 : {h->g_big_min, h->g_big_max})
                     for (int g4 : {1024, 4096}) {
                         const int g1c = std::max(1, std::min(g1, (N + (w ? w : kTileWindowMin) - 1) /
                                                                      (w ? w : kTileWindowMin)));
-                        const int g2c = std::max(1, std::min(g2, h->g_big_max));
                         const int g4c = std::max(1, std::min(g4, h->g_scatter_max));
                         bool dup = false;
-                        for (auto& c : cands) dup = dup || (c.w == w && c.g1 == g1c && c.g2 == g2c && c.g4 == g4c);
-                        if (!dup) cands.push_back(Cand{w, g1c, g2c, g30, g4c});
+                        for (auto& c : cands) dup = dup || (c.w == w && c.g1 == g1c && c.g2 == g2 && c.g4 == g4c);
+                        if (!dup) cands.push_back(Cand{w, g1c, g2, g4c});
                     }
         double best_ms = 1e30;
-        Cand best{w0, g10, g20, g30, g40};
+        Cand best{w0, g10, g20, g40};
         hipEvent_t e0, e1;
         HIP_OK(hipEventCreate(&e0));
         HIP_OK(hipEventCreate(&e1));
         for (const Cand& c : cands) {
-            if (!set_schedule(h, c.w, c.g1, c.g2, c.g3, c.g4)) continue;
+            if (!set_schedule(h, c.w, c.g1, c.g2, c.g4)) continue;
             if (sim_write_state(h, &snap) != SIM_OK) throw Fail{SIM_EDEVICE, h->err};
             launch_step(h, h->stream);   // first launch of a schedule is not timed
             HIP_OK(hipEventRecord(e0, h->stream));
@@ -1185,17 +1188,27 @@ sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
         }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
-        set_schedule(h, best.w, best.g1, best.g2, best.g3, best.g4);
+        set_schedule(h, best.w, best.g1, best.g2, best.g4);
         if (sim_write_state(h, &snap) != SIM_OK) throw Fail{SIM_EDEVICE, h->err};
         HIP_OK(hipMemcpy(h->d.tt_sum, tts.data(), 8 * E, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(h->d.tt_cnt, ttc.data(), 8 * E, hipMemcpyHostToDevice));
         capture_graph(h);
         if (cache_path) {
             if (FILE* f = fopen(cache_path, "a")) {
-                fprintf(f, "%s -> %d %d %d %d %d\n", key, best.w, best.g1, best.g2, best.g3, best.g4);
+                fprintf(f, "%s -> %d %d %d %d\n", key, best.w, best.g1, best.g2, best.g4);
                 fclose(f);
             }
         }
+    });
+}
+
+sim_status sim_big_tile_updates(sim_handle* h, int64_t* updates) {
+    if (!h || !updates) return SIM_EINVAL;
+    return guarded(h, [&] {
+        Ctl c;
+        HIP_OK(hipStreamSynchronize(h->stream));
+        HIP_OK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+        *updates = (int64_t)c.big_updates;
     });
 }
 

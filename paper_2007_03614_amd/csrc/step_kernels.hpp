@@ -8,12 +8,12 @@
 // stamped with the step they are valid for), the rear after the move
 // (admission), and the post-lane-change run of each lane (scatter).
 //
-// One step = 5 launches (6 on networks above 262,144 edges), all reading the
+// One step = 4 launches (5 on networks above 262,144 edges), all reading the
 // step number from device memory, so a captured graph of one step can be
 // replayed for every step:
 //   k_tile_step   Phases 1-2 per tile of whole edges, staged in LDS
-//   k_tile_big    the same for tiles above 384 vehicles (1,024 threads)
-//   k_admit       eligibility + atomicMin of a 64-bit priority key per lane
+//   k_big_admit   the same for tiles above 384 vehicles (1,024 threads), then
+//                 eligibility + atomicMin of a 64-bit priority key per lane
 //   k_commit      eight threads per edge, one per lane: winners, losers,
 //                 arrivals, departures, travel-time sums, new lane counts and
 //                 edge offsets within the workgroup
@@ -40,6 +40,7 @@ constexpr int kCommitLanes = 8;         // threads per edge in k_commit (an edge
 constexpr int kEdgeBlock = kNT / kCommitLanes;   // edges per commit workgroup
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
+constexpr unsigned long long kBarrierTimeout = 20000000ull;   // 0.2 s of the 100 MHz clock
 constexpr int kScanLdsMax = 8192;        // edge blocks whose offsets k_scatter scans in LDS (32 KiB)
 constexpr int kCounterCopies = 1024;     // each counter is spread over 1,024 slots (few colliding atomics)
 
@@ -67,19 +68,22 @@ enum Counter {
 
 struct Ctl {
     // The step number, kept twice so that no kernel has to change a value its
-    // own workgroups are still reading: the tile kernels and k_admit read t_a,
+    // own workgroups are still reading: the tile kernels and admission read t_a,
     // k_commit and k_scatter read t_b.  k_tile_step sets t_b = t_a; the
     // workgroup that finishes the step (finish_step) sets t_a = t + 1.
     int t_a;
     int t_b;
     int n_act[2];
-    int n_big[2];     // tiles above kTileCapLds, listed for k_tile_big
+    int n_big[2];     // tiles above kTileCapLds, listed for k_big_admit
     int err;          // non-zero: a layout bound check failed (see kErr*)
     int n_departed;   // vehicles admitted from the departure queues so far
-    int pad[7];
+    unsigned big_done;   // workgroups of k_big_admit past their big tiles (steps with big tiles)
+    int pad0;
+    unsigned long long big_updates;   // vehicle-updates done in big tiles (measurement)
+    int pad[2];
 };
 
-enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8 };
+enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8, kErrBarrier = 16 };
 
 struct Slots {
     float* x;
@@ -127,7 +131,7 @@ struct Outbox {       // end-of-edge request of a lane's front vehicle
     float xp;         // position on the next edge
     float phi;        // fraction of the step at which the stop line was crossed
     uint64_t key;     // admission priority (smaller first)
-    int elig;         // set by k_admit: the request passed the no-overlap test
+    int elig;         // set by admission: the request passed the no-overlap test
     uint32_t tl_cls;  // lane on the next edge | class << 8
     float v;          // speed after the step
     int nxt;          // next edge (-1 for an arrival)
@@ -932,7 +936,7 @@ __device__ inline int tile_window(const Dev& d, int n) {
 }
 
 // Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
-// tiles go to a list for k_tile_big.
+// tiles go to a list for k_big_admit.
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kWaves];
@@ -955,6 +959,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         // are unused during this one
         d.ctl->t_b = t;
         d.ctl->n_big[par ^ 1] = 0;
+        d.ctl->big_done = 0;
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
@@ -986,7 +991,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
 // Tiles above kTileCapLds: 1,024-thread workgroups with kBigCapLds vehicles
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
 // single edge larger than the LDS runs from the global-memory scratch.
-__global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
+__device__ inline void big_tiles(const Dev& d, int t, int par, int nbig) {
     __shared__ __align__(16) char lds[kBigCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kBigNT / 64];
     __shared__ int wsh[kBigNT / 64];
@@ -999,8 +1004,6 @@ __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
     if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     __syncthreads();
-    const int t = d.ctl->t_a, par = t & 1;
-    const int nbig = d.ctl->n_big[par];
     const int32_t* edge = d.s[par].edge;
     CounterAcc acc;
     acc.zero();
@@ -1031,6 +1034,7 @@ __global__ void __launch_bounds__(kBigNT) k_tile_big(Dev d) {
                 if (end < 0) end = first_edge_start<kBigNT>(edge, lim, a1, wsh);   // one edge beyond the LDS
             }
             const int cnt = end - pos;
+            if (threadIdx.x == 0) atomicAdd(&d.ctl->big_updates, (unsigned long long)cnt);
             if (cnt <= kBigCapLds) {
                 process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp, dq);
             } else {
@@ -1057,15 +1061,36 @@ __device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t
     d.enter_stamp[gl] = t;   // every claimant stores the same step
 }
 
+// Grid barrier of k_big_admit: every workgroup is resident (one per CU at
+// most, checked at launch), and the wait ends after kBarrierTimeout of the
+// 100 MHz clock at the latest, with an error flag instead of a hang.
+__device__ inline void grid_barrier(const Dev& d, unsigned* counter) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();                           // this workgroup's writes, device-wide
+        atomicAdd(counter, 1u);
+        const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
+        while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
+            if (__builtin_amdgcn_s_memrealtime() - t0 > kBarrierTimeout) {
+                atomicOr(&d.ctl->err, kErrBarrier);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+        }
+        __threadfence();
+    }
+    __syncthreads();
+}
+
 // One item per lane (its front may have asked to leave the edge this step)
 // and one per departure queue.  A request is eligible if it does not overlap
 // the target lane's rear after the move; a due queue head if the lane's rear
 // leaves it s0 at x = 0.
-__global__ void __launch_bounds__(kNT) k_admit(Dev d) {
-    const int t = d.ctl->t_a;
+template <int NT>
+__device__ inline void admit_items(const Dev& d, int t) {
     const int nl = d.n_lanes_total;
     const int total = nl + d.nq;
-    for (int i = blockIdx.x * kNT + threadIdx.x; i < total; i += gridDim.x * kNT) {
+    for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
         if (i < nl) {
             const Outbox ob = d.outbox[i];
             if (ob.stamp != t || ob.target < 0) continue;   // no request, or an arrival
@@ -1083,6 +1108,20 @@ __global__ void __launch_bounds__(kNT) k_admit(Dev d) {
             }
         }
     }
+}
+
+// The tiles above one workgroup's LDS, then admission, in one launch (one
+// launch less per step).  Admission reads the post-move rears that big tiles
+// write, so on a step with big tiles all workgroups meet at a grid barrier in
+// between; most steps have none and skip it.
+__global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
+    const int t = d.ctl->t_a, par = t & 1;
+    const int nbig = d.ctl->n_big[par];
+    if (nbig > 0) {
+        big_tiles(d, t, par, nbig);
+        grid_barrier(d, &d.ctl->big_done);
+    }
+    admit_items<kBigNT>(d, t);
 }
 
 // Sort eight (key, value) pairs by key, ascending, with the 19-comparator
@@ -1327,7 +1366,7 @@ __device__ inline void finish_step(const Dev& d, int t, int par, int total) {
     const int departed = d.ctl->n_departed;
     if (due_now > departed)
         atomicAdd(&d.counters[cInsertDenied * kCounterCopies], (unsigned long long)(due_now - departed));
-    d.ctl->t_a = t + 1;   // the tile kernels and k_admit of this step are done
+    d.ctl->t_a = t + 1;   // the tile kernels and admission of this step are done
 }
 
 // Networks with more edge blocks than kScanLdsMax: one workgroup scans the

@@ -168,6 +168,8 @@ def test_parity_dense_queue_big_tiles(M, oracle_mod):
     c = o.counters()
     assert c["stop_branch"] > 0 and c["lane_changes"] > 0, c
     assert 384 < n - c["arrived"] < 1408, c   # started above the LDS of one workgroup, ends inside it
+    # every step had a big tile: the big-tile part and the grid barrier of k_big_admit ran
+    assert g.big_tile_updates() == c["active_sum"]
 
 
 def test_parity_scaled_config2(M, oracle_mod):
