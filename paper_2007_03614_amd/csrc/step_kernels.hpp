@@ -78,7 +78,7 @@ struct Ctl {
     int err;          // non-zero: a layout bound check failed (see kErr*)
     int n_departed;   // vehicles admitted from the departure queues so far
     unsigned big_done;   // workgroups of k_big_admit past their big tiles (steps with big tiles)
-    int pad0;
+    unsigned cs_done;    // workgroups of k_commit_scatter past their commit blocks
     unsigned long long big_updates;   // vehicle-updates done in big tiles (measurement)
     int pad[2];
 };
@@ -960,6 +960,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         d.ctl->t_b = t;
         d.ctl->n_big[par ^ 1] = 0;
         d.ctl->big_done = 0;
+        d.ctl->cs_done = 0;
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
@@ -1151,17 +1152,10 @@ __device__ inline void sort8_by_key(uint32_t* k, double* v) {
 //   * inserts the departure whose key won its lane;
 //   * counts its vehicles for the next layout.
 // The edge's travel-time sum adds the exits in ascending vehicle id.
-__global__ void __launch_bounds__(kNT) k_commit(Dev d) {
-    __shared__ unsigned shc[cNumCounters];
-    __shared__ Scan4 wsh4[kWaves];
-    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
-    __syncthreads();
-    const int t = d.ctl->t_b, par = t & 1;
+__device__ inline void commit_block(const Dev& d, int blk, int t, int par, CounterAcc& acc, Scan4* wsh4) {
     const Slots S = d.s[par];
-    CounterAcc acc;
-    acc.zero();
     const int l = (int)(threadIdx.x & (kCommitLanes - 1));
-    const int e = blockIdx.x * kEdgeBlock + (int)(threadIdx.x / kCommitLanes);
+    const int e = blk * kEdgeBlock + (int)(threadIdx.x / kCommitLanes);
     int nl = 0, base = 0;
     double tts = 0.0;                              // the edge's travel-time sum and count (lane 0)
     unsigned long long ttc = 0;
@@ -1330,9 +1324,24 @@ __global__ void __launch_bounds__(kNT) k_commit(Dev d) {
     // offsets of the edges in the workgroup (one value per edge, at its lane 0)
     Scan4 run = wg_exclusive_scan4(Scan4{l == 0 ? c : 0, -1, -1, -1}, wsh4);
     if (l == 0 && e < d.n_edges) d.edge_rel[e] = run.s;
-    if (threadIdx.x == kNT - 1) d.blk_sum[blockIdx.x] = run.s + (l == 0 ? c : 0);
+    if (threadIdx.x == kNT - 1) d.blk_sum[blk] = run.s + (l == 0 ? c : 0);
+}
+
+__device__ inline void flush_commit_counters(const Dev& d, const CounterAcc& acc, unsigned* shc) {
     flush_counters_lds(d, acc, shc);   // ends with a barrier: shc is complete
     if (threadIdx.x == 0 && shc[cDeparted]) atomicAdd(&d.ctl->n_departed, (int)shc[cDeparted]);
+}
+
+__global__ void __launch_bounds__(kNT) k_commit(Dev d) {
+    __shared__ unsigned shc[cNumCounters];
+    __shared__ Scan4 wsh4[kWaves];
+    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = d.ctl->t_b, par = t & 1;
+    CounterAcc acc;
+    acc.zero();
+    commit_block(d, blockIdx.x, t, par, acc, wsh4);
+    flush_commit_counters(d, acc, shc);
 }
 
 // ---- offsets of the edge blocks and the end of the step --------------------
@@ -1386,11 +1395,7 @@ __global__ void __launch_bounds__(kBigNT) k_blkscan(Dev d) {
 // kScanLdsMax edge blocks), and workgroup 0 finishes the step; otherwise
 // k_blkscan has done both.
 template <bool kLds>
-__global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
-    __shared__ int soff[kLds ? kScanLdsMax : 1];
-    __shared__ Scan4 wsh4[kWaves];
-    __shared__ int tot;
-    __shared__ float slen[16];                    // vehicle length per class
+__device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* totp, float* slen) {
     if (threadIdx.x < 16) slen[threadIdx.x] = d.cp[threadIdx.x].len;
     const int t = d.ctl->t_b, par = t & 1;
     const int nold = d.ctl->n_act[par];
@@ -1398,7 +1403,7 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     const int* boff;
     int nnew;
     if (kLds) {
-        nnew = scan_block_sums<kNT>(d.blk_sum, d.n_blk, soff, wsh4, &tot);
+        nnew = scan_block_sums<kNT>(d.blk_sum, d.n_blk, soff, wsh4, totp);
         boff = soff;
         if (blockIdx.x == 0 && threadIdx.x == 0) finish_step(d, t, par, nnew);
     } else {
@@ -1468,6 +1473,36 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
             d.rear[gl] = lr;
         }
     }
+}
+
+template <bool kLds>
+__global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
+    __shared__ int soff[kLds ? kScanLdsMax : 1];
+    __shared__ Scan4 wsh4[kWaves];
+    __shared__ int tot;
+    __shared__ float slen[16];                    // vehicle length per class
+    scatter_items<kLds>(d, soff, wsh4, &tot, slen);
+}
+
+// Commit and scatter in one launch: the grid (at most what the device holds
+// at once) commits the edge blocks, meets at a grid barrier, then writes the
+// next layout.  Used when the block offsets fit the LDS (dynamic, 4 B per
+// edge block).
+__global__ void __launch_bounds__(kNT) k_commit_scatter(Dev d) {
+    extern __shared__ int soff_dyn[];
+    __shared__ unsigned shc[cNumCounters];
+    __shared__ Scan4 wsh4[kWaves];
+    __shared__ int tot;
+    __shared__ float slen[16];
+    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    __syncthreads();
+    const int t = d.ctl->t_b, par = t & 1;
+    CounterAcc acc;
+    acc.zero();
+    for (int blk = blockIdx.x; blk < d.n_blk; blk += gridDim.x) commit_block(d, blk, t, par, acc, wsh4);
+    flush_commit_counters(d, acc, shc);
+    grid_barrier(d, &d.ctl->cs_done);
+    scatter_items<true>(d, soff_dyn, wsh4, &tot, slen);
 }
 
 // ---- differentiable form: reverse sweep of one step ----------------------
