@@ -77,7 +77,6 @@ struct sim_handle {
     int t = 0;
     int n_veh = 0, n_edges = 0, n_lanes = 0, n_classes = 0;
     int g_tile = 1, g_big = 1, g_scatter = 1, n_blk = 1;
-    int g_cs = 0;                      // > 0: commit and scatter in one launch of g_cs workgroups
     int g_big_min = 1, g_big_max = 1, g_scatter_max = 1;
     int n_scen = 1;
     std::vector<int32_t> veh_off;   // ensemble: vehicles of scenario k
@@ -218,14 +217,9 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     const Dev& d = h->d;
     const dim3 b(kNT);
     const bool lds_scan = h->n_blk <= kScanLdsMax;
-    const size_t cs_lds = 4 * (size_t)h->n_blk;
     if (!ev) {
         hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
         hipLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, d);
-        if (h->g_cs > 0) {
-            hipLaunchKernelGGL(k_commit_scatter, dim3(h->g_cs), b, cs_lds, s, d);
-            return;
-        }
         hipLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, d);
         if (lds_scan) {
             hipLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, d);
@@ -237,11 +231,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     }
     hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
     hipExtLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
-    if (h->g_cs > 0) {   // commit and scatter in one launch: counted as commit
-        hipExtLaunchKernelGGL(k_commit_scatter, dim3(h->g_cs), b, cs_lds, s, ev[4], ev[5], 0, d);
-        HIP_OK(hipEventRecord(ev[6], s));
-        HIP_OK(hipEventRecord(ev[7], s));
-    } else if (lds_scan) {
+    if (lds_scan) {
         hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[4], ev[5], 0, d);
         hipExtLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, ev[6], ev[7], 0, d);
     } else {   // the block scan is counted with commit
@@ -530,14 +520,6 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
             h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
             d.n_blk = h->n_blk;
-            if (h->n_blk <= kScanLdsMax) {   // commit + scatter in one launch, all workgroups resident
-                int dev = 0, cus = 0, per_cu = 0;
-                HIP_OK(hipGetDevice(&dev));
-                HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_commit_scatter, kNT,
-                                                                    4 * (size_t)h->n_blk));
-                h->g_cs = std::max(0, std::min(h->n_blk, cus * per_cu));
-            }
             // ---- dynamic state
             const size_t NV = std::max(N, 1);
             for (int b = 0; b < 2; ++b) {

@@ -78,7 +78,7 @@ struct Ctl {
     int err;          // non-zero: a layout bound check failed (see kErr*)
     int n_departed;   // vehicles admitted from the departure queues so far
     unsigned big_done;   // workgroups of k_big_admit past their big tiles (steps with big tiles)
-    unsigned cs_done;    // workgroups of k_commit_scatter past their commit blocks
+    int pad0;
     unsigned long long big_updates;   // vehicle-updates done in big tiles (measurement)
     int pad[2];
 };
@@ -960,7 +960,6 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
         d.ctl->t_b = t;
         d.ctl->n_big[par ^ 1] = 0;
         d.ctl->big_done = 0;
-        d.ctl->cs_done = 0;
         if (d.trace) d.nact_hist[t - d.trace_t0] = n;
     }
     __syncthreads();
@@ -1484,26 +1483,6 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     scatter_items<kLds>(d, soff, wsh4, &tot, slen);
 }
 
-// Commit and scatter in one launch: the grid (at most what the device holds
-// at once) commits the edge blocks, meets at a grid barrier, then writes the
-// next layout.  Used when the block offsets fit the LDS (dynamic, 4 B per
-// edge block).
-__global__ void __launch_bounds__(kNT) k_commit_scatter(Dev d) {
-    extern __shared__ int soff_dyn[];
-    __shared__ unsigned shc[cNumCounters];
-    __shared__ Scan4 wsh4[kWaves];
-    __shared__ int tot;
-    __shared__ float slen[16];
-    if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
-    __syncthreads();
-    const int t = d.ctl->t_b, par = t & 1;
-    CounterAcc acc;
-    acc.zero();
-    for (int blk = blockIdx.x; blk < d.n_blk; blk += gridDim.x) commit_block(d, blk, t, par, acc, wsh4);
-    flush_commit_counters(d, acc, shc);
-    grid_barrier(d, &d.ctl->cs_done);
-    scatter_items<true>(d, soff_dyn, wsh4, &tot, slen);
-}
 
 // ---- differentiable form: reverse sweep of one step ----------------------
 // With the step's discrete decisions frozen (trace records), the state at
