@@ -1063,11 +1063,14 @@ __device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t
 
 // Grid barrier of k_big_admit: every workgroup is resident (one per CU at
 // most, checked at launch), and the wait ends after kBarrierTimeout of the
-// 100 MHz clock at the latest, with an error flag instead of a hang.
-__device__ inline void grid_barrier(const Dev& d, unsigned* counter) {
+// 100 MHz clock at the latest, with an error flag instead of a hang.  Only a
+// workgroup that wrote something (release) makes its writes device-wide
+// first: on a GPU whose XCDs have separate L2 caches that fence writes the
+// L2 back, the costly part of the barrier.
+__device__ inline void grid_barrier(const Dev& d, unsigned* counter, bool release) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        __threadfence();                           // this workgroup's writes, device-wide
+        if (release) __threadfence();
         atomicAdd(counter, 1u);
         const unsigned long long t0 = __builtin_amdgcn_s_memrealtime();
         while (__hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < gridDim.x) {
@@ -1119,7 +1122,7 @@ __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
     const int nbig = d.ctl->n_big[par];
     if (nbig > 0) {
         big_tiles(d, t, par, nbig);
-        grid_barrier(d, &d.ctl->big_done);
+        grid_barrier(d, &d.ctl->big_done, (int)blockIdx.x < nbig);   // workgroups that had a big tile
     }
     admit_items<kBigNT>(d, t);
 }
