@@ -220,7 +220,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     if (!ev) {
         hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
         hipLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, d);
-        hipLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, d);
+        hipLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, d);
         if (lds_scan) {
             hipLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, d);
         } else {
@@ -232,10 +232,10 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
     hipExtLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     if (lds_scan) {
-        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[4], ev[5], 0, d);
+        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, ev[4], ev[5], 0, d);
         hipExtLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, ev[6], ev[7], 0, d);
     } else {   // the block scan is counted with commit
-        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), b, 0, s, ev[4], nullptr, 0, d);
+        hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, ev[4], nullptr, 0, d);
         hipExtLaunchKernelGGL(k_blkscan, dim3(1), dim3(kBigNT), 0, s, nullptr, ev[5], 0, d);
         hipExtLaunchKernelGGL(k_scatter<false>, dim3(h->g_scatter), b, 0, s, ev[6], ev[7], 0, d);
     }

@@ -37,7 +37,8 @@ constexpr int kTileCapLds = 384;         // tiles up to this size are staged in 
 constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
 constexpr int kCommitLanes = 8;         // threads per edge in k_commit (an edge has at most 8 lanes)
-constexpr int kEdgeBlock = kNT / kCommitLanes;   // edges per commit workgroup
+constexpr int kCommitNT = 256;           // threads per commit workgroup
+constexpr int kEdgeBlock = kCommitNT / kCommitLanes;   // edges per commit workgroup
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
 constexpr unsigned long long kBarrierTimeout = 20000000ull;   // 0.2 s of the 100 MHz clock
@@ -1324,9 +1325,9 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
     }
 
     // offsets of the edges in the workgroup (one value per edge, at its lane 0)
-    Scan4 run = wg_exclusive_scan4(Scan4{l == 0 ? c : 0, -1, -1, -1}, wsh4);
+    Scan4 run = wg_exclusive_scan4<kCommitNT>(Scan4{l == 0 ? c : 0, -1, -1, -1}, wsh4);
     if (l == 0 && e < d.n_edges) d.edge_rel[e] = run.s;
-    if (threadIdx.x == kNT - 1) d.blk_sum[blk] = run.s + (l == 0 ? c : 0);
+    if (threadIdx.x == kCommitNT - 1) d.blk_sum[blk] = run.s + (l == 0 ? c : 0);
 }
 
 __device__ inline void flush_commit_counters(const Dev& d, const CounterAcc& acc, unsigned* shc) {
@@ -1334,9 +1335,9 @@ __device__ inline void flush_commit_counters(const Dev& d, const CounterAcc& acc
     if (threadIdx.x == 0 && shc[cDeparted]) atomicAdd(&d.ctl->n_departed, (int)shc[cDeparted]);
 }
 
-__global__ void __launch_bounds__(kNT) k_commit(Dev d) {
+__global__ void __launch_bounds__(kCommitNT) k_commit(Dev d) {
     __shared__ unsigned shc[cNumCounters];
-    __shared__ Scan4 wsh4[kWaves];
+    __shared__ Scan4 wsh4[kCommitNT / 64];
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     __syncthreads();
     const int t = d.ctl->t_b, par = t & 1;
