@@ -422,6 +422,35 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
     return hi;
 }
 
+// Both ends of a tile in one pass over the slots [w0, w0 + NT): a0 = the
+// first edge start in [w0, w1) (w1 if none), a1 = the first edge start at or
+// after w1 (n if none).  Windows are at most NT / 2 slots, so the pass also
+// covers NT / 2 slots past w1; a longer edge continues with first_edge_start.
+template <int NT>
+__device__ inline void tile_bounds(const int32_t* edge, int w0, int w1, int n, int* wsh2, int& a0, int& a1) {
+    constexpr int kW = NT / 64;
+    const int s = w0 + (int)threadIdx.x;
+    const bool f = s < n && (s == 0 || edge[s] != edge[s - 1]);
+    const bool in0 = f && s < w1, in1 = f && s >= w1;
+    const unsigned long long b0 = __ballot(in0), b1 = __ballot(in1);
+    const int wave = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        wsh2[wave] = b0 ? (w0 + wave * 64 + (__ffsll((long long)b0) - 1)) : INT32_MAX;
+        wsh2[kW + wave] = b1 ? (w0 + wave * 64 + (__ffsll((long long)b1) - 1)) : INT32_MAX;
+    }
+    __syncthreads();
+    int m0 = INT32_MAX, m1 = INT32_MAX;
+    for (int w = 0; w < kW; ++w) {
+        m0 = min(m0, wsh2[w]);
+        m1 = min(m1, wsh2[kW + w]);
+    }
+    __syncthreads();
+    a0 = m0 == INT32_MAX ? w1 : m0;
+    if (m1 != INT32_MAX) a1 = m1;
+    else a1 = (w0 + NT >= n) ? n : first_edge_start<NT>(edge, w0 + NT, n, wsh2);
+}
+
 // ---- lane-change draws computed by the whole workgroup -------------------
 // A task is one Philox block (vehicle q of the tile, stream, block index).
 // Its 24-bit words are added into the vehicle's slot with an LDS atomic; the
@@ -941,7 +970,7 @@ __device__ inline int tile_window(const Dev& d, int n) {
 __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kWaves];
-    __shared__ int wsh[kWaves];
+    __shared__ int wsh[2 * kWaves];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
     __shared__ uint32_t dtask[kTileDrawTasks];
@@ -970,9 +999,9 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     const int32_t* edge = d.s[par].edge;
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
         const int w0 = k * W, w1 = min(n, w0 + W);
-        const int a0 = first_edge_start<kNT>(edge, w0, w1, wsh);
+        int a0, a1;
+        tile_bounds<kNT>(edge, w0, w1, n, wsh, a0, a1);
         if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
-        const int a1 = first_edge_start<kNT>(edge, w1, n, wsh);
         const int cnt = a1 - a0;
         if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
             if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileTooBig);
