@@ -511,6 +511,27 @@ __device__ inline bool gap_with_noise(float G, float c, int word_sum) {
     return G >= need;
 }
 
+// The lane-change decision of vehicle q once its noise is drawn (Eqs. (3)-(4)):
+// b.moved[q] becomes 0 or 1.
+__device__ inline void finish_pending(const TileBuf& b, int q, int dir, const float* Ga, const float* ca,
+                                      const float* Gb, const float* cb, const int* na, const int* nb,
+                                      CounterAcc& acc) {
+    const int code = b.moved[q];
+    if (!(code & kPending)) return;
+    bool ok = true;
+    if (code & kDrawA) ok = gap_with_noise(Ga[q], ca[q], na[q]);
+    if (code & kDrawB) ok = ok && gap_with_noise(Gb[q], cb[q], nb[q]);
+    int moved = 0;
+    if (ok) {
+        moved = 1;
+        acc.c[cLaneChanges]++;
+        const uint32_t m = b.meta[q];
+        const int lp = (int)(b.el[q] & 15u) + dir;
+        if (lane_allowed(m, b.nxt[q], lp)) b.meta[q] = m & ~((1u << 4) | (127u << 8));
+    }
+    b.moved[q] = moved;
+}
+
 // ---- Phases 1-2 for one tile ----------------------------------------------
 template <int NT>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
@@ -701,30 +722,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
     if (tid < 2) dq.n[tid] = 0;   // lists of the next tile (several barriers away)
 
-    for (int q = tid; q < n; q += NT) {
-        const int code = b.moved[q];
-        if (!(code & kPending)) continue;
-        bool ok = true;
-        if (code & kDrawA) ok = gap_with_noise(Ga[q], ca[q], na[q]);
-        if (code & kDrawB) ok = ok && gap_with_noise(Gb[q], cb[q], nb[q]);
-        int moved = 0;
-        if (ok) {
-            moved = 1;
-            acc.c[cLaneChanges]++;
-            uint32_t m = b.meta[q];
-            const int lp = (int)(b.el[q] & 15u) + dir;
-            if (lane_allowed(m, b.nxt[q], lp)) b.meta[q] = m & ~((1u << 4) | (127u << 8));
-        }
-        b.moved[q] = moved;
-    }
-    __syncthreads();
-
     // ---- mover prefix sums and last-mover / last-stayer / run-start maxima
     {
         const int chunk = (n + NT - 1) / NT;
         const int lo = min(n, tid * chunk), hi = min(n, lo + chunk);
         Scan4 loc{0, -1, -1, -1};
         for (int q = lo; q < hi; ++q) {
+            // the decisions waiting for noise are finished by the thread that scans them
+            finish_pending(b, q, dir, Ga, ca, Gb, cb, na, nb, acc);
             const int mv = b.moved[q];
             loc.s += mv;
             if (mv) loc.a = q; else loc.b = q;
