@@ -84,6 +84,16 @@ struct Ctl {
     int pad[2];
 };
 
+// t_a, t_b, n_act[0], n_act[1] in one 16-byte load (the step number and both
+// active counts), so no read of the control block waits for another
+struct StepHead {
+    int t_a, t_b, n0, n1;
+};
+__device__ inline StepHead step_head(const Ctl* c) {
+    const int4 v = *(const int4*)c;
+    return StepHead{v.x, v.y, v.z, v.w};
+}
+
 enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8, kErrBarrier = 16 };
 
 struct Slots {
@@ -984,8 +994,9 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
-    const int t = d.ctl->t_a, par = t & 1;
-    const int n = d.ctl->n_act[par];
+    const StepHead sh = step_head(d.ctl);
+    const int t = sh.t_a, par = t & 1;
+    const int n = par ? sh.n1 : sh.n0;
     CounterAcc acc;
     acc.zero();
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -1153,8 +1164,9 @@ __device__ inline void admit_items(const Dev& d, int t) {
 // write, so on a step with big tiles all workgroups meet at a grid barrier in
 // between; most steps have none and skip it.
 __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
+    const int2 nb2 = *(const int2*)d.ctl->n_big;   // independent of the step number load
     const int t = d.ctl->t_a, par = t & 1;
-    const int nbig = d.ctl->n_big[par];
+    const int nbig = par ? nb2.y : nb2.x;
     if (nbig > 0) {
         big_tiles(d, t, par, nbig);
         grid_barrier(d, &d.ctl->big_done, (int)blockIdx.x < nbig);   // workgroups that had a big tile
@@ -1434,8 +1446,9 @@ __global__ void __launch_bounds__(kBigNT) k_blkscan(Dev d) {
 template <bool kLds>
 __device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* totp, float* slen) {
     if (threadIdx.x < 16) slen[threadIdx.x] = d.cp[threadIdx.x].len;
-    const int t = d.ctl->t_b, par = t & 1;
-    const int nold = d.ctl->n_act[par];
+    const StepHead sh = step_head(d.ctl);
+    const int t = sh.t_b, par = t & 1;
+    const int nold = par ? sh.n1 : sh.n0;
     const int nl = d.n_lanes_total;
     const int* boff;
     int nnew;
