@@ -395,10 +395,19 @@ struct CounterAcc {
     }
 };
 
-// counters: per-thread registers -> LDS atomics -> one global atomic each
+// counters: per-thread registers -> wavefront sums -> LDS atomics -> one
+// global atomic each.  The wavefront sum is a fixed-cost DPP reduction; an
+// atomic on a per-thread value would be split by the compiler into a loop
+// over the lanes holding a non-zero count, which at the end of a busy tile
+// costs microseconds.  Counters that no lane of the wavefront touched are
+// skipped on a ballot (all of them, where the kernel never updates one).
 __device__ inline void flush_counters_lds(const Dev& d, const CounterAcc& acc, unsigned* shc) {
-    for (int k = 0; k < cNumCounters; ++k)
-        if (acc.c[k]) atomicAdd(&shc[k], acc.c[k]);
+#pragma unroll
+    for (int k = 0; k < cNumCounters; ++k) {
+        if (__ballot(acc.c[k] != 0u) == 0ull) continue;   // uniform across the wavefront
+        const unsigned s = __ockl_wfred_add_u32(acc.c[k]);
+        if ((threadIdx.x & 63) == 0) atomicAdd(&shc[k], s);
+    }
     __syncthreads();
     if (threadIdx.x < cNumCounters && shc[threadIdx.x])
         atomicAdd(&d.counters[threadIdx.x * kCounterCopies + (blockIdx.x % kCounterCopies)],
@@ -1259,18 +1268,21 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
             d.fin_x[ob.vid] = xs;
             d.fin_v[ob.vid] = vs;
             d.fin_meta[ob.vid] = m;
-            acc.c[cArrived]++;
         } else if (won) {
             exits = true;
-            if (!lane_allowed(m, ob.nxt, l)) acc.c[cWaivedExits]++;
-            acc.c[cTransfers]++;
         } else {                                   // held at the stop line
             S.x[ob.slot] = d.L[e];
             S.v[ob.slot] = 0.0f;
             S.meta[ob.slot] = m | (1u << 5);
             if (hs < 0) d.held_since[ob.vid] = t;
-            acc.c[cHolds]++;
         }
+        // counted outside the branches: an increment of a different counter
+        // in each branch would be merged into one store through a computed
+        // index, which moves the counters to scratch memory
+        acc.c[cArrived] += arrived ? 1u : 0u;
+        acc.c[cTransfers] += won ? 1u : 0u;
+        acc.c[cWaivedExits] += (won && !lane_allowed(m, ob.nxt, l)) ? 1u : 0u;
+        acc.c[cHolds] += exits ? 0u : 1u;
         if (exits) {
             d.exit_stamp[gl] = t;
             tau = ((double)t + (double)ob.phi) * (double)d.dt;
