@@ -82,6 +82,9 @@ def _load(path):
     lib.orc_uniform_d.restype = D
     lib.orc_normal_d.argtypes = [U64, I64, I64, I32]
     lib.orc_normal_d.restype = D
+    lib.orc_set_v0_spread.argtypes = [P, ctypes.c_float]
+    lib.orc_driver_limit_d.argtypes = [U64, I64, I64, ctypes.c_float, ctypes.c_float]
+    lib.orc_driver_limit_d.restype = D
     return lib
 
 
@@ -122,6 +125,8 @@ class OracleSim:
                                        _p(k[18]), float(p.dt), int(p.seed))
         if not self._h:
             raise MemoryError("oracle create failed")
+        if getattr(p, "v0_spread", 0.0):
+            self._lib.orc_set_v0_spread(self._h, float(p.v0_spread))
 
     def __del__(self):
         h = getattr(self, "_h", None)
@@ -237,6 +242,11 @@ def uniform(seed, t, vid, stream, fp64=False):
 
 def normal(seed, t, vid, stream, fp64=False):
     return lib(fp64).orc_normal_d(seed, t, vid, stream)
+
+
+def driver_limit(seed, edge, vid, lim, spread, fp64=False):
+    """Free-flow limit of one driver on one edge under a per-driver v0 spread."""
+    return lib(fp64).orc_driver_limit_d(seed, edge, vid, lim, spread)
 
 
 def mand_trigger(seed, t, vid, d, fp64=False):

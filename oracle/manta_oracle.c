@@ -129,6 +129,20 @@ REAL orc_normal(uint64_t seed, int64_t t, int64_t id, int s) {
     return (REAL)c * RL(5.9604644775390625e-08);
 }
 
+/* ------------------------------------------------------------------ per-driver v0 (Sec. IV)
+ * Each driver's free-flow speed on an edge is drawn around the edge's limit
+ * with standard deviation 2 sigma_s, sigma_s the spread of observed speeds at
+ * that limit; here sigma_s = spread * limit (A28).  The draw is the
+ * Irwin-Hall normal of stream 4 with the edge in place of the step, so it is
+ * fixed for one driver on one edge, and the factor is floored at 0.1 (A29):
+ *   limit_i,e = limit_e * max(1 + (2 spread) z, 0.1).                       */
+REAL orc_driver_limit(uint64_t seed, int64_t edge, int64_t id, REAL lim, REAL spread) {
+    if (spread == RL(0.0)) return lim;
+    REAL f = RL(1.0) + (RL(2.0) * spread) * orc_normal(seed, edge, id, 4);
+    if (f < RL(0.1)) f = RL(0.1);
+    return lim * f;
+}
+
 /* ------------------------------------------------------------------ exp for Eq. (2)
  * exp(y) for y in (-17, 0], FP32, every operation in this order:
  * Cody-Waite reduction y = k ln2 + r with a two-part ln 2, a degree-7 Taylor
@@ -236,6 +250,7 @@ typedef struct orc_sim {
     REAL *v0f, *T, *a, *b, *s0, *len, *den;
     REAL dt;
     uint64_t seed;
+    REAL spread;        /* per-driver v0 spread (0: every driver drives at v0f * limit) */
     /* dynamic state, indexed by vehicle id */
     int t;
     uint8_t *status;
@@ -477,7 +492,7 @@ static void step_once(orc_sim *S) {
         /* desire: route-motivated (towards the allowed lanes) or incentive */
         int desire = (!allowed_l) && (lane_dist(S, e, f, lp) < lane_dist(S, e, f, l));
         if (!desire && allowed_lp && !(S->mand[i] && !allowed_l)) {
-            REAL v0 = S->v0f[c] * S->lim[e];
+            REAL v0 = S->v0f[c] * orc_driver_limit(S->seed, e, i, S->lim[e], S->spread);
             REAL acc_cur, acc_new;
             if (lead_cur >= 0) {
                 REAL s = (S->x[lead_cur] - S->len[S->cls[lead_cur]]) - S->x[i];
@@ -563,7 +578,7 @@ static void step_once(orc_sim *S) {
         S->ev_leader[i] = j;
         S->ev_kind[i] = kind;
         S->ev_partner[i] = (kind == K_VEH) ? j : (kind == K_LOOK ? mrear[S->lane_base[f] + (S->nlane[i] < S->lanes[f] - 1 ? S->nlane[i] : S->lanes[f] - 1)] : -1);
-        REAL v0 = S->v0f[c] * S->lim[e];
+        REAL v0 = S->v0f[c] * orc_driver_limit(S->seed, e, i, S->lim[e], S->spread);
         int idm_fl = 0;
         REAL acc = orc_idm(S->v[i], v0, vl, s, S->T[c], S->a[c], S->b[c], S->s0[c], S->den[c], kind, &idm_fl);
         S->ev_bits[i] = idm_fl;
@@ -849,7 +864,7 @@ double orc_replay(orc_sim *S, const double *theta, const double *target, const u
             else if (R->kind == K_STOP) { sgap = L - x[i]; }
             else if (R->kind == K_LOOK) { sgap = (L - x[i]) + (x[j] - (double)S->len[S->cls[j]]); vl = v[j]; }
             const double *th = theta + 5 * c;
-            const double v0 = th[0] * (double)S->lim[e];
+            const double v0 = th[0] * (double)orc_driver_limit(S->seed, e, i, S->lim[e], S->spread);
             double pd[8];
             const double acc = idm64(v[i], v0, vl, sgap, th[1], th[2], th[3], th[4], R->kind, R->bits, pd);
             double xnew, vnew;
@@ -943,7 +958,7 @@ double orc_replay(orc_sim *S, const double *theta, const double *target, const u
                     if (R->kind == K_VEH) { nx[j] += macc * pd[2]; nx[i] -= macc * pd[2]; nv[j] += macc * pd[1]; }
                     else if (R->kind == K_STOP) { nx[i] -= macc * pd[2]; }
                     else if (R->kind == K_LOOK) { nx[i] -= macc * pd[2]; nx[j] += macc * pd[2]; nv[j] += macc * pd[1]; }
-                    grad[5 * c + 0] += macc * pd[3] * (double)S->lim[e];
+                    grad[5 * c + 0] += macc * pd[3] * (double)orc_driver_limit(S->seed, e, i, S->lim[e], S->spread);
                     grad[5 * c + 1] += macc * pd[4];
                     grad[5 * c + 2] += macc * pd[5];
                     grad[5 * c + 3] += macc * pd[6];
@@ -1058,3 +1073,7 @@ double orc_crit_gap_d(double g0, double af, double vi, double as, double vo) {
 double orc_desired_gap_d(double vi) { return (double)orc_desired_gap((REAL)vi); }
 double orc_uniform_d(uint64_t seed, int64_t t, int64_t id, int32_t s) { return (double)orc_uniform(seed, t, id, s); }
 double orc_normal_d(uint64_t seed, int64_t t, int64_t id, int32_t s) { return (double)orc_normal(seed, t, id, s); }
+void orc_set_v0_spread(orc_sim *S, float spread) { S->spread = (REAL)spread; }
+double orc_driver_limit_d(uint64_t seed, int64_t edge, int64_t id, float lim, float spread) {
+    return (double)orc_driver_limit(seed, edge, id, (REAL)lim, (REAL)spread);
+}

@@ -109,6 +109,7 @@ class Params:
     seed: int = 0
     intersection_mode: int = 0
     record_every: int = 0
+    v0_spread: float = 0.0     # per-driver v0: sigma_s = v0_spread * limit, drawn at 2 sigma_s
 
     @property
     def n_classes(self) -> int:
@@ -157,7 +158,7 @@ def jitter_params(p: Params, rel: float, seed: int, purpose: int = _P_CLASS) -> 
     return Params(v0_factor=g(p.v0_factor, "v0_factor"), T=g(p.T, "T"), a=g(p.a, "a"), b=g(p.b, "b"),
                   s0=g(p.s0, "s0"),
                   veh_len=p.veh_len.copy(), dt=p.dt, seed=p.seed,
-                  intersection_mode=p.intersection_mode, record_every=p.record_every)
+                  intersection_mode=p.intersection_mode, record_every=p.record_every, v0_spread=p.v0_spread)
 
 
 # --------------------------------------------------------------------------- networks
