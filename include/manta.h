@@ -78,6 +78,11 @@ typedef struct {
     uint64_t seed;                        /* Philox key for the lane-change draws */
     int32_t intersection_mode;            /* 0 = all green (case 2); 1 = flashing red -> SIM_EUNSUPPORTED */
     int32_t record_every;                 /* >= 0; > 0: keep a checkpoint every record_every steps for sim_backward */
+    float v0_spread;                      /* [0, 0.25]; per-driver free-flow speed (Sec. IV, model validation):
+                                           * driver i on edge e drives at v0_factor * limit_e * f_i,e with
+                                           * f = max(1 + 2 v0_spread z, 0.1), z ~ N(0, 1) (Irwin-Hall of twelve
+                                           * Philox uniforms, stream 4, counter (edge, vehicle, 4, block)) fixed
+                                           * per driver and edge; 0 = every driver at the limit */
 } sim_idm_params;
 
 /* Per-vehicle state, all arrays [n_vehicles] indexed by vehicle id; any

@@ -48,7 +48,7 @@ class SimRoutes(ctypes.Structure):
 class SimIdmParams(ctypes.Structure):
     _fields_ = [("n_classes", I32), ("v0_factor", P), ("T", P), ("a", P), ("b", P), ("s0", P),
                 ("length_m", P), ("dt", F32), ("seed", U64), ("intersection_mode", I32),
-                ("record_every", I32)]
+                ("record_every", I32), ("v0_spread", F32)]
 
 
 class SimScenario(ctypes.Structure):
@@ -216,7 +216,8 @@ class Sim:
         self._routes = SimRoutes(n_master, _p(k["ro"]), _p(k["re"]), _p(k["dp"]), _p(k["vc"]), _p(k["al"]))
         self._params = SimIdmParams(int(p.T.shape[0]), _p(k["v0"]), _p(k["T"]), _p(k["a"]), _p(k["b"]),
                                     _p(k["s0"]), _p(k["vl"]), float(p.dt), int(p.seed),
-                                    int(getattr(p, "intersection_mode", 0)), int(getattr(p, "record_every", 0)))
+                                    int(getattr(p, "intersection_mode", 0)), int(getattr(p, "record_every", 0)),
+                                    float(getattr(p, "v0_spread", 0.0)))
         if allocator == "torch":
             use_torch_allocator()
         elif allocator == "hip":

@@ -80,6 +80,18 @@ __device__ inline float draw_normal(uint64_t seed, int t, uint32_t vid, int stre
     return (float)c * 5.9604644775390625e-08f;
 }
 
+// A driver's free-flow limit on an edge (Sec. IV, model validation): the
+// edge's limit times max(1 + 2 spread z, 0.1), z the Irwin-Hall normal of
+// stream 4 with the edge (modulo period: one scenario's edges in an
+// ensemble) in place of the step, so it is fixed for one driver on one edge.
+// spread = 0 returns the limit itself.
+__device__ inline float driver_limit(float lim, float spread, uint64_t seed, int edge, int period, uint32_t rid) {
+    if (spread == 0.0f) return lim;
+    float f = 1.0f + (2.0f * spread) * draw_normal(seed, edge % period, rid, 4);
+    f = f < 0.1f ? 0.1f : f;
+    return lim * f;
+}
+
 // exp(y) for y in (-17, 0] (Eq. (2)): Cody-Waite split y = k ln2 + r with
 // ln2 = 0x3F317200 + 1.4286068e-6, degree-7 Taylor polynomial of e^r by
 // Horner, then multiplication by 2^k built from its exponent bits (exact).

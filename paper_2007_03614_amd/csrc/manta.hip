@@ -172,6 +172,7 @@ void validate(const sim_network* net, const sim_routes* r, const sim_idm_params*
     if (p->intersection_mode != 0)
         throw Fail{SIM_EUNSUPPORTED, "intersection_mode 1 (flashing red) is not implemented"};
     if (p->record_every < 0) bad("record_every must be >= 0");
+    if (!finite_in(p->v0_spread, 0.0f, 0.25f)) bad("v0_spread outside [0, 0.25]");
     // a vehicle entering an edge must land behind everything on it: the
     // overshoot of one step stays below the shortest edge minus a length
     float vmax = 0, amax = 0, lmax = 0, lmin = 1e30f, limmax = 0;
@@ -184,7 +185,9 @@ void validate(const sim_network* net, const sim_routes* r, const sim_idm_params*
         lmin = std::min(lmin, net->length_m[e]);
         limmax = std::max(limmax, net->speed_limit_mps[e]);
     }
-    const double reach = ((double)vmax * limmax + (double)amax * p->dt) * p->dt + lmax;
+    // a driver's limit is at most 1 + 12 v0_spread times the edge's (|z| <= 6)
+    const double reach = ((double)vmax * limmax * (1.0 + 12.0 * (double)p->v0_spread) + (double)amax * p->dt) * p->dt +
+                         lmax;
     if (lmin < reach) bad(fmt("shortest edge %.2f m is below one step's reach %.2f m", lmin, reach));
 
     if (r->n_vehicles < 0) bad("n_vehicles < 0");
@@ -342,18 +345,21 @@ sim_status sim_set_allocator(void* (*alloc)(size_t, void*), void (*release)(void
 
 namespace {
 sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_idm_params* p, const uint32_t* rng_id,
-                       sim_handle** out);
+                       int32_t edge_period, sim_handle** out);
 }
 
 sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm_params* p, sim_handle** out) {
-    return create_impl(net, r, p, nullptr, out);
+    return create_impl(net, r, p, nullptr, net ? net->n_edges : 1, out);
 }
 
 }  // extern "C"
 
 namespace {
+// rng_id: per-vehicle draw id (null: the vehicle id); edge_period: the
+// draws keyed by an edge use the edge id modulo this (the edges of one
+// scenario in an ensemble's union network, else the edge count)
 sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_idm_params* p, const uint32_t* rng_id,
-                       sim_handle** out) {
+                       int32_t edge_period, sim_handle** out) {
     if (!out) return SIM_EINVAL;
     *out = nullptr;
     sim_handle* h = nullptr;
@@ -382,6 +388,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             h->conn_mask.assign(net->conn_lane_mask, net->conn_lane_mask + NC);
             h->L.assign(net->length_m, net->length_m + E);
             d.n_edges = E;
+            d.edge_period = std::max(1, edge_period);
             d.n_lanes_total = NL;
             d.L = h->upload(net->length_m, E);
             d.lim = h->upload(net->speed_limit_mps, E);
@@ -410,6 +417,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.cp = h->upload(cp.data(), 16);
             d.dt = p->dt;
             d.seed = p->seed;
+            d.v0_spread = p->v0_spread;
             // ---- vehicles
             d.n_veh = N;
             h->roff.assign(r->route_off, r->route_off + N + 1);
@@ -1068,7 +1076,7 @@ sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, cons
         ur = sim_routes{(int32_t)ntot, ro.data(), re.data(), dp.data(), vc.data(), al.data()};
     });
     if (st != SIM_OK) return st;
-    st = create_impl(&un, &ur, p, rid.data(), out);
+    st = create_impl(&un, &ur, p, rid.data(), net ? net->n_edges : 1, out);
     if (st == SIM_OK) {
         (*out)->n_scen = ns;
         (*out)->veh_off = vo;

@@ -190,6 +190,8 @@ struct Dev {
     const ClassParams* cp;
     float dt;
     uint64_t seed;
+    float v0_spread;    // per-driver free-flow speed spread (0: off)
+    int edge_period;    // draws keyed by an edge use edge % edge_period (one scenario's edges)
     // layout
     Slots s[2];
     // per vehicle (id-indexed)
@@ -588,7 +590,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.nxt[q] = f;
         const float L = d.L[e];
         b.L[q] = L;
-        b.lim[q] = d.lim[e];
+        const float lim = d.lim[e];
         b.lbe[q] = d.lane_base[e];
         b.lanes2[q] = (uint32_t)d.lanes[e] | ((f >= 0 ? (uint32_t)d.lanes[f] : 0u) << 8);
         b.lbf[q] = f >= 0 ? d.lane_base[f] : 0;
@@ -596,6 +598,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.alpha[q] = d.alpha[id];
         const uint32_t rid = d.rid[id];
         b.rid[q] = rid;
+        b.lim[q] = driver_limit(lim, d.v0_spread, d.seed, e, d.edge_period, rid);   // this driver's limit on e
         u1[q] = 0;
         na[q] = 0;
         nb[q] = 0;
@@ -1629,7 +1632,7 @@ __global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, co
         if (bits & (TB_HELD | TB_W)) continue;
         const int c = d.cls[i];
         const ClassParams cp = d.cp[c];
-        const double lim = (double)d.lim[e];
+        const double lim = (double)driver_limit(d.lim[e], d.v0_spread, d.seed, e, d.edge_period, d.rid[i]);
         const double v0 = (double)cp.v0f * lim;
         double pd[8];
         const double acc = idm_partials(v, v0, (double)R.vl, (double)R.s, cp, kind, bits, pd);
