@@ -83,6 +83,8 @@ def _load(path):
     lib.orc_normal_d.argtypes = [U64, I64, I64, I32]
     lib.orc_normal_d.restype = D
     lib.orc_set_v0_spread.argtypes = [P, ctypes.c_float]
+    lib.orc_set_intersection_mode.argtypes = [P, I32]
+    lib.orc_set_intersection_mode.restype = I32
     lib.orc_driver_limit_d.argtypes = [U64, I64, I64, ctypes.c_float, ctypes.c_float]
     lib.orc_driver_limit_d.restype = D
     return lib
@@ -127,6 +129,9 @@ class OracleSim:
             raise MemoryError("oracle create failed")
         if getattr(p, "v0_spread", 0.0):
             self._lib.orc_set_v0_spread(self._h, float(p.v0_spread))
+        if getattr(p, "intersection_mode", 0):
+            if self._lib.orc_set_intersection_mode(self._h, int(p.intersection_mode)) != 0:
+                raise ValueError("case 1 intersections need at most 64 (in, out) pairs per node")
 
     def __del__(self):
         h = getattr(self, "_h", None)

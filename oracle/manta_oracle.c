@@ -277,6 +277,15 @@ typedef struct orc_sim {
     int64_t *rec_off;          /* [steps + 1]: records of step t */
     int *ins_step;             /* step at whose end a vehicle was admitted, -1 */
     int rec_t0;                /* first recorded step */
+    /* case 1 intersections (flashing red; 0 = case 2, all green) */
+    int imode;
+    int stop_steps;            /* steps of the stop at the line: 2 s, rounded up */
+    int *pair_base;            /* [edge]: its index among the in-edges of its head node x out-degree */
+    int *out_idx;              /* [edge]: its index among the out-edges of its tail node */
+    int *nm;                   /* [node]: in-degree x out-degree, the round-robin length */
+    int *rr;                   /* [node]: pair served last, -1 before the first */
+    uint64_t *bestnode;        /* [node]: smallest eligible transfer key of the step */
+    int *tin;                  /* [lane]: a transfer enters it this step */
 } orc_sim;
 
 /* one active vehicle in one step, with every discrete decision frozen */
@@ -340,7 +349,8 @@ static void free_sim(orc_sim *S) {
                     S->T, S->a, S->b, S->s0, S->len, S->den, S->status, S->edge, S->k, S->lane,
                     S->mand, S->held, S->ww, S->x, S->v, S->tau_in, S->t_arr, S->tt_sum, S->tt_cnt,
                     S->nlane, S->xn, S->vn, S->tgt, S->elig, S->key, S->best, S->ev_leader,
-                    S->ev_kind, S->ev_flags, S->ev_partner, S->ev_bits, S->rec, S->rec_off, S->ins_step};
+                    S->ev_kind, S->ev_flags, S->ev_partner, S->ev_bits, S->rec, S->rec_off, S->ins_step,
+                    S->pair_base, S->out_idx, S->nm, S->rr, S->bestnode, S->tin};
     for (size_t q = 0; q < sizeof(ptrs) / sizeof(ptrs[0]); q++) free(ptrs[q]);
     if (S->lst) {
         for (int g = 0; g < S->n_lanes_total; g++) free(S->lst[g].a);
@@ -619,6 +629,8 @@ static void step_once(orc_sim *S) {
      * rear'(g, lam) = the active vehicle with the smallest (x_new, id) in the
      * post-change lane; it still counts if it is leaving itself. */
     for (int g = 0; g < S->n_lanes_total; g++) S->best[g] = UINT64_MAX;
+    if (S->imode == 1)
+        for (int v = 0; v < S->n_nodes; v++) S->bestnode[v] = UINT64_MAX;
     int *rearp = (int *)malloc((size_t)(S->n_lanes_total > 0 ? S->n_lanes_total : 1) * sizeof(int));
     for (int g = 0; g < S->n_lanes_total; g++) {
         int r = -1;
@@ -644,8 +656,21 @@ static void step_once(orc_sim *S) {
                     int ok = (r < 0) || ((S->xn[r] - S->len[S->cls[r]]) - xp >= RL(0));
                     uint64_t hs = (uint64_t)(S->held[i] >= 0 ? S->held[i] : t);
                     S->tgt[i] = g;
-                    S->elig[i] = ok;
                     S->key[i] = (hs << 32) | (uint64_t)(uint32_t)i;
+                    if (S->imode == 1) {
+                        /* case 1: a vehicle crosses only after a 2 s stop at the line
+                         * (held for ceil(2 s / dt) steps, A30); one crossing per node and step, the
+                         * (in, out) pairs served round-robin after the last served one
+                         * (A31): key = (distance in the cycle, held since, source lane) */
+                        const int node = S->efrom[f];
+                        const int pr = S->pair_base[e] + S->out_idx[f];
+                        int dd = (pr - S->rr[node] - 1) % S->nm[node];
+                        if (dd < 0) dd += S->nm[node];
+                        ok = ok && S->held[i] >= 0 && t - S->held[i] >= S->stop_steps;
+                        S->key[i] = ((uint64_t)dd << 58) | (hs << 26) | (uint64_t)(S->lane_base[e] + S->nlane[i]);
+                        if (ok && S->key[i] < S->bestnode[node]) S->bestnode[node] = S->key[i];
+                    }
+                    S->elig[i] = ok;
                     S->ev_flags[i] |= EV_REQ | (ok ? EV_ELIG : 0);
                 }
             }
@@ -659,16 +684,31 @@ static void step_once(orc_sim *S) {
             S->key[i] = (1ULL << 63) | ((uint64_t)(uint32_t)S->dep[i] << 32) | (uint64_t)(uint32_t)i;
             S->ev_flags[i] |= EV_INSERT_REQ | (ok ? EV_ELIG : 0);
         }
-        if (S->tgt[i] >= 0 && S->elig[i] && S->key[i] < S->best[S->tgt[i]]) S->best[S->tgt[i]] = S->key[i];
+        /* transfers of case 1 are arbitrated per node above, not per lane */
+        const int per_node = S->imode == 1 && S->status[i] == ACTIVE;
+        if (!per_node && S->tgt[i] >= 0 && S->elig[i] && S->key[i] < S->best[S->tgt[i]]) S->best[S->tgt[i]] = S->key[i];
     }
     free(rearp);
+    if (S->imode == 1) {
+        /* the node winners: their lanes take no departure this step */
+        for (int g = 0; g < S->n_lanes_total; g++) S->tin[g] = 0;
+        for (int i = 0; i < n; i++)
+            if (S->status[i] == ACTIVE && S->tgt[i] >= 0 && S->elig[i] &&
+                S->bestnode[S->efrom[next_edge(S, i)]] == S->key[i])
+                S->tin[S->tgt[i]] = 1;
+    }
 
     /* ---- Phase 4: commit, in ascending vehicle id (this is also the order of
      * the per-edge travel-time sums, A22). */
     for (int i = 0; i < n; i++) {
         if (S->status[i] == ACTIVE) {
             const int e = S->edge[i];
-            const int won = S->tgt[i] >= 0 && S->elig[i] && S->best[S->tgt[i]] == S->key[i];
+            int won = S->tgt[i] >= 0 && S->elig[i] && S->best[S->tgt[i]] == S->key[i];
+            if (S->imode == 1 && S->tgt[i] >= 0) {
+                const int f = next_edge(S, i), node = S->efrom[f];
+                won = S->elig[i] && S->bestnode[node] == S->key[i];
+                if (won) S->rr[node] = S->pair_base[e] + S->out_idx[f];
+            }
             if ((S->ev_flags[i] & EV_ARRIVE) || won) {
                 /* crossing time interpolated inside the step */
                 REAL phi = (S->xn[i] == S->x[i]) ? RL(0) : (S->L[e] - S->x[i]) / (S->xn[i] - S->x[i]);
@@ -710,7 +750,7 @@ static void step_once(orc_sim *S) {
                 S->lane[i] = S->nlane[i];
             }
         } else if (S->status[i] == WAITING && S->tgt[i] >= 0) {
-            if (S->elig[i] && S->best[S->tgt[i]] == S->key[i]) {
+            if (S->elig[i] && S->best[S->tgt[i]] == S->key[i] && !(S->imode == 1 && S->tin[S->tgt[i]])) {
                 int e0 = S->redges[S->roff[i]];
                 S->status[i] = ACTIVE;
                 S->edge[i] = e0;
@@ -1016,6 +1056,8 @@ void orc_write_state(orc_sim *S, int32_t t, const uint8_t *status, const int32_t
         S->ww[i] = ww[i];
         S->tau_in[i] = tau_in[i];
     }
+    if (S->rr)
+        for (int v = 0; v < S->n_nodes; v++) S->rr[v] = -1;   /* the round-robin restarts */
 }
 
 void orc_counters(const orc_sim *S, int64_t *out) {
@@ -1076,4 +1118,40 @@ double orc_normal_d(uint64_t seed, int64_t t, int64_t id, int32_t s) { return (d
 void orc_set_v0_spread(orc_sim *S, float spread) { S->spread = (REAL)spread; }
 double orc_driver_limit_d(uint64_t seed, int64_t edge, int64_t id, float lim, float spread) {
     return (double)orc_driver_limit(seed, edge, id, (REAL)lim, (REAL)spread);
+}
+
+/* Case 1 intersections (flashing red).  The (in, out) pairs of a node are
+ * numbered in-edge major, both in edge-id order.  Returns -1 if a node has
+ * more than 64 pairs or memory runs out. */
+int32_t orc_set_intersection_mode(orc_sim *S, int32_t mode) {
+    S->imode = mode;
+    if (mode != 1) return 0;
+    S->stop_steps = (int)ceil(2.0 / (double)S->dt - 1e-6);
+    const int E = S->n_edges, V = S->n_nodes;
+    int *indeg = calloc((size_t)V + 1, sizeof(int)), *outdeg = calloc((size_t)V + 1, sizeof(int));
+    S->pair_base = calloc((size_t)E + 1, sizeof(int));
+    S->out_idx = calloc((size_t)E + 1, sizeof(int));
+    S->nm = calloc((size_t)V + 1, sizeof(int));
+    S->rr = calloc((size_t)V + 1, sizeof(int));
+    S->bestnode = calloc((size_t)V + 1, sizeof(uint64_t));
+    S->tin = calloc((size_t)S->n_lanes_total + 1, sizeof(int));
+    if (!indeg || !outdeg || !S->pair_base || !S->out_idx || !S->nm || !S->rr || !S->bestnode || !S->tin) {
+        free(indeg); free(outdeg);
+        return -1;
+    }
+    int *in_idx = calloc((size_t)E + 1, sizeof(int));
+    if (!in_idx) { free(indeg); free(outdeg); return -1; }
+    for (int e = 0; e < E; e++) {                 /* edge-id order within each node */
+        in_idx[e] = indeg[S->eto[e]]++;
+        S->out_idx[e] = outdeg[S->efrom[e]]++;
+    }
+    int rc = 0;
+    for (int v = 0; v < V; v++) {
+        S->nm[v] = indeg[v] * outdeg[v];
+        if (S->nm[v] > 64) rc = -1;
+        S->rr[v] = -1;
+    }
+    for (int e = 0; e < E; e++) S->pair_base[e] = in_idx[e] * outdeg[S->eto[e]];
+    free(in_idx); free(indeg); free(outdeg);
+    return rc;
 }
