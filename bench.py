@@ -241,6 +241,8 @@ def main():
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
     ap.add_argument("--cpu-steps", type=int, default=7200, help="oracle sample length (0: skip)")
+    ap.add_argument("--intersection-mode", type=int, default=0, choices=[0, 1],
+                    help="0: all green (case 2); 1: flashing red at every node (case 1)")
     ap.add_argument("--v0-spread", type=float, default=0.0,
                     help="per-driver free-flow speed spread (sigma_s / limit; drivers drawn at 2 sigma_s)")
     ap.add_argument("--kernels-only", action="store_true",
@@ -280,6 +282,7 @@ def main():
         return
     w = make_workload(args.workload)
     w.params.v0_spread = args.v0_spread
+    w.params.intersection_mode = args.intersection_mode
     if args.copy_probe > 0:
         # a plain streaming kernel of known size: reads MIB MiB, writes MIB MiB
         # (torch's elementwise add; a device-to-device copy_ would use the DMA engine)
@@ -344,7 +347,8 @@ def main():
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if (tr.get("workload") == args.workload and tr.get("sources") == kernel_source_digest()
-                and tr.get("v0_spread", 0.0) == args.v0_spread):
+                and tr.get("v0_spread", 0.0) == args.v0_spread
+                and tr.get("intersection_mode", 0) == args.intersection_mode):
             traffic = tr.get("bytes_per_step")
     line = {
         "metric": "vehicle-updates/sec (1 GPU)",
@@ -361,7 +365,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "vehicles": w.n_vehicles, "edges": w.net.n_edges,
                    "lanes": int(w.net.lanes.sum()), "dt_s": 0.5, "steps": args.steps,
-                   "vehicle_updates": int(upd), **({"v0_spread": args.v0_spread} if args.v0_spread else {})},
+                   "vehicle_updates": int(upd), **({"v0_spread": args.v0_spread} if args.v0_spread else {}),
+                   **({"intersection_mode": 1} if args.intersection_mode else {})},
         "roofline": {"bound": "hbm", "kernel": "k_tile_step", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "us_per_launch": 1e3 * tile_ms / args.steps, "big_tile_updates": big_upd},

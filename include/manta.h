@@ -76,7 +76,15 @@ typedef struct {
     const float *v0_factor, *T, *a, *b, *s0, *length_m;   /* [n_classes] */
     float dt;                             /* (0, 1]; the paper uses 0.5 s */
     uint64_t seed;                        /* Philox key for the lane-change draws */
-    int32_t intersection_mode;            /* 0 = all green (case 2); 1 = flashing red -> SIM_EUNSUPPORTED */
+    int32_t intersection_mode;            /* Sec. II-E traffic control.  0 = case 2, all green: a front crosses
+                                           * when the target lane has room.  1 = case 1, flashing red: a front
+                                           * crosses only after standing ceil(2 s / dt) steps at the stop line,
+                                           * and each node passes one vehicle per step, its (in, out) pairs
+                                           * served round-robin (in-edge major, edge-id order; within a pair,
+                                           * earliest at the line, then lowest source lane).  Case 1 needs at
+                                           * most 64 pairs per node and fewer than 2^26 lanes, else
+                                           * SIM_EUNSUPPORTED; other values SIM_EINVAL.  sim_write_state
+                                           * restarts the round-robin. */
     int32_t record_every;                 /* >= 0; > 0: keep a checkpoint every record_every steps for sim_backward */
     float v0_spread;                      /* [0, 0.25]; per-driver free-flow speed (Sec. IV, model validation):
                                            * driver i on edge e drives at v0_factor * limit_e * f_i,e with

@@ -169,8 +169,25 @@ void validate(const sim_network* net, const sim_routes* r, const sim_idm_params*
             bad(fmt("class %d: length outside (0, 20]", c));
     }
     if (!(std::isfinite(p->dt) && p->dt > 0.0f && p->dt <= 1.0f)) bad("dt outside (0, 1]");
-    if (p->intersection_mode != 0)
-        throw Fail{SIM_EUNSUPPORTED, "intersection_mode 1 (flashing red) is not implemented"};
+    if (p->intersection_mode != 0 && p->intersection_mode != 1) bad("intersection_mode must be 0 or 1");
+    if (p->intersection_mode == 1) {
+        // case 1 keys hold the source lane in 26 bits and the round-robin distance in 6
+        if ((int64_t)net->n_nodes <= 0) bad("case 1 needs the node count");
+        std::vector<int> indeg((size_t)net->n_nodes, 0), outdeg((size_t)net->n_nodes, 0);
+        int64_t nl = 0;
+        for (int e = 0; e < E; ++e) {
+            if (net->edge_from[e] < 0 || net->edge_from[e] >= net->n_nodes || net->edge_to[e] < 0 ||
+                net->edge_to[e] >= net->n_nodes)
+                bad(fmt("edge %d: node out of range", e));
+            ++indeg[net->edge_to[e]];
+            ++outdeg[net->edge_from[e]];
+            nl += net->n_lanes[e];
+        }
+        for (int v = 0; v < net->n_nodes; ++v)
+            if (indeg[v] * outdeg[v] > 64)
+                throw Fail{SIM_EUNSUPPORTED, fmt("case 1: node %d has more than 64 (in, out) pairs", v)};
+        if (nl >= (1ll << 26)) throw Fail{SIM_EUNSUPPORTED, "case 1: more than 2^26 lanes"};
+    }
     if (p->record_every < 0) bad("record_every must be >= 0");
     if (!finite_in(p->v0_spread, 0.0f, 0.25f)) bad("v0_spread outside [0, 0.25]");
     // a vehicle entering an edge must land behind everything on it: the
@@ -272,6 +289,7 @@ void for_each_state_piece(sim_handle* h, F&& f) {
     f((void*)d.tt_cnt, 8 * E);
     f((void*)d.ctl, sizeof(Ctl));
     f((void*)d.counters, sizeof(unsigned long long) * cNumCounters * kCounterCopies);
+    if (d.imode == 1) f((void*)d.rr, 4 * (size_t)d.n_nodes);   // case 1 round-robin pointers
 }
 
 size_t state_bytes(sim_handle* h) {
@@ -389,6 +407,28 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             h->L.assign(net->length_m, net->length_m + E);
             d.n_edges = E;
             d.edge_period = std::max(1, edge_period);
+            d.imode = p->intersection_mode;
+            d.n_nodes = net->n_nodes;
+            if (d.imode == 1) {
+                // pairs numbered in-edge major, both in edge-id order within a node
+                const int V = net->n_nodes;
+                std::vector<int> indeg(V, 0), outdeg(V, 0), in_idx(E), out_idx(E), pb(E), nmv(V), rr0(V, -1);
+                for (int e = 0; e < E; ++e) {
+                    in_idx[e] = indeg[net->edge_to[e]]++;
+                    out_idx[e] = outdeg[net->edge_from[e]]++;
+                }
+                for (int e = 0; e < E; ++e) pb[e] = in_idx[e] * outdeg[net->edge_to[e]];
+                for (int v = 0; v < V; ++v) nmv[v] = std::max(1, indeg[v] * outdeg[v]);
+                d.stop_steps = (int)std::ceil(2.0 / (double)p->dt - 1e-6);
+                d.efrom = h->upload(net->edge_from, E);
+                d.pair_base = h->upload(pb.data(), E);
+                d.out_idx = h->upload(out_idx.data(), E);
+                d.nm = h->upload(nmv.data(), V);
+                d.rr = h->dev<int>(V);
+                HIP_OK(hipMemcpy(d.rr, rr0.data(), sizeof(int) * V, hipMemcpyHostToDevice));
+                d.win_node = h->dev<unsigned long long>(V);
+                HIP_OK(hipMemset(d.win_node, 0xFF, sizeof(unsigned long long) * V));
+            }
             d.n_lanes_total = NL;
             d.L = h->upload(net->length_m, E);
             d.lim = h->upload(net->speed_limit_mps, E);
@@ -879,6 +919,10 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * h->n_lanes));
         HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
+        if (d.imode == 1) {                        // the round-robin restarts
+            HIP_OK(hipMemset(d.rr, 0xFF, sizeof(int) * (size_t)d.n_nodes));
+            HIP_OK(hipMemset(d.win_node, 0xFF, sizeof(unsigned long long) * (size_t)d.n_nodes));
+        }
         Ctl c{};
         c.t_a = t;
         c.t_b = t;

@@ -141,9 +141,9 @@ struct Outbox {       // end-of-edge request of a lane's front vehicle
     int target;       // global lane on the next edge, -1 for an arrival
     float xp;         // position on the next edge
     float phi;        // fraction of the step at which the stop line was crossed
-    uint64_t key;     // admission priority (smaller first)
-    int elig;         // set by admission: the request passed the no-overlap test
-    uint32_t tl_cls;  // lane on the next edge | class << 8
+    uint64_t key;     // admission priority (smaller first); case 1: the node key set by admission
+    int elig;         // set by admission: 0 = refused; else 1 (case 2) or 1 + the node (case 1)
+    uint32_t tl_cls;  // lane on the next edge | class << 8 | (case 1) (in, out) pair << 16
     float v;          // speed after the step
     int nxt;          // next edge (-1 for an arrival)
 };
@@ -192,6 +192,16 @@ struct Dev {
     uint64_t seed;
     float v0_spread;    // per-driver free-flow speed spread (0: off)
     int edge_period;    // draws keyed by an edge use edge % edge_period (one scenario's edges)
+    // case 1 intersections (flashing red); imode 0 = case 2 (all green)
+    int imode;
+    int stop_steps;             // steps a vehicle stands at the line before it may cross (2 s)
+    int n_nodes;
+    const int* efrom;           // [edge] tail node
+    const int* pair_base;       // [edge] index among its head node's in-edges x that node's out-degree
+    const int* out_idx;         // [edge] index among its tail node's out-edges
+    const int* nm;              // [node] in-degree x out-degree (<= 64)
+    int* rr;                    // [node] pair served last, -1 before the first (state)
+    unsigned long long* win_node;   // [node] smallest eligible crossing key of the step
     // layout
     Slots s[2];
     // per vehicle (id-indexed)
@@ -1155,7 +1165,27 @@ __device__ inline void admit_items(const Dev& d, int t) {
         if (i < nl) {
             const Outbox ob = d.outbox[i];
             if (ob.stamp != t || ob.target < 0) continue;   // no request, or an arrival
-            const bool ok = transfer_eligible(d, ob, t);
+            bool ok = transfer_eligible(d, ob, t);
+            if (d.imode == 1) {
+                // case 1: only after standing stop_steps at the line (the key's
+                // step is the held-since step, t if not held); one crossing per
+                // node, its (in, out) pairs served round-robin after the last
+                // served one: key = (distance in the cycle, held since, source lane)
+                const int e = d.s[t & 1].edge[ob.slot], f = ob.nxt;
+                const int node = d.efrom[f], nmv = d.nm[node];
+                const int pr = d.pair_base[e] + d.out_idx[f];
+                int dd = (pr - d.rr[node] - 1) % nmv;
+                if (dd < 0) dd += nmv;
+                const int hs = (int)(ob.key >> 32);
+                ok = ok && t - hs >= d.stop_steps;
+                const unsigned long long nk = ((unsigned long long)dd << 58) |
+                                              ((unsigned long long)(uint32_t)hs << 26) | (unsigned long long)i;
+                d.outbox[i].key = nk;
+                d.outbox[i].elig = ok ? 1 + node : 0;
+                d.outbox[i].tl_cls = ob.tl_cls | ((uint32_t)pr << 16);
+                if (ok) atomicMin(&d.win_node[node], nk);
+                continue;
+            }
             d.outbox[i].elig = ok ? 1 : 0;
             if (ok) claim(d, ob.target, ob.key, t);
         } else {
@@ -1237,12 +1267,17 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
     int pcnt = 0;
     bool claimed = false;
     unsigned long long w = ~0ull;
+    bool transfer_in = false;                      // case 1: this node's crossing enters this lane
     if (lane_ok) {
         ob = d.outbox[gl];
         const LanePost p = d.post[gl];
         pcnt = p.stamp == t ? p.cnt : 0;
         claimed = d.enter_stamp[gl] == t;
         w = d.win[gl];
+        if (d.imode == 1) {
+            const unsigned long long wn = d.win_node[d.efrom[e]];
+            if (wn != ~0ull) transfer_in = d.outbox[(int)(wn & ((1ull << 26) - 1))].target == gl;
+        }
     }
     const bool req = lane_ok && ob.stamp == t;
 
@@ -1261,7 +1296,12 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
             kk = d.cursor[ob.vid] + 1;
             r0 = d.roff[ob.vid];
         }
-        won = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
+        if (d.imode == 1) {
+            won = ob.target >= 0 && ob.elig && d.win_node[ob.elig - 1] == ob.key;
+            if (won) d.rr[ob.elig - 1] = (int)((ob.tl_cls >> 16) & 255u);   // the pair just served
+        } else {
+            won = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
+        }
         if (d.trace)
             d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + ob.slot].kb |=
                 (ob.target < 0 ? TB_ARRIVE : (won ? TB_EXIT : TB_HELD)) << 8;
@@ -1327,9 +1367,13 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
         else d.tau_in[ob.vid] = tau;
     }
 
-    // the departure whose key won this lane (the winning key of a claimed lane)
-    const bool ins = lane_ok && claimed && (w >> 63);
+    // the departure whose key won this lane (the winning key of a claimed lane);
+    // in case 1 only departures claim lanes, and a crossing into the lane
+    // comes first
+    const bool ins = lane_ok && claimed && (w >> 63) && !transfer_in;
     const int ins_vid = ins ? (int)(uint32_t)w : 0;
+    if (transfer_in && !claimed) d.enter_stamp[gl] = t;   // the scatter takes the crossing's record
+    claimed = claimed || transfer_in;
 
     // next layout: this lane's count, its offset in the edge, the edge's count
     const int nc = pcnt - (exits ? 1 : 0) + (claimed ? 1 : 0);
@@ -1355,7 +1399,7 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
         r.vid = ob.vid;
         r.edge = ob.nxt;
         r.gl = ob.target;
-        r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)(ob.tl_cls >> 8), d.rmask[r0 + kk]);
+        r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)((ob.tl_cls >> 8) & 255u), d.rmask[r0 + kk]);
         r.nxt = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
         r.pad = 0;
         d.cursor[ob.vid] = kk;
@@ -1547,6 +1591,8 @@ __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
     __shared__ int tot;
     __shared__ float slen[16];                    // vehicle length per class
     scatter_items<kLds>(d, soff, wsh4, &tot, slen);
+    if (d.imode == 1)                             // case 1: nodes free for the next step's crossings
+        for (int v = blockIdx.x * kNT + threadIdx.x; v < d.n_nodes; v += gridDim.x * kNT) d.win_node[v] = ~0ull;
 }
 
 

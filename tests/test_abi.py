@@ -104,11 +104,41 @@ def test_bad_params(M, base, field, val):
 
 def test_unsupported_modes(M, base):
     w = copy.deepcopy(base)
-    w.params.intersection_mode = 1
-    _expect(M, w, "SIM_EUNSUPPORTED")
+    w.params.intersection_mode = 2
+    _expect(M, w, "SIM_EINVAL")
     w = copy.deepcopy(base)
     w.params.record_every = -1
     _expect(M, w, "SIM_EINVAL")
+    for spread in (-0.01, 0.3, float("nan")):
+        w = copy.deepcopy(base)
+        w.params.v0_spread = spread
+        _expect(M, w, "SIM_EINVAL")
+
+
+def test_flashing_red_needs_at_most_64_pairs_per_node(M):
+    """Case 1 numbers a node's (in, out) pairs in 6 bits of its key: a star of
+    nine two-way spokes (81 pairs at the hub) is refused by the library and by
+    the oracle; eight spokes (64 pairs) pass the oracle."""
+    import oracle
+    for spokes in (9, 8):
+        ang = np.arange(spokes) * 2 * np.pi / spokes
+        nx = np.concatenate([[0.0], 300.0 * np.cos(ang)])
+        ny = np.concatenate([[0.0], 300.0 * np.sin(ang)])
+        net = W._finish_edges(nx, ny, np.zeros(spokes, np.int64), np.arange(1, spokes + 1),
+                              np.full(spokes, 300.0, np.float32), np.full(spokes, 13.9, np.float32),
+                              np.ones(spokes, np.int64))
+        e_in = int(np.nonzero((net.edge_from == 1) & (net.edge_to == 0))[0][0])
+        e_out = int(np.nonzero((net.edge_from == 0) & (net.edge_to == 2))[0][0])
+        p = W.base_params(1)
+        p.intersection_mode = 1
+        w = W.Workload("star", net, np.array([0, 2], np.int64), np.array([e_in, e_out], np.int32),
+                       np.zeros(1, np.int32), np.zeros(1, np.uint8), np.full(1, 0.2, np.float32), p, 10)
+        if spokes == 9:
+            _expect(M, w, "SIM_EUNSUPPORTED")
+            with pytest.raises(ValueError):
+                oracle.OracleSim(w)
+        else:
+            oracle.OracleSim(w)
 
 
 def test_step_reach_bound(M, base):
