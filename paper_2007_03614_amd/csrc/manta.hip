@@ -238,7 +238,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     const dim3 b(kNT);
     const bool lds_scan = h->n_blk <= kScanLdsMax;
     if (!ev) {
-        hipLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, d);
+        hipLaunchKernelGGL(d.v0_spread != 0.0f ? k_tile_step_v0spread : k_tile_step, dim3(h->g_tile), b, 0, s, d);
         hipLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, d);
         hipLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, d);
         if (lds_scan) {
@@ -249,7 +249,8 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
         }
         return;
     }
-    hipExtLaunchKernelGGL(k_tile_step, dim3(h->g_tile), b, 0, s, ev[0], ev[1], 0, d);
+    hipExtLaunchKernelGGL(d.v0_spread != 0.0f ? k_tile_step_v0spread : k_tile_step, dim3(h->g_tile), b, 0, s, ev[0],
+                          ev[1], 0, d);
     hipExtLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     if (lds_scan) {
         hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, ev[4], ev[5], 0, d);

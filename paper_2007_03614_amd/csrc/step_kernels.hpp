@@ -564,7 +564,9 @@ __device__ inline void finish_pending(const TileBuf& b, int q, int dir, const fl
 }
 
 // ---- Phases 1-2 for one tile ----------------------------------------------
-template <int NT>
+// kSpread: the per-driver limits may be on (a kernel of its own, so that the
+// common case carries none of their code)
+template <int NT, bool kSpread>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
                                     CounterAcc& acc, Scan4* wsh4, const ClassParams* scp, const DrawQ& dq) {
     const Slots S = d.s[par];
@@ -608,7 +610,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.alpha[q] = d.alpha[id];
         const uint32_t rid = d.rid[id];
         b.rid[q] = rid;
-        b.lim[q] = driver_limit(lim, d.v0_spread, d.seed, e, d.edge_period, rid);   // this driver's limit on e
+        b.lim[q] = lim;
         u1[q] = 0;
         na[q] = 0;
         nb[q] = 0;
@@ -622,6 +624,9 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     }
     __syncthreads();
     draw_run<NT>(dq, 0, d.seed, t, b.rid, u1, na, nb);
+    if (kSpread && d.v0_spread != 0.0f)   // each driver's own limit on its edge (Sec. IV)
+        for (int q = tid; q < n; q += NT)
+            b.lim[q] = driver_limit(b.lim[q], d.v0_spread, d.seed, (int)(b.el[q] >> 4), d.edge_period, b.rid[q]);
 
     // ---- runs of S_t (tile order: edge, lane, then x and id descending)
     {
@@ -1004,7 +1009,8 @@ __device__ inline int tile_window(const Dev& d, int n) {
 
 // Small tiles (<= kTileCapLds vehicles) in 256-thread workgroups; larger
 // tiles go to a list for k_big_admit.
-__global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
+template <bool kSpread>
+__device__ inline void tile_step(const Dev& d) {
     __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kWaves];
     __shared__ int wsh[2 * kWaves];
@@ -1046,7 +1052,7 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
             continue;
         }
         if (cnt <= kTileCapLds) {
-            process_tile<kNT>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
+            process_tile<kNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
         } else if (threadIdx.x == 0) {
             const int q = atomicAdd(&d.ctl->n_big[par], 1);
             d.big_list[2 * q] = a0;
@@ -1055,6 +1061,10 @@ __global__ void __launch_bounds__(kNT) k_tile_step(Dev d) {
     }
     flush_counters_lds(d, acc, shc);
 }
+
+__global__ void __launch_bounds__(kNT) k_tile_step(Dev d) { tile_step<false>(d); }
+// the same with per-driver free-flow limits (v0_spread > 0)
+__global__ void __launch_bounds__(kNT) k_tile_step_v0spread(Dev d) { tile_step<true>(d); }
 
 // Tiles above kTileCapLds: 1,024-thread workgroups with kBigCapLds vehicles
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
@@ -1104,10 +1114,10 @@ __device__ inline void big_tiles(const Dev& d, int t, int par, int nbig) {
             const int cnt = end - pos;
             if (threadIdx.x == 0) atomicAdd(&d.ctl->big_updates, (unsigned long long)cnt);
             if (cnt <= kBigCapLds) {
-                process_tile<kBigNT>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp, dq);
+                process_tile<kBigNT, true>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp, dq);
             } else {
                 char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
-                process_tile<kBigNT>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp, dq);
+                process_tile<kBigNT, true>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp, dq);
             }
             pos = end;
         }
