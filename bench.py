@@ -230,13 +230,82 @@ def bench_calibration(args, M, torch, stream):
     }
 
 
+def bench_calibration_search(args, M, torch, stream):
+    """The paper's calibration loop (Sec. IV-A) on the 10x10 grid with
+    flashing-red intersections (case 1, where stops and queues make speeds
+    depend on the parameters), one class, 1 h (7,200 steps): observed edge
+    speeds from a run at hidden (a, b, T, s0) = config-1 values * (1 + U[-0.3,
+    0.3]) (clipped to the bounds); the search starts from (2, 2.5, 1, 3).
+    5 iterations of 5 parameter sets, each iteration one ensemble handle,
+    against the same loop with 5 handles run one after another (identical
+    decisions, checked), and against 5 iterations of adjoint gradient descent
+    on the same L1 loss."""
+    import workloads as W
+    from paper_2007_03614_amd import calibrate as C
+    steps = args.steps if args.steps_given else 7200
+    w = W.config1(n_steps=steps)
+    w.params.intersection_mode = 1
+    rng = np.random.default_rng(11)
+    ref_p = np.array([w.params.a[0], w.params.b[0], w.params.T[0], w.params.s0[0]], np.float64)
+    lo, hi = C._bounds_arrays()
+    hidden = np.clip(ref_p * (1.0 + rng.uniform(-0.3, 0.3, 4)), lo, hi)
+    base = np.array([2.0, 2.5, 1.0, 3.0])
+    ref = M.Sim(M.with_class_params(w, C.class_params(w, hidden).astype(np.float64)), stream=stream)
+    ref.step(steps)
+    mean, cnt = ref.mean_travel_times()
+    ref.close()
+    observed = C.edge_speeds(mean, cnt, w.net.length)
+    deltas = rng.uniform(-1.0, 1.0, (5, 4, 4))
+
+    def sequential(sets):
+        out = []
+        for th in sets:
+            sim = M.Sim(M.with_class_params(w, C.class_params(w, th).astype(np.float64)), stream=stream)
+            sim.step(steps)
+            mm, cc = sim.mean_travel_times()
+            sim.close()
+            out.append(C.l1_speed_loss(C.edge_speeds(mm, cc, w.net.length), observed))
+        return out
+
+    C.random_search(w, observed, steps, deltas[:1], theta0=base, tol=0.0, stream=stream)      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    th_e, h_e = C.random_search(w, observed, steps, deltas, theta0=base, tol=0.0, stream=stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    th_s, h_s = C.random_search(w, observed, steps, deltas, theta0=base, tol=0.0, evaluate=sequential)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    assert all(a["losses"] == b["losses"] for a, b in zip(h_e, h_s)), "ensemble and sequential runs differ"
+    th_g, h_g = C.gradient_descent(w, observed, steps, iterations=5, lr=0.05, decay=0.7, theta0=base,
+                                   stream=stream)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    it = len(h_e)
+    return {
+        "metric": "calibration search: seconds per iteration (5 parameter sets in one ensemble)",
+        "value": (t1 - t0) / it, "unit": "s", "n_gpus": 1, "steps": steps, "warmup": 1,
+        "ms_per_step": 1e3 * (t1 - t0) / (it * steps), "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "calibration_search_grid10x10_case1", "vehicles": w.n_vehicles, "sets": 5,
+                   "iterations": it, "hidden_abTs0": hidden.tolist(), "start_abTs0": base.tolist(),
+                   "random_search": {"abTs0": th_e.tolist(),
+                                     "mean_diff_mph": [h["mean_diff_mps"] / C.MPH for h in h_e],
+                                     "s": t1 - t0},
+                   "sequential_handles_s": t2 - t1, "ensemble_speedup": (t2 - t1) / (t1 - t0),
+                   "gradient_descent": {"abTs0": th_g.tolist(),
+                                        "mean_diff_mph": [h["mean_diff_mps"] / C.MPH for h in h_g],
+                                        "s": t3 - t2}},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=21600)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="perturbed_grid_ring",
-                    choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration"])
+                    choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration", "calibration_search"])
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
@@ -279,6 +348,9 @@ def main():
         return
     if args.workload == "calibration":
         print(json.dumps(bench_calibration(args, M, torch, stream)), flush=True)
+        return
+    if args.workload == "calibration_search":
+        print(json.dumps(bench_calibration_search(args, M, torch, stream)), flush=True)
         return
     w = make_workload(args.workload)
     w.params.v0_spread = args.v0_spread

@@ -151,6 +151,12 @@ typedef struct {
     int32_t n_vehicles;                   /* the first n_vehicles of the master demand, 0..master */
     int32_t n_reduced;                    /* >= 0 */
     const int32_t *reduced_edges;         /* [n_reduced] edge ids forced to 1 lane (all moves from lane 0) */
+    const float *class_params;            /* optional [5 * n_classes]: this scenario's (v0_factor, T, a, b, s0)
+                                           * per class (Sec. IV-A runs several parameter sets per calibration
+                                           * iteration); NULL: the shared parameters.  If any scenario gives
+                                           * them, class c of scenario k is class k * n_classes + c of the
+                                           * handle (state, sim_backward), n_scen * n_classes <= 16 (else
+                                           * SIM_EUNSUPPORTED), each value within the bounds of sim_create */
 } sim_scenario;
 
 /* One handle running n_scen >= 1 scenarios in the same kernels: the device

@@ -52,7 +52,7 @@ class SimIdmParams(ctypes.Structure):
 
 
 class SimScenario(ctypes.Structure):
-    _fields_ = [("n_vehicles", I32), ("n_reduced", I32), ("reduced_edges", P)]
+    _fields_ = [("n_vehicles", I32), ("n_reduced", I32), ("reduced_edges", P), ("class_params", P)]
 
 
 class SimState(ctypes.Structure):
@@ -195,9 +195,12 @@ class Sim:
     ``alpha``, ``params``)."""
 
     def __init__(self, w, stream=None, allocator: str = "torch", scenarios=None):
-        """scenarios: optional list of (n_vehicles, reduced_edges) — an
-        ensemble over the workload's network, with the workload's demand as
-        the master list (sim_create_ensemble)."""
+        """scenarios: optional list of (n_vehicles, reduced_edges) or
+        (n_vehicles, reduced_edges, class_params) — an ensemble over the
+        workload's network, with the workload's demand as the master list
+        (sim_create_ensemble).  class_params: None or [n_classes, 5]
+        (v0_factor, T, a, b, s0) for that scenario; if any scenario has them,
+        scenario k's class c is class k * n_classes + c of the handle."""
         net, p = w.net, w.params
         self.n_edges_base = int(net.edge_from.shape[0])
         keep = dict(
@@ -230,12 +233,17 @@ class Sim:
             _check(_lib.sim_create(ctypes.byref(self._net), ctypes.byref(self._routes),
                                    ctypes.byref(self._params), ctypes.byref(h)))
         else:
-            red = [_c(r, np.int32) for _, r in scenarios]
-            sc = (SimScenario * len(scenarios))(*[SimScenario(int(n), int(r.size), _p(r))
-                                                  for (n, _), r in zip(scenarios, red)])
-            keep["red"], keep["sc"] = red, sc
+            red = [_c(sc_[1], np.int32) for sc_ in scenarios]
+            cps = [None if len(sc_) < 3 or sc_[2] is None else _c(np.asarray(sc_[2]).reshape(-1), np.float32)
+                   for sc_ in scenarios]
+            sc = (SimScenario * len(scenarios))(*[SimScenario(int(sc_[0]), int(r.size), _p(r),
+                                                              None if cp is None else _p(cp))
+                                                  for sc_, r, cp in zip(scenarios, red, cps)])
+            keep["red"], keep["sc"], keep["cps"] = red, sc, cps
             self.n_scen = len(scenarios)
-            self.n = int(sum(int(n) for n, _ in scenarios))
+            self.n = int(sum(int(sc_[0]) for sc_ in scenarios))
+            if any(cp is not None for cp in cps):
+                self.n_classes = self.n_scen * int(p.T.shape[0])
             self.n_edges = self.n_edges_base * self.n_scen
             _check(_lib.sim_create_ensemble(ctypes.byref(self._net), ctypes.byref(self._routes),
                                             ctypes.cast(sc, P), self.n_scen, ctypes.byref(self._params),
@@ -255,7 +263,7 @@ class Sim:
         """dL/d(class parameters) as [n_classes, 5] (v0_factor, T, a, b, s0)
         for dL/d(per-edge mean traversal time) = dL_dmean (sim_backward)."""
         g = _c(dL_dmean, np.float64)
-        out = np.zeros(5 * int(self._params.n_classes), np.float64)
+        out = np.zeros(5 * int(getattr(self, "n_classes", self._params.n_classes)), np.float64)
         _check(_lib.sim_backward(self._h, _p(g), _p(out)), self._h)
         return out.reshape(-1, 5)
 

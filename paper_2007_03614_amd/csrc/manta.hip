@@ -1057,6 +1057,9 @@ sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, cons
     std::vector<uint8_t> la, cm, vc;
     std::vector<int64_t> ro;
     std::vector<uint32_t> rid;
+    std::vector<float> cv0, cT, ca, cb, cs0, clen;   // classes of all scenarios (per-scenario parameters)
+    sim_idm_params up{};
+    bool per_scen = false;
     sim_network un{};
     sim_routes ur{};
     sim_status st = guarded(nullptr, [&] {
@@ -1079,6 +1082,34 @@ sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, cons
             ntot += sc[k].n_vehicles;
         }
         if (ntot >= (1ll << 31)) bad("ensemble has too many vehicles");
+        for (int k = 0; k < ns; ++k) per_scen = per_scen || sc[k].class_params != nullptr;
+        const int nc = p->n_classes;
+        if (per_scen) {
+            // scenario k's class c becomes class k * nc + c; create_impl checks the bounds
+            if (nc < 1 || !p->v0_factor || !p->T || !p->a || !p->b || !p->s0 || !p->length_m)
+                bad("parameter array missing");
+            if ((int64_t)ns * nc > 16) throw Fail{SIM_EUNSUPPORTED, "n_scen * n_classes above 16"};
+            for (int k = 0; k < ns; ++k)
+                for (int c = 0; c < nc; ++c) {
+                    const float* q = sc[k].class_params ? sc[k].class_params + 5 * c : nullptr;
+                    cv0.push_back(q ? q[0] : p->v0_factor[c]);
+                    cT.push_back(q ? q[1] : p->T[c]);
+                    ca.push_back(q ? q[2] : p->a[c]);
+                    cb.push_back(q ? q[3] : p->b[c]);
+                    cs0.push_back(q ? q[4] : p->s0[c]);
+                    clen.push_back(p->length_m[c]);
+                }
+            up = *p;
+            up.n_classes = ns * nc;
+            up.v0_factor = cv0.data();
+            up.T = cT.data();
+            up.a = ca.data();
+            up.b = cb.data();
+            up.s0 = cs0.data();
+            up.length_m = clen.data();
+            for (int i = 0; i < m->n_vehicles; ++i)
+                if (!m->vclass || m->vclass[i] >= nc) bad(fmt("vehicle %d: class out of range", i));
+        }
         const size_t EU = (size_t)(E * ns);
         ef.resize(EU); et.resize(EU); ln.resize(EU); li.resize(EU); la.resize(EU);
         co.resize(EU + 1); ct.resize((size_t)NC * ns); cm.resize((size_t)NC * ns);
@@ -1110,7 +1141,7 @@ sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, cons
                     re.push_back((int32_t)(m->route_edges[q] + k * E));
                 ro.push_back((int64_t)re.size());
                 dp.push_back(m->depart_step[i]);
-                vc.push_back(m->vclass[i]);
+                vc.push_back(per_scen ? (uint8_t)(k * nc + m->vclass[i]) : m->vclass[i]);
                 al.push_back(m->alpha_s[i]);
                 rid.push_back((uint32_t)i);
             }
@@ -1121,7 +1152,7 @@ sim_status sim_create_ensemble(const sim_network* net, const sim_routes* m, cons
         ur = sim_routes{(int32_t)ntot, ro.data(), re.data(), dp.data(), vc.data(), al.data()};
     });
     if (st != SIM_OK) return st;
-    st = create_impl(&un, &ur, p, rid.data(), net ? net->n_edges : 1, out);
+    st = create_impl(&un, &ur, per_scen ? &up : p, rid.data(), net ? net->n_edges : 1, out);
     if (st == SIM_OK) {
         (*out)->n_scen = ns;
         (*out)->veh_off = vo;
