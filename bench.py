@@ -299,13 +299,79 @@ def bench_calibration_search(args, M, torch, stream):
     }
 
 
+def bench_metro_scale(args, M, torch, stream):
+    """Config 2 at metropolitan size: 16 copies of the perturbed grid + ring
+    and its 200,000-vehicle demand in one ensemble handle -- 3.2M vehicles on
+    572,800 edges, the sizes of the metropolitan config -- over the same 3 h.
+    Measures the step where tiles no longer fit in one round of resident
+    workgroups: vehicle-updates/s from the graph path, and the tile kernel
+    against the HBM roofline (48 B per vehicle-update) from the event pass."""
+    import workloads as W
+    copies = 16
+    w = W.config2()
+    steps = args.steps if args.steps_given else w.n_steps
+    n = int(w.depart_step.shape[0])
+    scen = [(n, np.zeros(0, np.int32))] * copies
+    warm = M.Sim(w, scenarios=scen, stream=stream)
+    warm.step(args.warmup)
+    warm.close()
+    sim = M.Sim(w, scenarios=scen, stream=stream)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    done = 0
+    chunk = 2400
+    while done < steps:                           # progress lines for long runs
+        k = min(chunk, steps - done)
+        sim.step(k)
+        done += k
+        if args.progress:
+            torch.cuda.synchronize()
+            print(f"graph pass: {done}/{steps}", file=sys.stderr, flush=True)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    upd = sim.counters()["active_sum"]
+    sim.close()
+    ev = M.Sim(w, scenarios=scen, stream=stream)
+    kernel_ms, tot = {}, 0.0
+    done = 0
+    while done < steps:
+        k = min(chunk, steps - done)
+        kms, t = ev.step_timed(k)
+        for key, v in kms.items():
+            kernel_ms[key] = kernel_ms.get(key, 0.0) + v
+        tot += t
+        done += k
+        if args.progress:
+            print(f"event pass: {done}/{steps}", file=sys.stderr, flush=True)
+    big = ev.big_tile_updates()
+    assert ev.counters()["active_sum"] == upd
+    ev.close()
+    tile_ms = kernel_ms["k_tile_step"]
+    achieved = BYTES_PER_UPDATE * (upd - big) / (tile_ms / 1e3) / 1e9
+    return {
+        "metric": "vehicle-updates/sec (1 GPU)", "value": upd / (ms / 1e3), "unit": "vehicle-updates/s",
+        "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": ms / steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "perturbed_grid_ring_x16", "copies": copies, "vehicles": n * copies,
+                   "edges": w.net.n_edges * copies, "steps": steps, "vehicle_updates": int(upd)},
+        "roofline": {"bound": "hbm", "kernel": "k_tile_step", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "us_per_launch": 1e3 * tile_ms / steps, "big_tile_updates": big},
+        "kernel_us_per_step": {k: round(1e3 * v / steps, 3) for k, v in kernel_ms.items()},
+        "event_path_ms_per_step": tot / steps,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=21600)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="perturbed_grid_ring",
-                    choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration", "calibration_search"])
+                    choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration", "calibration_search",
+                             "metro_scale"])
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
@@ -348,6 +414,9 @@ def main():
         return
     if args.workload == "calibration":
         print(json.dumps(bench_calibration(args, M, torch, stream)), flush=True)
+        return
+    if args.workload == "metro_scale":
+        print(json.dumps(bench_metro_scale(args, M, torch, stream)), flush=True)
         return
     if args.workload == "calibration_search":
         print(json.dumps(bench_calibration_search(args, M, torch, stream)), flush=True)

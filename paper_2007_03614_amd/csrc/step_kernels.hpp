@@ -1485,6 +1485,42 @@ __device__ inline int scan_block_sums(const int* blk_sum, int nb, int* off, Scan
     return *tot;
 }
 
+// The same for many blocks (one workgroup, global output): the counts go
+// through `stage` (LDS, cap entries per round), read coalesced with every
+// load of a thread in flight together, scanned there by contiguous chunks
+// and written back coalesced.  With tens of blocks per thread, reading each
+// thread's contiguous chunk straight from memory would wait for one load
+// after another.
+template <int NT>
+__device__ inline int scan_block_sums_staged(const int* blk_sum, int nb, int* off, int* stage, int cap,
+                                             Scan4* wsh4, int* tot) {
+    int carry = 0;
+    for (int r0 = 0; r0 < nb; r0 += cap) {
+        const int m = min(cap, nb - r0);
+        // coalesced loads, every one of a thread in flight before the first use
+#pragma unroll 8
+        for (int i = (int)threadIdx.x; i < m; i += NT) stage[i] = blk_sum[r0 + i];
+        __syncthreads();
+        const int chunk = (m + NT - 1) / NT;
+        const int lo = min(m, (int)threadIdx.x * chunk), hi = min(m, lo + chunk);
+        int loc = 0;
+        for (int i = lo; i < hi; ++i) loc += stage[i];
+        const Scan4 r = wg_exclusive_scan4<NT>(Scan4{loc, -1, -1, -1}, wsh4);
+        int o = carry + r.s;
+        for (int i = lo; i < hi; ++i) {
+            const int v = stage[i];
+            stage[i] = o;
+            o += v;
+        }
+        if (hi == m && lo < hi) *tot = o;
+        __syncthreads();
+        for (int i = (int)threadIdx.x; i < m; i += NT) off[r0 + i] = stage[i];
+        carry = *tot;
+        __syncthreads();                            // stage and *tot are reused by the next round
+    }
+    return carry;
+}
+
 // n_act of the next step, refused departures of this one (every due vehicle
 // still waiting asked for a lane and was refused), and the step counter
 __device__ inline void finish_step(const Dev& d, int t, int par, int total) {
@@ -1501,8 +1537,9 @@ __device__ inline void finish_step(const Dev& d, int t, int par, int total) {
 __global__ void __launch_bounds__(kBigNT) k_blkscan(Dev d) {
     __shared__ Scan4 wsh4[kBigNT / 64];
     __shared__ int tot;
+    __shared__ int stage[kScanLdsMax];
     const int t = d.ctl->t_b, par = t & 1;
-    const int total = scan_block_sums<kBigNT>(d.blk_sum, d.n_blk, d.blk_off, wsh4, &tot);
+    const int total = scan_block_sums_staged<kBigNT>(d.blk_sum, d.n_blk, d.blk_off, stage, kScanLdsMax, wsh4, &tot);
     if (threadIdx.x == 0) finish_step(d, t, par, total);
 }
 
