@@ -72,6 +72,8 @@ struct sim_handle {
     hipStream_t stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipGraph_t graph_k = nullptr;     // kGraphSteps steps in one graph (fewer graph launches)
+    hipGraphExec_t exec_k = nullptr;
     std::string err;
     Dev d{};
     int t = 0;
@@ -109,8 +111,12 @@ struct sim_handle {
     void release_all() {
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (exec_k) (void)hipGraphExecDestroy(exec_k);
+        if (graph_k) (void)hipGraphDestroy(graph_k);
         exec = nullptr;
         graph = nullptr;
+        exec_k = nullptr;
+        graph_k = nullptr;
         for (void* p : bufs) al.put(p);
         bufs.clear();
         for (void* p : snaps) al.put(p);
@@ -316,21 +322,34 @@ void load_state(sim_handle* h, const void* src, int t) {
     h->t = t;
 }
 
+// Graphs of one step and of kGraphSteps steps.  Every kernel reads the step
+// number from the control block, so the launches of consecutive steps are the
+// same and one captured sequence serves any step.
+constexpr int kGraphSteps = 8;
+
 void capture_graph(sim_handle* h) {
     if (h->exec) (void)hipGraphExecDestroy(h->exec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->exec_k) (void)hipGraphExecDestroy(h->exec_k);
+    if (h->graph_k) (void)hipGraphDestroy(h->graph_k);
     h->exec = nullptr;
     h->graph = nullptr;
-    hipStream_t cs;
-    HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
-    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) {
-        launch_step(h, cs);
-        e = hipStreamEndCapture(cs, &h->graph);
+    h->exec_k = nullptr;
+    h->graph_k = nullptr;
+    for (int which = 0; which < 2; ++which) {
+        hipStream_t cs;
+        HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            for (int q = 0; q < (which ? kGraphSteps : 1); ++q) launch_step(h, cs);
+            e = hipStreamEndCapture(cs, &g);
+        }
+        (void)hipStreamDestroy(cs);
+        HIP_OK(e);
+        (which ? h->graph_k : h->graph) = g;
+        HIP_OK(hipGraphInstantiate(which ? &h->exec_k : &h->exec, g, nullptr, nullptr, 0));
     }
-    (void)hipStreamDestroy(cs);
-    HIP_OK(e);
-    HIP_OK(hipGraphInstantiate(&h->exec, h->graph, nullptr, nullptr, 0));
 }
 
 template <class F>
@@ -652,17 +671,21 @@ sim_status sim_step(sim_handle* h, int32_t n) {
         return SIM_EINVAL;
     }
     return guarded(h, [&] {
-        for (int q = 0; q < n; ++q) {
-            if (h->rec_every > 0 && !h->rec_broken && h->t % h->rec_every == 0 &&
-                (size_t)(h->t / h->rec_every) == h->snaps.size()) {
+        const bool rec = h->rec_every > 0 && !h->rec_broken;
+        for (int q = 0; q < n;) {
+            if (rec && h->t % h->rec_every == 0 && (size_t)(h->t / h->rec_every) == h->snaps.size()) {
                 if (!h->snap_bytes) h->snap_bytes = state_bytes(h);
                 void* p = h->al.get(h->snap_bytes);
                 if (!p) throw Fail{SIM_ENOMEM, "no device memory for a checkpoint"};
                 h->snaps.push_back(p);
                 save_state(h, p);
             }
-            HIP_OK(hipGraphLaunch(h->exec, h->stream));
-            h->t += 1;
+            // kGraphSteps at once unless a checkpoint falls strictly inside them
+            const bool batch = n - q >= kGraphSteps &&
+                               (!rec || (h->t / h->rec_every + 1) * h->rec_every >= h->t + kGraphSteps);
+            HIP_OK(hipGraphLaunch(batch ? h->exec_k : h->exec, h->stream));
+            h->t += batch ? kGraphSteps : 1;
+            q += batch ? kGraphSteps : 1;
         }
         HIP_OK(hipGetLastError());
     });
