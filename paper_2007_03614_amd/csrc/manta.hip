@@ -1024,7 +1024,7 @@ sim_status sim_backward(sim_handle* h, const double* dL_dmean_tt, double* dL_dpa
             q = (double*)get(8 * (size_t)N);
             HIP_OK(hipMemsetAsync(q, 0, 8 * (size_t)N, h->stream));
         }
-        double *lx = lam[0], *lv = lam[1], *nx = lam[2], *nv = lam[3], *lt = lam[4];
+        double* lt = lam[4];   // lam[0..3]: the two (x, v) adjoint pairs, swapped every step
         double* gpart = (double*)get(8 * (size_t)gbw * np);
         HIP_OK(hipMemsetAsync(gpart, 0, 8 * (size_t)gbw * np, h->stream));
         TraceRec* trace = (TraceRec*)get(sizeof(TraceRec) * (size_t)R * N);
@@ -1033,26 +1033,88 @@ sim_status sim_backward(sim_handle* h, const double* dL_dmean_tt, double* dL_dpa
         save_state(h, end_state);
         const int nseg = (T + R - 1) / R;
         if ((int)h->snaps.size() < nseg) throw Fail{SIM_ESTATE, "missing checkpoints"};
-        for (int sg = nseg - 1; sg >= 0; --sg) {
-            const int t0 = sg * R, t1 = std::min(T, t0 + R);
-            load_state(h, h->snaps[sg], t0);
-            h->d.trace = trace;
-            h->d.trace_t0 = t0;
-            h->d.trace_stride = N;
-            h->d.nact_hist = nact;
-            for (int t = t0; t < t1; ++t) launch_step(h, h->stream);
-            h->d = saved;
-            for (int t = t1 - 1; t >= t0; --t) {
-                HIP_OK(hipMemsetAsync(nx, 0, 8 * (size_t)N, h->stream));
-                HIP_OK(hipMemsetAsync(nv, 0, 8 * (size_t)N, h->stream));
-                hipLaunchKernelGGL(k_backward, dim3(gbw), dim3(kNT), 0, h->stream, h->d,
-                                   trace + (size_t)(t - t0) * N, nact + (t - t0), t, NC, lx, lv, nx, nv, lt, dw,
-                                   gpart);
-                std::swap(lx, nx);
-                std::swap(lv, nv);
+        Dev traced = saved;
+        traced.trace = trace;
+        traced.trace_period = R;
+        traced.trace_stride = N;
+        traced.nact_hist = nact;
+        // one reverse step: (lx, lv) -> (nx, nv) for step index i of a segment
+        auto reverse_step = [&](hipStream_t s, int i, double* ix, double* iv, double* ox, double* ov) {
+            hipLaunchKernelGGL(k_zero2, dim3(gbw), dim3(kNT), 0, s, ox, ov, N);
+            hipLaunchKernelGGL(k_backward, dim3(gbw), dim3(kNT), 0, s, saved, trace + (size_t)i * N, nact + i, i, NC,
+                               ix, iv, ox, ov, lt, dw, gpart);
+        };
+        // Full segments replay captured graphs: the traced re-run (kGraphSteps
+        // steps at a time) and the whole reverse sweep of R steps, for either
+        // assignment of the two adjoint buffer pairs (they swap every step).
+        // The last segment may be shorter and runs launch by launch.
+        hipGraph_t gg[4] = {nullptr, nullptr, nullptr, nullptr};
+        hipGraphExec_t ge[4] = {nullptr, nullptr, nullptr, nullptr};   // fwd 1 step, fwd k steps, rev A, rev B
+        auto capture = [&](int which) {
+            hipStream_t cs;
+            HIP_OK(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                if (which < 2) {
+                    h->d = traced;
+                    for (int q = 0; q < (which ? kGraphSteps : 1); ++q) launch_step(h, cs);
+                    h->d = saved;
+                } else {
+                    double *ax = lam[0], *av = lam[1], *bx = lam[2], *bv = lam[3];
+                    if (which == 3) {
+                        std::swap(ax, bx);
+                        std::swap(av, bv);
+                    }
+                    for (int i = R - 1; i >= 0; --i) {
+                        reverse_step(cs, i, ax, av, bx, bv);
+                        std::swap(ax, bx);
+                        std::swap(av, bv);
+                    }
+                }
+                e = hipStreamEndCapture(cs, &gg[which]);
             }
+            (void)hipStreamDestroy(cs);
+            HIP_OK(e);
+            HIP_OK(hipGraphInstantiate(&ge[which], gg[which], nullptr, nullptr, 0));
+        };
+        try {
+            for (int wch = 0; wch < 4; ++wch) capture(wch);
+            bool a_is_in = true;                       // lx/lv are lam[0]/lam[1]
+            for (int sg = nseg - 1; sg >= 0; --sg) {
+                const int t0 = sg * R, t1 = std::min(T, t0 + R);
+                load_state(h, h->snaps[sg], t0);
+                for (int t = t0; t < t1;) {
+                    const bool batch = t1 - t >= kGraphSteps;
+                    HIP_OK(hipGraphLaunch(ge[batch ? 1 : 0], h->stream));
+                    t += batch ? kGraphSteps : 1;
+                }
+                double *ix = a_is_in ? lam[0] : lam[2], *iv = a_is_in ? lam[1] : lam[3];
+                double *ox = a_is_in ? lam[2] : lam[0], *ov = a_is_in ? lam[3] : lam[1];
+                if (t1 - t0 == R) {
+                    HIP_OK(hipGraphLaunch(ge[a_is_in ? 2 : 3], h->stream));
+                } else {
+                    for (int t = t1 - 1; t >= t0; --t) {
+                        reverse_step(h->stream, t - t0, ix, iv, ox, ov);
+                        std::swap(ix, ox);
+                        std::swap(iv, ov);
+                    }
+                }
+                if ((t1 - t0) & 1) a_is_in = !a_is_in;
+            }
+            HIP_OK(hipGetLastError());
+        } catch (...) {
+            h->d = saved;
+            for (int q = 0; q < 4; ++q) {
+                if (ge[q]) (void)hipGraphExecDestroy(ge[q]);
+                if (gg[q]) (void)hipGraphDestroy(gg[q]);
+            }
+            throw;
         }
-        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(h->stream));
+        for (int q = 0; q < 4; ++q) {
+            if (ge[q]) (void)hipGraphExecDestroy(ge[q]);
+            if (gg[q]) (void)hipGraphDestroy(gg[q]);
+        }
         load_state(h, end_state, T);
         std::vector<double> gp((size_t)gbw * np);
         HIP_OK(hipMemcpyAsync(gp.data(), gpart, 8 * gp.size(), hipMemcpyDeviceToHost, h->stream));

@@ -235,9 +235,11 @@ struct Dev {
     int* big_list;
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
-    // traced re-run: record of step t at trace[(t - trace_t0) * trace_stride + slot]
+    // traced re-run of a segment that starts at a multiple of trace_period:
+    // record of step t at trace[(t % trace_period) * trace_stride + slot], so one
+    // captured graph serves every segment
     TraceRec* trace;
-    int trace_t0;
+    int trace_period;
     int trace_stride;
     int* nact_hist;
     char* big;
@@ -934,7 +936,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             tr.edge = e;
             tr.kb = (uint32_t)kind | (tb << 8);
             tr.pad = 0.0f;
-            d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + dst] = tr;
+            d.trace[(size_t)(t % d.trace_period) * d.trace_stride + dst] = tr;
         }
         b.pel[newpos] = elam;
         b.inv[newpos] = q;
@@ -1034,7 +1036,7 @@ __device__ inline void tile_step(const Dev& d) {
         d.ctl->t_b = t;
         d.ctl->n_big[par ^ 1] = 0;
         d.ctl->big_done = 0;
-        if (d.trace) d.nact_hist[t - d.trace_t0] = n;
+        if (d.trace) d.nact_hist[t % d.trace_period] = n;
     }
     __syncthreads();
     // a tile is the set of edges whose first slot lies in one window
@@ -1313,7 +1315,7 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
             won = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
         }
         if (d.trace)
-            d.trace[(size_t)(t - d.trace_t0) * d.trace_stride + ob.slot].kb |=
+            d.trace[(size_t)(t % d.trace_period) * d.trace_stride + ob.slot].kb |=
                 (ob.target < 0 ? TB_ARRIVE : (won ? TB_EXIT : TB_HELD)) << 8;
         if (ob.target < 0) {                       // arrival at the route end
             arrived = exits = true;
@@ -1772,6 +1774,15 @@ __global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, co
         }
         if (threadIdx.x == 0) gpart[(size_t)blockIdx.x * np + k] += red[0];
         __syncthreads();
+    }
+}
+
+// nx = nv = 0 before a step of the reverse sweep (a kernel, not a memset, so
+// that it can sit in a captured graph)
+__global__ void __launch_bounds__(kNT) k_zero2(double* a, double* b, int n) {
+    for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
+        a[i] = 0.0;
+        b[i] = 0.0;
     }
 }
 
