@@ -83,6 +83,9 @@ def _load(path):
     lib.orc_normal_d.argtypes = [U64, I64, I64, I32]
     lib.orc_normal_d.restype = D
     lib.orc_set_v0_spread.argtypes = [P, ctypes.c_float]
+    lib.orc_route.argtypes = [I32, I32, P, P, P, I32, I32, P, I32]
+    lib.orc_route.restype = I32
+    lib.orc_route_dist.argtypes = [I32, I32, P, P, P, I32, P]
     lib.orc_set_intersection_mode.argtypes = [P, I32]
     lib.orc_set_intersection_mode.restype = I32
     lib.orc_driver_limit_d.argtypes = [U64, I64, I64, ctypes.c_float, ctypes.c_float]
@@ -256,3 +259,24 @@ def driver_limit(seed, edge, vid, lim, spread, fp64=False):
 
 def mand_trigger(seed, t, vid, d, fp64=False):
     return lib(fp64).orc_mand_trigger(seed, t, vid, d)
+
+
+def route(net, cost, o, d, fp64=False):
+    """Shortest route from node o to node d on binary32 edge costs (list of
+    edge ids), or None (o == d or unreachable)."""
+    ef, et = _c(net.edge_from, np.int32), _c(net.edge_to, np.int32)
+    c = _c(cost, np.float32)
+    out = np.empty(net.n_edges, np.int32)
+    n = lib(fp64).orc_route(net.n_nodes, net.n_edges, _p(ef), _p(et), _p(c), int(o), int(d), _p(out), out.size)
+    return None if n < 0 else out[:n].tolist()
+
+
+def route_dist(net, cost, d, fp64=False):
+    """dist_d(v) for every node v (binary32 in the FP32 build)."""
+    ef, et = _c(net.edge_from, np.int32), _c(net.edge_to, np.int32)
+    c = _c(cost, np.float32)
+    dist = np.empty(net.n_nodes, np.float32 if not fp64 else np.float64)
+    if fp64:
+        raise NotImplementedError("route_dist is binary32")
+    lib(False).orc_route_dist(net.n_nodes, net.n_edges, _p(ef), _p(et), _p(c), int(d), _p(dist))
+    return dist

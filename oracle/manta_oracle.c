@@ -1155,3 +1155,74 @@ int32_t orc_set_intersection_mode(orc_sim *S, int32_t mode) {
     free(in_idx); free(indeg); free(outdeg);
     return rc;
 }
+
+/* ------------------------------------------------------------------ routes on travel times
+ * Shortest routes (Sec. II-C, re-computed on current edge costs) in binary32:
+ * dist_d(v) = min over out-edges e = (v -> u) of fl(cost_e + dist_d(u)),
+ * dist_d(d) = 0, by Dijkstra from d over the reversed edges (plain O(V^2)
+ * selection of the smallest label, ties to the lower node id).  The route
+ * from o leaves every node by the out-edge of smallest (fl(cost_e + dist(head
+ * e)), edge id) until it reaches d.  Returns the number of edges written, or
+ * -1 (o == d, d unreachable, or more than cap edges). */
+int32_t orc_route(int32_t n_nodes, int32_t n_edges, const int32_t *edge_from, const int32_t *edge_to,
+                  const float *cost, int32_t o, int32_t d, int32_t *out, int32_t cap) {
+    if (o == d) return -1;
+    float *dist = malloc(sizeof(float) * (size_t)n_nodes);
+    uint8_t *done = calloc((size_t)n_nodes, 1);
+    if (!dist || !done) { free(dist); free(done); return -1; }
+    for (int v = 0; v < n_nodes; v++) dist[v] = INFINITY;
+    dist[d] = 0.0f;
+    for (int it = 0; it < n_nodes; it++) {
+        int best = -1;
+        for (int v = 0; v < n_nodes; v++)
+            if (!done[v] && dist[v] < INFINITY && (best < 0 || dist[v] < dist[best])) best = v;
+        if (best < 0) break;
+        done[best] = 1;
+        for (int e = 0; e < n_edges; e++)          /* edges into best */
+            if (edge_to[e] == best && !done[edge_from[e]]) {
+                const float c = cost[e] + dist[best];
+                if (c < dist[edge_from[e]]) dist[edge_from[e]] = c;
+            }
+    }
+    int n = -1;
+    if (dist[o] < INFINITY) {
+        n = 0;
+        int v = o;
+        while (v != d) {
+            int be = -1;
+            float bc = INFINITY;
+            for (int e = 0; e < n_edges; e++)
+                if (edge_from[e] == v) {
+                    const float c = cost[e] + dist[edge_to[e]];
+                    if (be < 0 || c < bc) { be = e; bc = c; }   /* edges scanned in id order: ties to the lower id */
+                }
+            if (be < 0 || n >= cap) { n = -1; break; }
+            out[n++] = be;
+            v = edge_to[be];
+        }
+    }
+    free(dist); free(done);
+    return n;
+}
+
+/* dist_d(v) of the above for every node (pins) */
+void orc_route_dist(int32_t n_nodes, int32_t n_edges, const int32_t *edge_from, const int32_t *edge_to,
+                    const float *cost, int32_t d, float *dist) {
+    uint8_t *done = calloc((size_t)n_nodes, 1);
+    if (!done) return;
+    for (int v = 0; v < n_nodes; v++) dist[v] = INFINITY;
+    dist[d] = 0.0f;
+    for (int it = 0; it < n_nodes; it++) {
+        int best = -1;
+        for (int v = 0; v < n_nodes; v++)
+            if (!done[v] && dist[v] < INFINITY && (best < 0 || dist[v] < dist[best])) best = v;
+        if (best < 0) break;
+        done[best] = 1;
+        for (int e = 0; e < n_edges; e++)
+            if (edge_to[e] == best && !done[edge_from[e]]) {
+                const float c = cost[e] + dist[best];
+                if (c < dist[edge_from[e]]) dist[edge_from[e]] = c;
+            }
+    }
+    free(done);
+}
