@@ -1048,6 +1048,10 @@ void orc_write_state(orc_sim *S, int32_t t, const uint8_t *status, const int32_t
         S->status[i] = status[i];
         S->edge[i] = edge[i];
         S->lane[i] = lane[i];
+        if (status[i] == WAITING) {   /* a waiting vehicle sits at its first route edge and entry lane (A18) */
+            S->edge[i] = S->redges[S->roff[i]];
+            S->lane[i] = S->ins_lane[i];
+        }
         S->k[i] = cursor[i];
         S->x[i] = (REAL)x[i];
         S->v[i] = (REAL)v[i];
