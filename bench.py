@@ -364,6 +364,51 @@ def bench_metro_scale(args, M, torch, stream):
     }
 
 
+def bench_reroute(args, M, torch, stream):
+    """Routes on travel times for every vehicle of config 2 (200,000 O/D
+    pairs, about 9,900 distinct destinations, 10,040 nodes): edge costs are the
+    mean traversal times after 1.5 h of the plain run (free-flow time where
+    nothing traversed); sim_shortest_routes on the GPU, timed end to end (host
+    copies included), against the oracle's routing on a sample of pairs."""
+    import workloads as W
+    w = W.config2()
+    sim = M.Sim(w, stream=stream)
+    sim.step(10800)
+    mean, cnt = sim.mean_travel_times()
+    sim.close()
+    net = w.net
+    cost = np.where(cnt > 0, mean, net.length / net.limit).astype(np.float32)
+    o = net.edge_from[w.route_edges[w.route_off[:-1]]].astype(np.int32)
+    d = net.edge_to[w.route_edges[w.route_off[1:] - 1]].astype(np.int32)
+    M.shortest_routes(net, cost, o[:1000], d[:1000])           # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    off, edges = M.shortest_routes(net, cost, o, d)
+    t1 = time.perf_counter()
+    changed = sum(1 for q in range(0, o.size, 97)
+                  if not np.array_equal(edges[off[q]:off[q + 1]], w.route_edges[w.route_off[q]:w.route_off[q + 1]]))
+    line = {
+        "metric": "routes/s (sim_shortest_routes, 1 GPU)", "value": o.size / (t1 - t0), "unit": "routes/s",
+        "n_gpus": 1, "steps": 10800, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "reroute_perturbed_grid_ring", "queries": int(o.size),
+                   "destinations": int(np.unique(d).size), "nodes": int(net.n_nodes), "edges": int(net.n_edges),
+                   "route_edges": int(edges.size), "s": t1 - t0,
+                   "changed_vs_free_flow_routes_sampled": changed / len(range(0, o.size, 97))},
+    }
+    if args.cpu_steps > 0:
+        import oracle
+        k = 12
+        t2 = time.perf_counter()
+        for q in range(k):
+            r = oracle.route(net, cost, int(o[q]), int(d[q]))
+            assert r == edges[off[q]:off[q + 1]].tolist()
+        t3 = time.perf_counter()
+        line["cpu_baseline"] = {"value": k / (t3 - t2), "unit": "routes/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the first {k} O/D pairs (one O(V^2) Dijkstra each), same routes"}
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -371,7 +416,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--workload", default="perturbed_grid_ring",
                     choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration", "calibration_search",
-                             "metro_scale"])
+                             "metro_scale", "reroute"])
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
@@ -414,6 +459,9 @@ def main():
         return
     if args.workload == "calibration":
         print(json.dumps(bench_calibration(args, M, torch, stream)), flush=True)
+        return
+    if args.workload == "reroute":
+        print(json.dumps(bench_reroute(args, M, torch, stream)), flush=True)
         return
     if args.workload == "metro_scale":
         print(json.dumps(bench_metro_scale(args, M, torch, stream)), flush=True)

@@ -249,6 +249,25 @@ sim_status sim_destroy(sim_handle *h);
 
 /* Message of the last failed call on h (or of the last failed sim_create when
  * h is NULL).  Valid until the next call on the same handle. */
+/* Shortest routes on travel times (the routes of Sec. II-C, which the paper
+ * computes once on CPUs, re-computed on the GPU from current per-edge costs,
+ * e.g. the mean traversal times of sim_read_edge_stats).  edge_cost: [n_edges]
+ * binary32 seconds, finite and > 0.  For each query q the route from node
+ * origin[q] to node dest[q] minimises the cost summed, in binary32, from the
+ * destination back (dist(d) = 0, dist(v) = min over out-edges e of
+ * cost_e + dist(head e)) and leaves every node by the out-edge of smallest
+ * (cost_e + dist(head e), edge id).  No move restrictions are applied: a
+ * shortest route never turns back, so on networks whose moves exclude only
+ * U-turns every route is a valid route for sim_create.
+ * Output (host memory): route_off [n_queries + 1] and route_edges [capacity];
+ * *n_route_edges is set to the total even when capacity is too small (then
+ * SIM_EINVAL).  Errors: SIM_EINVAL (bad input, origin == destination, no
+ * route), SIM_EUNSUPPORTED (more than 16,000 nodes), SIM_ENOMEM, SIM_EDEVICE.
+ * Needs no handle; runs on the current device and synchronises it. */
+sim_status sim_shortest_routes(const sim_network *net, const float *edge_cost, int32_t n_queries,
+                               const int32_t *origin, const int32_t *dest, int64_t *route_off,
+                               int32_t *route_edges, int64_t capacity, int64_t *n_route_edges);
+
 const char *sim_last_error(const sim_handle *h);
 
 /* Vehicle-updates done in tiles above one workgroup's LDS (inside

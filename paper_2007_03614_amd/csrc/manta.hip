@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "../../include/manta.h"
+#include "routing.hpp"
 #include "step_kernels.hpp"
 
 using namespace manta;
@@ -1449,3 +1450,104 @@ sim_status sim_probe_draws(uint64_t seed, const int64_t* t, const int64_t* id, f
 }
 
 }  // extern "C"
+
+// ---- routes on travel times ------------------------------------------------
+namespace {
+struct DevBufs {   // device buffers of one routing call, freed on every exit
+    std::vector<void*> p;
+    template <class T>
+    T* get(size_t n) {
+        void* q = nullptr;
+        HIP_OK(hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+        p.push_back(q);
+        return (T*)q;
+    }
+    ~DevBufs() {
+        for (void* q : p) (void)hipFree(q);
+    }
+};
+}  // namespace
+
+extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* edge_cost, int32_t n_queries,
+                                          const int32_t* origin, const int32_t* dest, int64_t* route_off,
+                                          int32_t* route_edges, int64_t capacity, int64_t* n_route_edges) {
+    return guarded(nullptr, [&] {
+        auto bad = [](std::string m) { throw Fail{SIM_EINVAL, std::move(m)}; };
+        if (!net || !edge_cost || !route_off || !n_route_edges || n_queries < 0) bad("null argument");
+        if (n_queries > 0 && (!origin || !dest)) bad("null argument");
+        const int V = net->n_nodes, E = net->n_edges;
+        if (V <= 0 || E <= 0 || !net->edge_from || !net->edge_to) bad("network must have nodes and edges");
+        if (V > kRouteMaxNodes) throw Fail{SIM_EUNSUPPORTED, fmt("more than %d nodes", kRouteMaxNodes)};
+        for (int e = 0; e < E; ++e) {
+            if (net->edge_from[e] < 0 || net->edge_from[e] >= V || net->edge_to[e] < 0 || net->edge_to[e] >= V)
+                bad(fmt("edge %d: node out of range", e));
+            if (!(std::isfinite(edge_cost[e]) && edge_cost[e] > 0.0f)) bad(fmt("edge %d: cost not finite and > 0", e));
+        }
+        for (int q = 0; q < n_queries; ++q)
+            if (origin[q] < 0 || origin[q] >= V || dest[q] < 0 || dest[q] >= V) bad(fmt("query %d: node out of range", q));
+        route_off[0] = 0;
+        if (n_queries == 0) {
+            *n_route_edges = 0;
+            return;
+        }
+        // out-edges per node, ascending edge id
+        std::vector<int> out_off(V + 1, 0), out_edge(E), fill(V, 0);
+        for (int e = 0; e < E; ++e) ++out_off[net->edge_from[e] + 1];
+        for (int v = 0; v < V; ++v) out_off[v + 1] += out_off[v];
+        for (int e = 0; e < E; ++e) out_edge[out_off[net->edge_from[e]] + fill[net->edge_from[e]]++] = e;
+        // one label array per distinct destination
+        std::vector<int> slot_of(V, -1), dests, slot(n_queries);
+        for (int q = 0; q < n_queries; ++q) {
+            if (slot_of[dest[q]] < 0) {
+                slot_of[dest[q]] = (int)dests.size();
+                dests.push_back(dest[q]);
+            }
+            slot[q] = slot_of[dest[q]];
+        }
+        const int nd = (int)dests.size();
+        if ((double)nd * V * 4.0 > 16e9) throw Fail{SIM_EUNSUPPORTED, "labels of all destinations above 16 GB"};
+        DevBufs b;
+        int* d_off = b.get<int>(V + 1);
+        int* d_oe = b.get<int>(E);
+        int* d_to = b.get<int>(E);
+        float* d_cost = b.get<float>(E);
+        int* d_dest = b.get<int>(nd);
+        float* d_dist = b.get<float>((size_t)nd * V);
+        int* d_slot = b.get<int>(n_queries);
+        int* d_o = b.get<int>(n_queries);
+        int* d_d = b.get<int>(n_queries);
+        int* d_len = b.get<int>(n_queries);
+        HIP_OK(hipMemcpy(d_off, out_off.data(), 4 * (size_t)(V + 1), hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_oe, out_edge.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_to, net->edge_to, 4 * (size_t)E, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_cost, edge_cost, 4 * (size_t)E, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_dest, dests.data(), 4 * (size_t)nd, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_slot, slot.data(), 4 * (size_t)n_queries, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_o, origin, 4 * (size_t)n_queries, hipMemcpyHostToDevice));
+        HIP_OK(hipMemcpy(d_d, dest, 4 * (size_t)n_queries, hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_route_dist, dim3(std::min(nd, 2048)), dim3(kRouteNT), 0, 0, V, d_off, d_oe, d_to, d_cost,
+                           d_dest, nd, d_dist);
+        HIP_OK(hipGetLastError());
+        const int gw = std::max(1, std::min(4096, (n_queries + 255) / 256));
+        hipLaunchKernelGGL(k_route_walk, dim3(gw), dim3(256), 0, 0, V, d_off, d_oe, d_to, d_cost, d_dist, d_slot, d_o,
+                           d_d, n_queries, 0, d_len, (const int64_t*)nullptr, (int*)nullptr);
+        HIP_OK(hipGetLastError());
+        std::vector<int> len(n_queries);
+        HIP_OK(hipMemcpy(len.data(), d_len, 4 * (size_t)n_queries, hipMemcpyDeviceToHost));
+        for (int q = 0; q < n_queries; ++q) {
+            if (len[q] < 0) bad(fmt("query %d: no route from node %d to node %d", q, origin[q], dest[q]));
+            route_off[q + 1] = route_off[q] + len[q];
+        }
+        *n_route_edges = route_off[n_queries];
+        if (!route_edges || capacity < route_off[n_queries])
+            bad(fmt("route_edges holds %lld edges, the routes need %lld", (long long)capacity,
+                    (long long)route_off[n_queries]));
+        int64_t* d_roff = b.get<int64_t>(n_queries + 1);
+        int* d_re = b.get<int>((size_t)route_off[n_queries]);
+        HIP_OK(hipMemcpy(d_roff, route_off, 8 * (size_t)(n_queries + 1), hipMemcpyHostToDevice));
+        hipLaunchKernelGGL(k_route_walk, dim3(gw), dim3(256), 0, 0, V, d_off, d_oe, d_to, d_cost, d_dist, d_slot, d_o,
+                           d_d, n_queries, 1, d_len, (const int64_t*)d_roff, d_re);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipMemcpy(route_edges, d_re, 4 * (size_t)route_off[n_queries], hipMemcpyDeviceToHost));
+    });
+}

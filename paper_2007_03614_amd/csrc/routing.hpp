@@ -1,0 +1,95 @@
+// Routes on travel times (the fixed routes of Sec. II-C, re-computed on the
+// GPU from current per-edge costs, e.g. the mean traversal times of the step
+// statistics).  Binary32 costs; for a destination d
+//   dist(d) = 0,  dist(v) = min over out-edges e = (v -> u) of fl(cost_e + dist(u)),
+// and a route leaves every node by the out-edge of smallest
+// (fl(cost_e + dist(head e)), edge id).  Any order of relaxation reaches the
+// same least fixed point as Dijkstra from d when every cost is positive, so
+// the result does not depend on the schedule of the sweeps.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace manta {
+
+constexpr int kRouteNT = 1024;
+constexpr int kRouteMaxNodes = 16000;   // one binary32 label per node, within 64 KiB of LDS
+
+// One workgroup per destination: labels in LDS, Bellman-Ford sweeps in
+// place until one changes nothing (at most V sweeps).  Out-edges of node v
+// are out_edge[out_off[v] .. out_off[v + 1]).
+__global__ void __launch_bounds__(kRouteNT) k_route_dist(int V, const int* out_off, const int* out_edge,
+                                                        const int* edge_to, const float* cost, const int* dests,
+                                                        int nd, float* dist_out) {
+    __shared__ float dist[kRouteMaxNodes];
+    __shared__ int changed;
+    for (int q = blockIdx.x; q < nd; q += gridDim.x) {
+        const int d = dests[q];
+        for (int v = threadIdx.x; v < V; v += kRouteNT) dist[v] = v == d ? 0.0f : INFINITY;
+        __syncthreads();
+        for (int it = 0; it < V; ++it) {
+            if (threadIdx.x == 0) changed = 0;
+            __syncthreads();
+            bool ch = false;
+            for (int v = threadIdx.x; v < V; v += kRouteNT) {
+                float best = dist[v];
+                for (int k = out_off[v]; k < out_off[v + 1]; ++k) {
+                    const int e = out_edge[k];
+                    const float c = cost[e] + dist[edge_to[e]];
+                    if (c < best) best = c;
+                }
+                if (best < dist[v]) {
+                    dist[v] = best;
+                    ch = true;
+                }
+            }
+            if (ch) changed = 1;
+            __syncthreads();
+            const bool more = changed != 0;
+            __syncthreads();   // every thread has read the flag before it is reset
+            if (!more) break;
+        }
+        for (int v = threadIdx.x; v < V; v += kRouteNT) dist_out[(size_t)q * V + v] = dist[v];
+        __syncthreads();
+    }
+}
+
+// One thread per query: walk from the origin to the destination over the
+// labels of its destination (slot).  fill == 0: write the number of edges to
+// len[q] (-1: origin == destination, unreachable, or longer than V edges);
+// fill == 1: write the edges at route_edges[off[q] ...].
+__global__ void __launch_bounds__(256) k_route_walk(int V, const int* out_off, const int* out_edge,
+                                                   const int* edge_to, const float* cost, const float* dist_all,
+                                                   const int* slot, const int* origin, const int* dest, int nq,
+                                                   int fill, int* len, const int64_t* off, int* route_edges) {
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < nq; q += gridDim.x * 256) {
+        const float* dist = dist_all + (size_t)slot[q] * V;
+        const int o = origin[q], d = dest[q];
+        int n = 0;
+        bool ok = o != d && dist[o] < INFINITY;
+        int v = o;
+        while (ok && v != d) {
+            int be = -1;
+            float bc = INFINITY;
+            for (int k = out_off[v]; k < out_off[v + 1]; ++k) {   // ascending edge id within a node
+                const int e = out_edge[k];
+                const float c = cost[e] + dist[edge_to[e]];
+                if (be < 0 || c < bc) {
+                    be = e;
+                    bc = c;
+                }
+            }
+            if (be < 0 || n >= V) {
+                ok = false;
+                break;
+            }
+            if (fill) route_edges[off[q] + n] = be;
+            ++n;
+            v = edge_to[be];
+        }
+        if (!fill) len[q] = ok ? n : -1;
+    }
+}
+
+}  // namespace manta
