@@ -445,8 +445,8 @@ def main():
         print(json.dumps(traffic_from(*args.traffic_from, probe_mib=args.copy_probe or 256), indent=1))
         return
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulation is "
-              "single-device and its multi-GPU sharding is not part of this build.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the simulation is single-device; "
+              "sharding it by edges over several GPUs is not implemented.", file=sys.stderr)
         sys.exit(2)
 
     import torch
