@@ -76,7 +76,7 @@ typedef struct {
     const float *v0_factor, *T, *a, *b, *s0, *length_m;   /* [n_classes] */
     float dt;                             /* (0, 1]; the paper uses 0.5 s */
     uint64_t seed;                        /* Philox key for the lane-change draws */
-    int32_t intersection_mode;            /* Sec. II-E traffic control.  0 = case 2, all green: a front crosses
+    int32_t intersection_mode;            /* Sec. II-D traffic control.  0 = case 2, all green: a front crosses
                                            * when the target lane has room.  1 = case 1, flashing red: a front
                                            * crosses only after standing ceil(2 s / dt) steps at the stop line,
                                            * and each node passes one vehicle per step, its (in, out) pairs

@@ -1,4 +1,4 @@
-"""Pins for case 1 intersections (flashing red, Sec. II-E and the red/green
+"""Pins for case 1 intersections (flashing red, Sec. II-D and the red/green
 light runs): a vehicle passes only after stopping 2 s at the line, one vehicle
 crosses a node at a time, and the node serves its n x m (in, out) pairs
 round-robin, the vehicles of a pair in the order they reached the line.
