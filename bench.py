@@ -84,6 +84,21 @@ def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step",),
             "fetch_scale": fs, "write_scale": ws}
 
 
+def stored_traffic(workload: str, v0_spread: float = 0.0, intersection_mode: int = 0,
+                   path: str = TRAFFIC_FILE):
+    """HBM bytes per step of k_tile_step from the committed counter record, or
+    None when there is no record or it was taken on other HIP sources, another
+    workload or other options (its bytes then describe another kernel)."""
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if (tr.get("workload") == workload and tr.get("sources") == kernel_source_digest()
+            and tr.get("v0_spread", 0.0) == v0_spread and tr.get("intersection_mode", 0) == intersection_mode):
+        return tr.get("bytes_per_step")
+    return None
+
+
 def make_workload(name: str):
     import workloads as W
     if name == "perturbed_grid_ring":
@@ -531,14 +546,7 @@ def main():
     # tiles above one workgroup's LDS) over its event-measured time
     tile_ms = kernel_ms["k_tile_step"]
     achieved = BYTES_PER_UPDATE * (upd - big_upd) / (tile_ms / 1e3) / 1e9
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if (tr.get("workload") == args.workload and tr.get("sources") == kernel_source_digest()
-                and tr.get("v0_spread", 0.0) == args.v0_spread
-                and tr.get("intersection_mode", 0) == args.intersection_mode):
-            traffic = tr.get("bytes_per_step")
+    traffic = stored_traffic(args.workload, args.v0_spread, args.intersection_mode)
     line = {
         "metric": "vehicle-updates/sec (1 GPU)",
         "value": value,

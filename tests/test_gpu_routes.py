@@ -89,3 +89,20 @@ def test_reroute_future_departures_continues_like_the_oracle(M, oracle_mod):
     assert changed > 0
     _, o, bitwise = run_pair(M, oracle_mod, w2, [901, 1800, 3600], init=st)
     assert bitwise and o.counters()["arrived"] > 0
+
+
+def test_routes_at_the_node_limit(M, oracle_mod):
+    """A 125 x 128 grid has 16,000 nodes, the most whose labels one
+    workgroup's LDS holds: routes on perturbed costs still equal the oracle's
+    (corner to corner, about 250 edges).  One node more is refused."""
+    net = W.grid_network(125, 128)
+    assert net.n_nodes == 16000
+    cost = ((net.length / net.limit) * np.random.default_rng(9).uniform(0.5, 2.0, net.n_edges)).astype(np.float32)
+    o = np.array([0, 127, 8000, 15999, 15872, 64], np.int32)
+    d = np.array([15999, 15872, 15999, 0, 127, 8000], np.int32)
+    _check(M, oracle_mod, net, cost, o, d)
+    big = W.grid_network(127, 127)
+    assert big.n_nodes > 16000
+    with pytest.raises(M.SimError):
+        M.shortest_routes(big, np.full(big.n_edges, 1.0, np.float32), np.array([0], np.int32),
+                          np.array([5], np.int32))
