@@ -52,9 +52,10 @@ def test_parity_scaled_config2_case1(M, oracle_mod):
 
 
 def test_case1_resume_from_written_state(M, oracle_mod):
-    """sim_write_state restarts the round-robin on both sides."""
+    """sim_write_state restarts the round-robin on both sides.  The written
+    state is the oracle's own at step 900."""
     w = case1(W.config1())
-    a = M.Sim(w)
+    a = oracle_mod.OracleSim(w)
     a.step(900)
     st = a.state()
     init = {k: st[k] for k in ("status", "edge", "lane", "cursor", "x", "v", "held_since", "mand", "ww",
@@ -102,7 +103,9 @@ def test_backward_case1_matches_fp64_adjoint(M, oracle_mod):
     o = oracle_mod.OracleSim(w)
     o.enable_record()
     o.step(steps)
-    _, _, og = o.replay(o.theta(w), target, use.astype(np.uint8), grad=True)
+    ouse = (o.edge_stats()[1] > 0) & (c > 0)     # the oracle's own mask, from its own run
+    assert np.array_equal(ouse, use)
+    _, _, og = o.replay(o.theta(w), target, ouse.astype(np.uint8), grad=True)
     og = og.reshape(-1, 5)
     rel = np.linalg.norm(g - og) / np.linalg.norm(og)
     print("relative gradient error vs FP64 adjoint (case 1):", rel)

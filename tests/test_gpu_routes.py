@@ -69,12 +69,41 @@ def test_errors(M):
     assert off.tolist() == [0] and edges.size == 0
 
 
+def _oracle_reroute(oracle_mod, w, ost):
+    """The oracle's side of re-routing, from the oracle's own run: costs =
+    its mean traversal times (free-flow where nothing traversed), new routes
+    of the vehicles still waiting for a later departure from oracle.route,
+    and the state to continue from (first route edge, cursor 0)."""
+    t = int(ost["t"])
+    s, c = ost["edge_stats"]
+    mean = np.where(c > 0, s / np.maximum(c, 1), 0.0)
+    cost = np.where(c > 0, mean, w.net.length / w.net.limit).astype(np.float32)
+    net, roff, redges = w.net, w.route_off, w.route_edges
+    routes = []
+    for i in range(w.n_vehicles):
+        r = redges[roff[i]:roff[i + 1]].tolist()
+        if w.depart_step[i] > t and ost["status"][i] == 0:
+            r = oracle_mod.route(net, cost, int(net.edge_from[r[0]]), int(net.edge_to[r[-1]]))
+        routes.append(r)
+    w2 = W.Workload(w.name, net, np.concatenate([[0], np.cumsum([len(r) for r in routes])]).astype(np.int64),
+                    np.concatenate(routes).astype(np.int32), w.depart_step, w.vclass, w.alpha, w.params, w.n_steps)
+    fut = np.nonzero((w.depart_step > t) & (ost["status"] == 0))[0]
+    st = {k: np.array(ost[k], copy=True) for k in ("status", "edge", "lane", "cursor", "x", "v", "held_since",
+                                                   "mand", "ww", "tau_in")}
+    st["edge"][fut] = w2.route_edges[w2.route_off[fut]]
+    st["cursor"][fut] = 0
+    st.update(t_arr=np.full(w.n_vehicles, -1.0), counters=None, t=t)
+    return w2, st, cost
+
+
 def test_reroute_future_departures_continues_like_the_oracle(M, oracle_mod):
     """Config 1 with departures over 30 min: at step 900 the vehicles not yet
-    departed get routes on the mean traversal times so far (GPU routing);
-    the run goes on from the same state on the GPU and in the oracle."""
+    departed get routes on the mean traversal times so far.  The GPU side
+    re-routes from its own run with GPU routing, the oracle side from its own
+    run with the oracle's routes; the costs, the new routes and the
+    continued runs agree."""
     from paper_2007_03614_amd.reroute import reroute_future_departures
-    from test_gpu_parity import run_pair
+    from test_gpu_parity import compare_states
     w = W.config1(n_steps=3600)
     w.depart_step = (w.depart_step * 3).astype(np.int32)     # departures over 30 min
     sim = M.Sim(w)
@@ -82,12 +111,28 @@ def test_reroute_future_departures_continues_like_the_oracle(M, oracle_mod):
     mean, cnt = sim.mean_travel_times()
     cost = np.where(cnt > 0, mean, w.net.length / w.net.limit).astype(np.float32)
     w2, st = reroute_future_departures(w, sim.state(), cost)
+    o0 = oracle_mod.OracleSim(w)
+    o0.step(900)
+    ost = o0.state()
+    ost["edge_stats"] = o0.edge_stats()
+    w2o, sto, costo = _oracle_reroute(oracle_mod, w, ost)
+    assert np.array_equal(cost, costo)
+    assert np.array_equal(w2.route_off, w2o.route_off) and np.array_equal(w2.route_edges, w2o.route_edges)
     fut = np.nonzero(w.depart_step > 900)[0]
     assert fut.size > 500
     changed = sum(not np.array_equal(w.route_edges[w.route_off[i]:w.route_off[i + 1]],
                                      w2.route_edges[w2.route_off[i]:w2.route_off[i + 1]]) for i in fut)
     assert changed > 0
-    _, o, bitwise = run_pair(M, oracle_mod, w2, [901, 1800, 3600], init=st)
+    g = M.Sim(w2)
+    g.write_state(st)
+    o = oracle_mod.OracleSim(w2o)
+    o.write_state(sto["t"], sto)
+    t, bitwise = 900, True
+    for cp in (901, 1800, 3600):
+        g.step(cp - t)
+        o.step(cp - t)
+        t = cp
+        bitwise &= compare_states(g.state(), o.state(), f"step {t}")
     assert bitwise and o.counters()["arrived"] > 0
 
 

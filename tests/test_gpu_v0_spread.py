@@ -98,7 +98,9 @@ def test_backward_with_spread_matches_fp64_adjoint(M, oracle_mod):
     o = oracle_mod.OracleSim(w)
     o.enable_record()
     o.step(steps)
-    _, _, og = o.replay(o.theta(w), target, use.astype(np.uint8), grad=True)
+    ouse = (o.edge_stats()[1] > 0) & (c > 0)     # the oracle's own mask, from its own run
+    assert np.array_equal(ouse, use)
+    _, _, og = o.replay(o.theta(w), target, ouse.astype(np.uint8), grad=True)
     og = og.reshape(-1, 5)
     rel = np.linalg.norm(g - og) / np.linalg.norm(og)
     print("relative gradient error vs FP64 adjoint (v0 spread 0.05):", rel)
