@@ -1525,8 +1525,31 @@ extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* e
         HIP_OK(hipMemcpy(d_slot, slot.data(), 4 * (size_t)n_queries, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d_o, origin, 4 * (size_t)n_queries, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d_d, dest, 4 * (size_t)n_queries, hipMemcpyHostToDevice));
-        hipLaunchKernelGGL(k_route_dist, dim3(std::min(nd, 2048)), dim3(kRouteNT), 0, 0, V, d_off, d_oe, d_to, d_cost,
-                           d_dest, nd, d_dist);
+        int max_deg = 0;
+        for (int v = 0; v < V; ++v) max_deg = std::max(max_deg, out_off[v + 1] - out_off[v]);
+        const dim3 gd(std::min(nd, 2048));
+        if (max_deg <= 8) {   // padded adjacency, slot-major: [j * V + v]
+            const int km = max_deg <= 4 ? 4 : 8;
+            std::vector<int> pto((size_t)km * V);
+            std::vector<float> pcost((size_t)km * V);
+            for (int v = 0; v < V; ++v)
+                for (int j = 0; j < km; ++j) {
+                    const int k = out_off[v] + j;
+                    const bool has = k < out_off[v + 1];
+                    pto[(size_t)j * V + v] = has ? net->edge_to[out_edge[k]] : v;
+                    pcost[(size_t)j * V + v] = has ? edge_cost[out_edge[k]] : INFINITY;
+                }
+            int* d_pto = b.get<int>((size_t)km * V);
+            float* d_pcost = b.get<float>((size_t)km * V);
+            HIP_OK(hipMemcpy(d_pto, pto.data(), 4 * (size_t)km * V, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d_pcost, pcost.data(), 4 * (size_t)km * V, hipMemcpyHostToDevice));
+            if (km == 4)
+                hipLaunchKernelGGL(k_route_dist_padded<4>, gd, dim3(kRouteNT), 0, 0, V, d_pto, d_pcost, d_dest, nd, d_dist);
+            else
+                hipLaunchKernelGGL(k_route_dist_padded<8>, gd, dim3(kRouteNT), 0, 0, V, d_pto, d_pcost, d_dest, nd, d_dist);
+        } else {
+            hipLaunchKernelGGL(k_route_dist, gd, dim3(kRouteNT), 0, 0, V, d_off, d_oe, d_to, d_cost, d_dest, nd, d_dist);
+        }
         HIP_OK(hipGetLastError());
         const int gw = std::max(1, std::min(4096, (n_queries + 255) / 256));
         hipLaunchKernelGGL(k_route_walk, dim3(gw), dim3(256), 0, 0, V, d_off, d_oe, d_to, d_cost, d_dist, d_slot, d_o,

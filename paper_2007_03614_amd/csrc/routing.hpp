@@ -55,6 +55,58 @@ __global__ void __launch_bounds__(kRouteNT) k_route_dist(int V, const int* out_o
     }
 }
 
+// The same sweeps over a padded adjacency: slot j of node v holds its j-th
+// out-edge's head and cost at [j * V + v] (unused slots: head v, cost +inf,
+// which never improves a label).  A node's KM loads are independent of each
+// other and of the labels, so they are in flight together, and neighbouring
+// threads read neighbouring words; the CSR form above chains out_off ->
+// out_edge -> edge_to for every edge.  Same labels: each is the minimum of
+// the same fl(cost + dist(head)) values, in any order.
+template <int KM>
+__global__ void __launch_bounds__(kRouteNT) k_route_dist_padded(int V, const int* __restrict__ adj_to,
+                                                               const float* __restrict__ adj_cost,
+                                                               const int* __restrict__ dests, int nd,
+                                                               float* __restrict__ dist_out) {
+    __shared__ float dist[kRouteMaxNodes];
+    __shared__ int changed;
+    for (int q = blockIdx.x; q < nd; q += gridDim.x) {
+        const int d = dests[q];
+        for (int v = threadIdx.x; v < V; v += kRouteNT) dist[v] = v == d ? 0.0f : INFINITY;
+        __syncthreads();
+        for (int it = 0; it < V; ++it) {
+            if (threadIdx.x == 0) changed = 0;
+            __syncthreads();
+            bool ch = false;
+            for (int v = threadIdx.x; v < V; v += kRouteNT) {
+                int to[KM];
+                float c[KM];
+#pragma unroll
+                for (int j = 0; j < KM; ++j) {
+                    to[j] = adj_to[(size_t)j * V + v];
+                    c[j] = adj_cost[(size_t)j * V + v];
+                }
+                float best = dist[v];
+#pragma unroll
+                for (int j = 0; j < KM; ++j) {
+                    const float cj = c[j] + dist[to[j]];
+                    if (cj < best) best = cj;
+                }
+                if (best < dist[v]) {
+                    dist[v] = best;
+                    ch = true;
+                }
+            }
+            if (ch) changed = 1;
+            __syncthreads();
+            const bool more = changed != 0;
+            __syncthreads();   // every thread has read the flag before it is reset
+            if (!more) break;
+        }
+        for (int v = threadIdx.x; v < V; v += kRouteNT) dist_out[(size_t)q * V + v] = dist[v];
+        __syncthreads();
+    }
+}
+
 // One thread per query: walk from the origin to the destination over the
 // labels of its destination (slot).  fill == 0: write the number of edges to
 // len[q] (-1: origin == destination, unreachable, or longer than V edges);

@@ -151,3 +151,30 @@ def test_routes_at_the_node_limit(M, oracle_mod):
     with pytest.raises(M.SimError):
         M.shortest_routes(big, np.full(big.n_edges, 1.0, np.float32), np.array([0], np.int32),
                           np.array([5], np.int32))
+
+
+def _grid_with_hub(n_spokes):
+    """10 x 10 grid plus a hub node joined both ways to n_spokes grid nodes:
+    the hub's out-degree picks the label kernel (<= 4, <= 8 padded slots,
+    above 8 the CSR form)."""
+    g = W.grid_network(10, 10)
+    spokes = np.linspace(0, 99, n_spokes).astype(int)
+    seg_u = np.concatenate([g.edge_from[g.edge_from < g.edge_to], np.full(n_spokes, 100)])
+    seg_v = np.concatenate([g.edge_to[g.edge_from < g.edge_to], spokes])
+    nx = np.concatenate([g.node_x, [900.0]])
+    ny = np.concatenate([g.node_y, [2300.0]])
+    ln = np.hypot(nx[seg_u] - nx[seg_v], ny[seg_u] - ny[seg_v])
+    n = seg_u.size
+    return W._finish_edges(nx, ny, seg_u, seg_v, ln, np.full(n, np.float32(50 / 3.6)), np.full(n, 2))
+
+
+@pytest.mark.parametrize("n_spokes", [3, 7, 12])
+def test_label_kernels_by_out_degree(M, oracle_mod, n_spokes):
+    net = _grid_with_hub(n_spokes)
+    assert np.bincount(net.edge_from).max() == max(4, n_spokes)
+    cost = ((net.length / net.limit) * np.random.default_rng(n_spokes).uniform(0.5, 2.0, net.n_edges)).astype(np.float32)
+    rng = np.random.default_rng(11)
+    o = np.concatenate([rng.integers(0, 101, 150), np.full(20, 100)]).astype(np.int32)
+    d = np.concatenate([rng.integers(0, 101, 150), rng.integers(0, 100, 20)]).astype(np.int32)
+    d[o == d] = (d[o == d] + 1) % 101
+    _check(M, oracle_mod, net, cost, o, d)
