@@ -1543,7 +1543,10 @@ extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* e
             float* d_pcost = b.get<float>((size_t)km * V);
             HIP_OK(hipMemcpy(d_pto, pto.data(), 4 * (size_t)km * V, hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(d_pcost, pcost.data(), 4 * (size_t)km * V, hipMemcpyHostToDevice));
-            if (km == 4)
+            if (km == 4 && V <= 10 * kRouteNT)   // adjacency in registers
+                hipLaunchKernelGGL((k_route_dist_regs<4, 10>), gd, dim3(kRouteNT), 0, 0, V, d_pto, d_pcost, d_dest, nd,
+                                   d_dist);
+            else if (km == 4)
                 hipLaunchKernelGGL(k_route_dist_padded<4>, gd, dim3(kRouteNT), 0, 0, V, d_pto, d_pcost, d_dest, nd, d_dist);
             else
                 hipLaunchKernelGGL(k_route_dist_padded<8>, gd, dim3(kRouteNT), 0, 0, V, d_pto, d_pcost, d_dest, nd, d_dist);

@@ -107,6 +107,63 @@ __global__ void __launch_bounds__(kRouteNT) k_route_dist_padded(int V, const int
     }
 }
 
+// The padded sweeps with the adjacency held in registers: thread x owns
+// nodes x + i * kRouteNT (i < NPT) and loads their KM (head, cost) slots once
+// per workgroup, before its first destination; a sweep then touches only
+// the labels in LDS.  For networks of at most NPT * kRouteNT nodes.
+template <int KM, int NPT>
+__global__ void __launch_bounds__(kRouteNT) k_route_dist_regs(int V, const int* __restrict__ adj_to,
+                                                             const float* __restrict__ adj_cost,
+                                                             const int* __restrict__ dests, int nd,
+                                                             float* __restrict__ dist_out) {
+    __shared__ float dist[kRouteMaxNodes];
+    __shared__ int changed;
+    int to[NPT][KM];
+    float c[NPT][KM];
+#pragma unroll
+    for (int i = 0; i < NPT; ++i) {
+        const int v = (int)threadIdx.x + i * kRouteNT;
+#pragma unroll
+        for (int j = 0; j < KM; ++j) {
+            to[i][j] = v < V ? adj_to[(size_t)j * V + v] : 0;
+            c[i][j] = v < V ? adj_cost[(size_t)j * V + v] : INFINITY;
+        }
+    }
+    for (int q = blockIdx.x; q < nd; q += gridDim.x) {
+        const int d = dests[q];
+        for (int v = threadIdx.x; v < V; v += kRouteNT) dist[v] = v == d ? 0.0f : INFINITY;
+        __syncthreads();
+        for (int it = 0; it < V; ++it) {
+            if (threadIdx.x == 0) changed = 0;
+            __syncthreads();
+            bool ch = false;
+#pragma unroll
+            for (int i = 0; i < NPT; ++i) {
+                const int v = (int)threadIdx.x + i * kRouteNT;
+                if (v < V) {
+                    float best = dist[v];
+#pragma unroll
+                    for (int j = 0; j < KM; ++j) {
+                        const float cj = c[i][j] + dist[to[i][j]];
+                        if (cj < best) best = cj;
+                    }
+                    if (best < dist[v]) {
+                        dist[v] = best;
+                        ch = true;
+                    }
+                }
+            }
+            if (ch) changed = 1;
+            __syncthreads();
+            const bool more = changed != 0;
+            __syncthreads();   // every thread has read the flag before it is reset
+            if (!more) break;
+        }
+        for (int v = threadIdx.x; v < V; v += kRouteNT) dist_out[(size_t)q * V + v] = dist[v];
+        __syncthreads();
+    }
+}
+
 // One thread per query: walk from the origin to the destination over the
 // labels of its destination (slot).  fill == 0: write the number of edges to
 // len[q] (-1: origin == destination, unreachable, or longer than V edges);
