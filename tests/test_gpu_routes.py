@@ -178,3 +178,16 @@ def test_label_kernels_by_out_degree(M, oracle_mod, n_spokes):
     d = np.concatenate([rng.integers(0, 101, 150), rng.integers(0, 100, 20)]).astype(np.int32)
     d[o == d] = (d[o == d] + 1) % 101
     _check(M, oracle_mod, net, cost, o, d)
+
+
+@pytest.mark.parametrize("rows,cols", [(80, 128), (81, 127)])
+def test_register_label_kernel_at_its_node_limit(M, oracle_mod, rows, cols):
+    """The register-resident label kernel holds 10 nodes per thread of 1,024:
+    10,240 nodes fill every slot (the last thread's last node is 10,239);
+    10,287 nodes go to the padded kernel.  Routes equal the oracle's on both."""
+    net = W.grid_network(rows, cols)
+    cost = ((net.length / net.limit) * np.random.default_rng(rows).uniform(0.5, 2.0, net.n_edges)).astype(np.float32)
+    V = net.n_nodes
+    o = np.array([0, V - 1, cols - 1, V - cols], np.int32)
+    d = np.array([V - 1, 0, V - cols, V - 2], np.int32)
+    _check(M, oracle_mod, net, cost, o, d)
