@@ -27,14 +27,16 @@
  *   Eqs. (3)-(4) critical lead and lag gaps with anticipation times
  *              alpha in [0.05, 0.40] and N(0,1) noise in metres;
  *   Sec. II-D (intersections, case 2)  all-green nodes, finite edge capacity.
- * Where the paper is silent the readings are the ones listed in the design
- * notes (A1..A24); each is named at the place it is used.
+ * Where the paper is silent, ambiguous or garbled, the reading taken is stated
+ * in a comment at the place it is used (tags A1..A35 name the readings).
  *
  * Parity pins: see tests/test_oracle_*.py (closed forms of Eq. (1), the
  * platoon equilibrium gap, Eq. (2) frequencies, Philox against numpy,
  * exp against libm, brute-force leader and admission checks, invariants).
- * Lane-change behaviour and the admission policy are pinned only by the
- * written contract: parity unpinned by the paper.
+ * Lane-change behaviour and the admission policy follow readings of the
+ * paper, which prints no values for them; they are pinned by brute-force
+ * re-derivations of those readings in plain Python (leaders, Phase-1
+ * decisions, admission winners, case-1 round-robin), not by paper values.
  */
 #include <math.h>
 #include <stdint.h>
