@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SRC = os.path.join(HERE, "csrc", "manta.hip")
 DEPS = [SRC, os.path.join(HERE, "csrc", "step_kernels.hpp"), os.path.join(HERE, "csrc", "device_math.hpp"),
-        os.path.join(ROOT, "include", "manta.h")]
+        os.path.join(HERE, "csrc", "routing.hpp"), os.path.join(ROOT, "include", "manta.h")]
 LIB = os.path.join(HERE, "libmanta.so")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
