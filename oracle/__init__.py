@@ -63,6 +63,7 @@ def _load(path):
     lib.orc_counters.argtypes = [P, P]
     lib.orc_edge_stats.argtypes = [P, P, P]
     lib.orc_last_events.argtypes = [P] + [P] * 7
+    lib.orc_last_partner.argtypes = [P, P]
     lib.orc_real_bytes.restype = I32
     lib.orc_enable_record.argtypes = [P]
     lib.orc_enable_record.restype = I32
@@ -211,6 +212,8 @@ class OracleSim:
                   target_lane=np.empty(n, np.int32))
         self._lib.orc_last_events(self._h, *[_p(ev[k]) for k in ("leader", "kind", "flags", "post_lane",
                                                                    "xnew", "vnew", "target_lane")])
+        ev["partner"] = np.empty(n, np.int32)
+        self._lib.orc_last_partner(self._h, _p(ev["partner"]))
         return ev
 
 

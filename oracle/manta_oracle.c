@@ -33,6 +33,14 @@
  * Parity pins: see tests/test_oracle_*.py (closed forms of Eq. (1), the
  * platoon equilibrium gap, Eq. (2) frequencies, Philox against numpy,
  * exp against libm, brute-force leader and admission checks, invariants).
+ * The crossing time inside a step (per-edge traversal times) is pinned by
+ * exact cruise kinematics (each traversal lasts L/v0), by first-order
+ * convergence to the closed-form free-road time from rest, and by a hold
+ * released at the stop line (crossing at the step start).  Phase 2's kind
+ * tree (VEH, FREE, STOP, LOOK with its partner from the start-of-step
+ * table), the integration with its clamp and wrong-lane hold, and the
+ * mandatory flag and wrong-lane wait are pinned by a plain re-derivation
+ * from S_t; the 60-step patience by a hand-built deadlock at a junction.
  * Lane-change behaviour and the admission policy follow readings of the
  * paper, which prints no values for them; they are pinned by brute-force
  * re-derivations of those readings in plain Python (leaders, Phase-1
@@ -1089,6 +1097,12 @@ void orc_last_events(const orc_sim *S, int32_t *leader, int32_t *kind, int32_t *
         vnew[i] = (double)S->vn[i];
         target_lane[i] = S->tgt[i];
     }
+}
+
+/* Phase-2 partner of the last step: the same-lane leader (VEH) or the rear
+ * of the look-ahead lane in the start-of-step table (LOOK), -1 otherwise */
+void orc_last_partner(const orc_sim *S, int32_t *partner) {
+    for (int i = 0; i < S->n; i++) partner[i] = S->ev_partner[i];
 }
 
 int32_t orc_real_bytes(void) { return (int32_t)sizeof(REAL); }
