@@ -3,21 +3,24 @@
 
 A "step" is one simulated time step (dt = 0.5 s) of the whole hot path:
 lane changes, leader search, IDM, integration, intersection admission and the
-rebuild of the sorted vehicle layout.  The default workload is the perturbed
-100x100 grid with a ring highway, 200,000 vehicles, timed over its full
-3-hour horizon (21,600 steps) from t = 0, with inputs already resident in
-device memory when the timed region starts.
+rebuild of the sorted vehicle layout.  The default workload is the
+metropolitan-scale network (about 224k nodes, 549k directed edges, 3.2M
+trips departing 05:00-10:00) timed at 08:00, the peak of its demand: the run
+is stepped untimed from 05:00 to 08:00, `--warmup` steps follow untimed, then
+`--steps` steps are timed, with every input resident in device memory.
 
 value = vehicle-updates/s = sum over the timed steps of the vehicles active at
 each step's start, divided by the device time of those steps (HIP events on
-the simulation's stream around sim_step, which replays one captured graph per
-step).  The same steps are then run again kernel by kernel between HIP
+the simulation's stream around sim_step, which replays captured graphs of 8
+steps).  The same window is then run again kernel by kernel between HIP
 events to time each kernel.  The roofline object covers k_tile_step, which
 does Phases 1-2 of every vehicle in a tile that fits one workgroup's LDS:
-algorithmic bytes = 48 B per vehicle-update it does (read and write of the
-24-byte sorted vehicle record; updates in larger tiles, done by k_big_admit,
-are counted by the library and left out), over its summed event-measured
-time.
+algorithmic bytes = 28 B per vehicle-update it does (read x, v, id and the
+packed lane/flags word, write x, v and that word; updates in larger tiles,
+done by k_big_admit, are counted by the library and left out), over its
+event-measured time.  The CPU baseline is the oracle on an 08:00 state built
+from the demand (which it can start from), on one thread and on every thread;
+the GPU runs the same steps from the same state and the two are compared.
 """
 import argparse
 import json
@@ -31,8 +34,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-BYTES_PER_UPDATE = 48
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_kernels_traffic_perturbed_grid_ring.json")
+BYTES_PER_UPDATE = 28      # read x, v, id, meta (16 B), write x, v, meta (12 B)
 
 
 def kernel_source_digest() -> str:
@@ -49,7 +51,7 @@ def kernel_source_digest() -> str:
 
 
 def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step",),
-                 probe_mib: int = 256) -> dict:
+                 probe_mib: int = 256, workload: str = "metro") -> dict:
     """HBM bytes per step of the tile kernel (launched once per step) from
     two --pmc summaries (FETCH_SIZE, WRITE_SIZE in KiB per dispatch),
     each counter scaled by what it reads for the copy probe (torch's add of
@@ -77,18 +79,22 @@ def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step",),
     kf, kw = per_kernel(f, "FETCH_SIZE"), per_kernel(w, "WRITE_SIZE")
     known = probe_mib * 1024.0
     fs, ws = known / pf, known / pw
-    return {"workload": "perturbed_grid_ring", "kernels": list(kernels), "sources": kernel_source_digest(),
+    return {"workload": workload, "kernels": list(kernels), "sources": kernel_source_digest(),
             "bytes_per_step": 1024.0 * sum(kf[k] * fs + kw[k] * ws for k in kernels),
             "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
             "probe": pname[:80], "probe_fetch_kib": pf, "probe_write_kib": pw,
             "fetch_scale": fs, "write_scale": ws}
 
 
-def stored_traffic(workload: str, v0_spread: float = 0.0, intersection_mode: int = 0,
-                   path: str = TRAFFIC_FILE):
+def traffic_file(workload: str) -> str:
+    return os.path.join(ROOT, "profiles", f"tile_kernels_traffic_{workload}.json")
+
+
+def stored_traffic(workload: str, v0_spread: float = 0.0, intersection_mode: int = 0, path: str = None):
     """HBM bytes per step of k_tile_step from the committed counter record, or
     None when there is no record or it was taken on other HIP sources, another
     workload or other options (its bytes then describe another kernel)."""
+    path = path or traffic_file(workload)
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -99,8 +105,17 @@ def stored_traffic(workload: str, v0_spread: float = 0.0, intersection_mode: int
     return None
 
 
+# step at which each plain workload is timed: 08:00, the morning peak of its demand
+PEAK_STEP = {"metro": 21600, "perturbed_grid_ring": 10800, "grid10x10": 600}
+# assumed mean speed, as a fraction of each edge's limit, of the vehicles placed
+# on their routes to build the 08:00 state the oracle starts from
+SPEED_FRAC = 0.4
+
+
 def make_workload(name: str):
     import workloads as W
+    if name == "metro":
+        return W.config3()
     if name == "perturbed_grid_ring":
         return W.config2()
     if name == "grid10x10":
@@ -108,16 +123,40 @@ def make_workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(w, steps: int):
-    """The oracle as it stands, single-threaded, on the first `steps` steps."""
+def cpu_info() -> dict:
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": usable}
+
+
+def cpu_baseline(w, state0, warmup: int, steps: int, threads: int):
+    """The oracle as it stands, from the same written state as the GPU run:
+    `warmup` untimed steps, then `steps` timed steps, with `threads` OpenMP
+    threads in its parallel phases.  Returns the figures and the oracle's
+    counters and state at the end (for the window's parity check)."""
     import oracle
+    used = oracle.set_threads(threads)
     s = oracle.OracleSim(w)
+    s.write_state(int(state0["t"]), state0)
+    s.step(warmup)
+    before = s.counters()["active_sum"]
     t0 = time.perf_counter()
     s.step(steps)
     dt = time.perf_counter() - t0
-    upd = s.counters()["active_sum"]
-    return {"value": upd / dt, "unit": "vehicle-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"steps 0-{steps} of the same workload ({upd} vehicle-updates, {dt:.1f} s)"}
+    upd = s.counters()["active_sum"] - before
+    return {"value": upd / dt, "unit": "vehicle-updates/s", "cores": used, "kind": "oracle",
+            "vehicle_updates": int(upd), "s": dt}, s.counters(), s.state()
 
 
 def summarize_pmc(directory: str) -> dict:
@@ -427,15 +466,18 @@ def bench_reroute(args, M, torch, stream):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=21600)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="perturbed_grid_ring",
-                    choices=["perturbed_grid_ring", "grid10x10", "ensemble", "calibration", "calibration_search",
-                             "metro_scale", "reroute"])
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--workload", default="metro",
+                    choices=["metro", "perturbed_grid_ring", "grid10x10", "ensemble", "calibration",
+                             "calibration_search", "metro_scale", "reroute"])
+    ap.add_argument("--start", type=int, default=-1,
+                    help="plain workloads: step of the written start state (default: 08:00, the demand peak)")
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
     ap.add_argument("--scenarios", type=int, default=64, help="ensemble: number of scenarios")
     ap.add_argument("--tune-at", type=int, default=3000, help="ensemble: step at which the schedule is tuned")
-    ap.add_argument("--cpu-steps", type=int, default=7200, help="oracle sample length (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=20,
+                    help="plain workloads: most steps the oracle times (0: skip); reroute: on if > 0")
     ap.add_argument("--intersection-mode", type=int, default=0, choices=[0, 1],
                     help="0: all green (case 2); 1: flashing red at every node (case 1)")
     ap.add_argument("--v0-spread", type=float, default=0.0,
@@ -457,7 +499,8 @@ def main():
         print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
         return
     if args.traffic_from:
-        print(json.dumps(traffic_from(*args.traffic_from, probe_mib=args.copy_probe or 256), indent=1))
+        print(json.dumps(traffic_from(*args.traffic_from, probe_mib=args.copy_probe or 256,
+                                      workload=args.workload), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the simulation is single-device; "
@@ -484,9 +527,73 @@ def main():
     if args.workload == "calibration_search":
         print(json.dumps(bench_calibration_search(args, M, torch, stream)), flush=True)
         return
+    print(json.dumps(bench_plain(args, M, torch, stream)), flush=True)
+
+
+def _window(sim, M, torch, stream, steps, progress, kernels_only):
+    """`steps` steps from the handle's current state, twice: on the graph path
+    between two HIP events, then (state restored) kernel by kernel between HIP
+    events.  Returns (graph ms or None, vehicle-updates, per-kernel ms, event
+    path ms, big-tile updates, state at the end)."""
+    start_state = sim.state()
+    before = int(start_state["counters"][0])
+    total_ms = None
+    if not kernels_only:                     # counter runs: the event-timed pass below is enough
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        if progress:                         # profiling runs only: these syncs cost time
+            for k0 in range(0, steps, progress):
+                sim.step(min(progress, steps - k0))
+                torch.cuda.synchronize()
+                print(f"graph path: step {k0 + min(progress, steps - k0)}", flush=True)
+        else:
+            sim.step(steps)                  # the production path: captured graphs of 8 steps
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms = e0.elapsed_time(e1)
+    end_state = sim.state()
+    upd = int(end_state["counters"][0]) - before
+    sim.write_state(start_state)
+    big0 = sim.big_tile_updates()
+    if progress:
+        kernel_ms, event_ms = None, 0.0
+        for k0 in range(0, steps, progress):
+            km, tm = sim.step_timed(min(progress, steps - k0))
+            kernel_ms = km if kernel_ms is None else {k: kernel_ms[k] + km[k] for k in km}
+            event_ms += tm
+            print(f"event path: step {k0 + min(progress, steps - k0)}", flush=True)
+    else:
+        kernel_ms, event_ms = sim.step_timed(steps)
+    upd_t = sim.counters()["active_sum"] - before
+    big = sim.big_tile_updates() - big0
+    if kernels_only:
+        upd, total_ms, end_state = upd_t, event_ms, sim.state()
+    assert upd_t == upd, (upd_t, upd)
+    return total_ms, upd, kernel_ms, event_ms, big, end_state
+
+
+def bench_plain(args, M, torch, stream):
+    """The plain step on one workload, timed at 08:00, the peak of its
+    demand.  The run starts at the workload's first step and is stepped
+    untimed on the graph path to 08:00 (setup); `warmup` steps follow untimed,
+    then `steps` steps are timed with HIP events on the handle's stream, and
+    the same window runs again kernel by kernel for per-kernel times.
+
+    The oracle cannot reach 08:00 of the metropolitan run in a bench's time,
+    so the CPU baseline and the parity check of a timed window start from the
+    08:00 state built from the demand (workloads.loaded_state), written into
+    both the oracle and a GPU handle: the oracle runs `warmup` + min(steps,
+    cpu_steps) steps on one thread and on every thread, and its counters and
+    end state are compared with the GPU's over the same steps."""
+    import workloads as W
+    t_setup = time.perf_counter()
     w = make_workload(args.workload)
     w.params.v0_spread = args.v0_spread
     w.params.intersection_mode = args.intersection_mode
+    start = PEAK_STEP[args.workload] if args.start < 0 else args.start
+    print(f"{args.workload}: {w.n_vehicles} vehicles, {w.net.n_edges} edges "
+          f"({time.perf_counter() - t_setup:.1f} s)", file=sys.stderr, flush=True)
     if args.copy_probe > 0:
         # a plain streaming kernel of known size: reads MIB MiB, writes MIB MiB
         # (torch's elementwise add; a device-to-device copy_ would use the DMA engine)
@@ -497,56 +604,25 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    # warm-up on its own handle (kernels, graph, caches), then a fresh handle
-    warm = M.Sim(w, stream=stream)
-    warm.step(args.warmup)
-    warm.close()
     sim = M.Sim(w, stream=stream)
-    before = sim.counters()["active_sum"]
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t_ff = time.perf_counter()
+    sim.step(start)                          # untimed: the run from its first step to 08:00
+    sim.step(args.warmup)
     torch.cuda.synchronize()
-    e0.record(stream)
-    if args.kernels_only:                # counter runs: the event-timed pass below is enough
-        pass
-    elif args.progress:                  # profiling runs only: these syncs cost time
-        for k0 in range(0, args.steps, args.progress):
-            sim.step(min(args.progress, args.steps - k0))
-            torch.cuda.synchronize()
-            print(f"graph path: step {k0 + min(args.progress, args.steps - k0)}", flush=True)
-    else:
-        sim.step(args.steps)             # the production path: one captured graph per step
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    upd = sim.counters()["active_sum"] - before
-    sim.close()
-
-    # the same steps again, kernel by kernel between HIP events on the same
-    # stream, for the duration of each kernel (results are identical)
-    timed = M.Sim(w, stream=stream)
-    torch.cuda.synchronize()
-    if args.progress:
-        kernel_ms, event_total_ms = None, 0.0
-        for k0 in range(0, args.steps, args.progress):
-            km, tm = timed.step_timed(min(args.progress, args.steps - k0))
-            kernel_ms = km if kernel_ms is None else {k: kernel_ms[k] + km[k] for k in km}
-            event_total_ms += tm
-            print(f"event path: step {k0 + min(args.progress, args.steps - k0)}", flush=True)
-    else:
-        kernel_ms, event_total_ms = timed.step_timed(args.steps)
-    if args.kernels_only:
-        upd = timed.counters()["active_sum"]
-        total_ms = event_total_ms
-    assert timed.counters()["active_sum"] == upd
-    big_upd = timed.big_tile_updates()
-    timed.close()
+    active0 = sim.n_active
+    print(f"run to step {start} + {args.warmup} warm-up steps: {active0} active "
+          f"({time.perf_counter() - t_ff:.1f} s)", file=sys.stderr, flush=True)
+    total_ms, upd, kernel_ms, event_ms, big_upd, _ = _window(sim, M, torch, stream, args.steps, args.progress,
+                                                               args.kernels_only)
     value = upd / (total_ms / 1e3)
 
-    # roofline of k_tile_step: the vehicle-updates it does (all but those in
-    # tiles above one workgroup's LDS) over its event-measured time
+    # roofline of k_tile_step: 28 algorithmic bytes per vehicle-update it does
+    # (all but those in tiles above one workgroup's LDS) over its event time
     tile_ms = kernel_ms["k_tile_step"]
     achieved = BYTES_PER_UPDATE * (upd - big_upd) / (tile_ms / 1e3) / 1e9
     traffic = stored_traffic(args.workload, args.v0_spread, args.intersection_mode)
+    clock0 = {"metro": 5.0, "perturbed_grid_ring": 6.5}.get(args.workload)
+    hh = None if clock0 is None else clock0 + start * 0.5 / 3600
     line = {
         "metric": "vehicle-updates/sec (1 GPU)",
         "value": value,
@@ -561,18 +637,49 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": args.workload, "vehicles": w.n_vehicles, "edges": w.net.n_edges,
-                   "lanes": int(w.net.lanes.sum()), "dt_s": 0.5, "steps": args.steps,
+                   "lanes": int(w.net.lanes.sum()), "dt_s": 0.5,
+                   "timed_from_step": start + args.warmup,
+                   **({"clock": f"{int(hh):02d}:{int(round(hh % 1 * 60)):02d}"} if hh is not None else {}),
+                   "active_at_timed_start": int(active0), "steps": args.steps,
                    "vehicle_updates": int(upd), **({"v0_spread": args.v0_spread} if args.v0_spread else {}),
                    **({"intersection_mode": 1} if args.intersection_mode else {})},
         "roofline": {"bound": "hbm", "kernel": "k_tile_step", "achieved": achieved,
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "us_per_launch": 1e3 * tile_ms / args.steps, "big_tile_updates": big_upd},
+                     "bytes_per_update": BYTES_PER_UPDATE, "us_per_launch": 1e3 * tile_ms / args.steps,
+                     "big_tile_updates": big_upd},
         "kernel_us_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in kernel_ms.items()},
-        "event_path_ms_per_step": event_total_ms / args.steps,
+        "event_path_ms_per_step": event_ms / args.steps,
     }
     if args.cpu_steps > 0:
-        line["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
-    print(json.dumps(line), flush=True)
+        k = min(args.steps, args.cpu_steps)
+        state0, info = W.loaded_state(w, start, speed_frac=SPEED_FRAC)
+        one, _, _ = cpu_baseline(w, state0, args.warmup, k, 1)
+        allc, oc, os_ = cpu_baseline(w, state0, args.warmup, k, 0)
+        sample = (f"{k} steps after {args.warmup} from the 08:00 state built from the demand "
+                  f"({info['active']} active, mean speed {SPEED_FRAC} x limit; "
+                  f"{allc['vehicle_updates']} vehicle-updates)")
+        line["cpu_baseline"] = {"value": allc["value"], "unit": "vehicle-updates/s", "cores": allc["cores"],
+                                "kind": "oracle", "sample": sample,
+                                "single_thread": {"value": one["value"], "cores": 1, "s": one["s"]},
+                                "all_threads_s": allc["s"], **cpu_info()}
+        # the same steps on the GPU from the same written state: its rate
+        # beside the oracle's, and the window's parity (counters exact,
+        # discrete state bit for bit, x and v within 1e-5 relative)
+        sim.write_state(dict(state0, counters=np.zeros(len(M.COUNTERS), np.int64)))
+        sim.step(args.warmup)
+        torch.cuda.synchronize()
+        g_ms, g_upd, _, _, _, g_end = _window(sim, M, torch, stream, k, 0, False)
+        gc = dict(zip(M.COUNTERS, g_end["counters"].tolist()))
+        same = all(np.array_equal(g_end[q], os_[q].astype(g_end[q].dtype))
+                   for q in ("status", "edge", "lane", "cursor", "held_since", "mand", "ww"))
+        rel = max(float(np.max(np.abs(g_end[q].astype(np.float64) - os_[q].astype(np.float64))
+                               / np.maximum(np.abs(os_[q].astype(np.float64)), 1.0), initial=0.0))
+                  for q in ("x", "v"))
+        line["built_state_window"] = {"gpu_value": g_upd / (g_ms / 1e3), "vehicle_updates": g_upd,
+                                      "counters_equal": gc == oc, "discrete_state_equal": bool(same),
+                                      "max_rel_xv": rel}
+    sim.close()
+    return line
 
 
 if __name__ == "__main__":

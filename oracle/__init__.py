@@ -32,7 +32,7 @@ EV = dict(REQ=1, WIN=2, ARRIVE=4, WHOLD=8, CLAMP=16, STOPB=32, ELIG=64, INSERT_R
           MOVED=256, MAND_TRIG=512)
 KIND = dict(FREE=0, VEH=1, STOP=2, LOOK=3)
 
-_CFLAGS = ["-O2", "-std=gnu99", "-fPIC", "-shared", "-ffp-contract=off", "-fno-fast-math",
+_CFLAGS = ["-O2", "-std=gnu99", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
            "-fno-unsafe-math-optimizations"]
 
 
@@ -59,12 +59,15 @@ def _load(path):
     lib.orc_time.argtypes = [P]
     lib.orc_time.restype = I32
     lib.orc_read_state.argtypes = [P] + [P] * 11
-    lib.orc_write_state.argtypes = [P, I32] + [P] * 10
+    lib.orc_write_state.argtypes = [P, I32] + [P] * 11
     lib.orc_counters.argtypes = [P, P]
     lib.orc_edge_stats.argtypes = [P, P, P]
     lib.orc_last_events.argtypes = [P] + [P] * 7
     lib.orc_last_partner.argtypes = [P, P]
     lib.orc_real_bytes.restype = I32
+    lib.orc_set_threads.argtypes = [I32]
+    lib.orc_set_threads.restype = I32
+    lib.orc_set_threads(1)          # one thread unless asked: test runners start many processes
     lib.orc_enable_record.argtypes = [P]
     lib.orc_enable_record.restype = I32
     lib.orc_replay.argtypes = [P, P, P, P, P, P]
@@ -169,7 +172,8 @@ class OracleSim:
         a = [_c(s["status"], np.uint8), _c(s["edge"], np.int32), _c(s["lane"], np.int32),
              _c(s["cursor"], np.int32), _c(s["x"], np.float64), _c(s["v"], np.float64),
              _c(s["held_since"], np.int32), _c(s["mand"], np.uint8), _c(s["ww"], np.int32),
-             _c(s["tau_in"], np.float64)]
+             _c(s["tau_in"], np.float64),
+             _c(s["t_arr"], np.float64) if s.get("t_arr") is not None else None]
         self._lib.orc_write_state(self._h, int(t), *[_p(q) for q in a])
 
     def counters(self) -> dict:
@@ -215,6 +219,23 @@ class OracleSim:
         ev["partner"] = np.empty(n, np.int32)
         self._lib.orc_last_partner(self._h, _p(ev["partner"]))
         return ev
+
+
+def all_threads() -> int:
+    """OMP_NUM_THREADS if set, else every CPU this process may run on."""
+    env = os.environ.get("OMP_NUM_THREADS", "")
+    if env.isdigit() and int(env) > 0:
+        return int(env)
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def set_threads(n: int = 1, fp64: bool = False) -> int:
+    """Threads of the oracle's parallel phases (the library starts with one;
+    n <= 0: all_threads()); returns the count in use."""
+    return int(lib(fp64).orc_set_threads(int(n) if n > 0 else all_threads()))
 
 
 # ---------------------------------------------------------------- scalar hooks for pins

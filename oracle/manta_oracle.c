@@ -9,6 +9,10 @@
  *
  * It is deliberately plain: per-lane vehicle lists rebuilt by bucket + insertion
  * sort every phase, brute-force admission, one vehicle at a time in id order.
+ * Phases 1 and 2 decide each vehicle from S_t alone and write only that
+ * vehicle's entries, so built with OpenMP they run over vehicles in parallel;
+ * their event counts are integer sums, so every thread count gives the same
+ * result bit for bit.  Everything else runs in id order on one thread.
  *
  * Precision.  The paper fixes none.  Compiled with REAL=float (default) it is
  * the parity oracle: every FP32 operation in the order written below, no
@@ -50,6 +54,9 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 
 #ifndef REAL
 #define REAL float
@@ -476,6 +483,8 @@ static void step_once(orc_sim *S) {
      * step go the same direction (A15), so checking both gaps >= 0 against the
      * S_t neighbours keeps the post-change lanes free of overlap. */
     const int dir = (t % 2 == 0) ? -1 : +1;
+    int64_t n_mand = 0, n_lc = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : n_mand, n_lc)
     for (int i = 0; i < n; i++) {
         S->nlane[i] = S->lane[i];
         if (S->status[i] != ACTIVE || S->held[i] >= 0) continue;
@@ -485,12 +494,12 @@ static void step_once(orc_sim *S) {
         if (!allowed_l && !S->mand[i]) {
             REAL d = S->L[e] - S->x[i];
             if (d <= RL(X0)) {
-                S->mand[i] = 1; S->cnt[C_MAND_TRIGGERS]++; S->ev_flags[i] |= EV_MAND_TRIG;
+                S->mand[i] = 1; n_mand++; S->ev_flags[i] |= EV_MAND_TRIG;
             } else {
                 REAL dm = d - RL(X0);
                 REAL z = dm * dm;
                 if (z < RL(Z_CUT) && orc_uniform(S->seed, t, i, 1) < (REAL)ORC_EXP(-z)) {
-                    S->mand[i] = 1; S->cnt[C_MAND_TRIGGERS]++; S->ev_flags[i] |= EV_MAND_TRIG;
+                    S->mand[i] = 1; n_mand++; S->ev_flags[i] |= EV_MAND_TRIG;
                 }
             }
         }
@@ -552,9 +561,11 @@ static void step_once(orc_sim *S) {
         if (!ok) continue;
         S->nlane[i] = lp;
         S->ev_flags[i] |= EV_MOVED;
-        S->cnt[C_LANE_CHANGES]++;
+        n_lc++;
         if (allowed_lp) { S->mand[i] = 0; S->ww[i] = 0; }
     }
+    S->cnt[C_MAND_TRIGGERS] += n_mand;
+    S->cnt[C_LANE_CHANGES] += n_lc;
 
     /* M_t rears (pre-change lanes) are needed for look-ahead: keep them */
     int *mrear = (int *)malloc((size_t)(S->n_lanes_total > 0 ? S->n_lanes_total : 1) * sizeof(int));
@@ -563,6 +574,8 @@ static void step_once(orc_sim *S) {
 
     /* ---- Phase 2: leader on the post-change lane, Eq. (1), integration */
     build_lanes(S, S->nlane, S->x);
+    int64_t n_stopb = 0, n_clamp = 0, n_whold = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : n_stopb, n_clamp, n_whold)
     for (int i = 0; i < n; i++) {
         if (S->status[i] != ACTIVE) continue;
         const int e = S->edge[i], l = S->nlane[i], f = next_edge(S, i), c = S->cls[i];
@@ -611,14 +624,14 @@ static void step_once(orc_sim *S) {
         } else {
             xnew = S->x[i] - ((S->v[i] * S->v[i]) / (RL(2.0) * acc));
             vnew = RL(0);
-            S->cnt[C_STOP_BRANCH]++;
+            n_stopb++;
             S->ev_flags[i] |= EV_STOPB;
             S->ev_bits[i] |= RB_B;
         }
         /* A7: never past the leader's S_t rear */
         if (kind == K_VEH) {
             REAL rear = S->x[j] - S->len[S->cls[j]];
-            if (xnew > rear) { xnew = rear; S->cnt[C_CLAMP]++; S->ev_flags[i] |= EV_CLAMP; S->ev_bits[i] |= RB_C; }
+            if (xnew > rear) { xnew = rear; n_clamp++; S->ev_flags[i] |= EV_CLAMP; S->ev_bits[i] |= RB_C; }
         }
         /* A8/A19: a wrong-lane vehicle waits at the stop line */
         if (f >= 0 && !allowed_l && S->ww[i] < PATIENCE && xnew >= S->L[e]) {
@@ -626,13 +639,16 @@ static void step_once(orc_sim *S) {
             vnew = RL(0);
             S->mand[i] = 1;
             S->ww[i] += 1;
-            S->cnt[C_WRONG_LANE_HOLDS]++;
+            n_whold++;
             S->ev_flags[i] |= EV_WHOLD;
             S->ev_bits[i] |= RB_W;
         }
         S->xn[i] = xnew;
         S->vn[i] = vnew;
     }
+    S->cnt[C_STOP_BRANCH] += n_stopb;
+    S->cnt[C_CLAMP] += n_clamp;
+    S->cnt[C_WRONG_LANE_HOLDS] += n_whold;
     free(mrear);
 
     /* ---- Phase 3: end of edge and admission (case 2 intersections, A16-A18).
@@ -1052,7 +1068,7 @@ void orc_read_state(const orc_sim *S, uint8_t *status, int32_t *edge, int32_t *l
 void orc_write_state(orc_sim *S, int32_t t, const uint8_t *status, const int32_t *edge,
                      const int32_t *lane, const int32_t *cursor, const double *x, const double *v,
                      const int32_t *held_since, const uint8_t *mand, const int32_t *ww,
-                     const double *tau_in) {
+                     const double *tau_in, const double *t_arr) {
     S->t = t;
     for (int i = 0; i < S->n; i++) {
         S->status[i] = status[i];
@@ -1069,6 +1085,7 @@ void orc_write_state(orc_sim *S, int32_t t, const uint8_t *status, const int32_t
         S->mand[i] = mand[i];
         S->ww[i] = ww[i];
         S->tau_in[i] = tau_in[i];
+        if (t_arr) S->t_arr[i] = t_arr[i];
     }
     if (S->rr)
         for (int v = 0; v < S->n_nodes; v++) S->rr[v] = -1;   /* the round-robin restarts */
@@ -1106,6 +1123,18 @@ void orc_last_partner(const orc_sim *S, int32_t *partner) {
 }
 
 int32_t orc_real_bytes(void) { return (int32_t)sizeof(REAL); }
+
+/* threads of the parallel phases (0: leave the OpenMP default); returns the
+ * count in use, 1 in a build without OpenMP */
+int32_t orc_set_threads(int32_t n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+    return (int32_t)omp_get_max_threads();
+#else
+    (void)n;
+    return 1;
+#endif
+}
 
 /* Eq. (2) trigger test hook: does the draw at (t, id) fire at distance d? */
 int32_t orc_mand_trigger(uint64_t seed, int64_t t, int64_t id, double d_in) {

@@ -1,5 +1,6 @@
-"""Writes oracle_snapshots.json: the CPU oracle's state at a few steps of two
-seeded 10x10-grid runs, as frozen expected values.
+"""Writes oracle_snapshots.json: the CPU oracle's state at a few steps of
+three seeded runs (two on the 10x10 grid, one on the full-size perturbed grid
+with ring highway through its morning peak), as frozen expected values.
 
 Every number in the file comes from ``oracle/`` run on inputs from the seeded
 generators in ``workloads/`` (which hold none of the step's arithmetic).  The
@@ -50,11 +51,19 @@ def case_workload(name: str):
         w.params.v0_spread = 0.05
         w.params.intersection_mode = 1
         return w
+    if name == "perturbed_grid_ring_peak":
+        return W.config2()
     raise KeyError(name)
 
 
+# checkpoints per case; config 2 at 07:45 and 08:00 (its departures peak at
+# 08:00, about 110,000 vehicles active)
 CASES = {"grid10x10_case2": [300, 1200, 3600],
-         "grid10x10_case1_4classes_spread": [600, 1200, 2400]}
+         "grid10x10_case1_4classes_spread": [600, 1200, 2400],
+         "perturbed_grid_ring_peak": [9900, 10800]}
+# cases whose run is long: the oracle uses every thread for them (the result
+# does not depend on the thread count)
+LONG = ("perturbed_grid_ring_peak",)
 
 
 def state_digest(s: dict, fields) -> str:
@@ -66,8 +75,13 @@ def state_digest(s: dict, fields) -> str:
     return h.hexdigest()
 
 
-def sample_ids(n: int) -> list:
-    return np.random.default_rng(20070361).choice(n, N_SAMPLE, replace=False).tolist()
+def sample_ids(n: int, k: int = N_SAMPLE) -> list:
+    return np.random.default_rng(20070361).choice(n, k, replace=False).tolist()
+
+
+def case_sample_ids(name: str, n: int) -> list:
+    """The sampled vehicles of a case: 16, or 64 on the large network."""
+    return sample_ids(n, 64 if name in LONG else N_SAMPLE)
 
 
 def snapshot(s: dict, counters: dict, ids: list) -> dict:
@@ -86,12 +100,13 @@ def snapshot(s: dict, counters: dict, ids: list) -> dict:
 def main() -> None:
     import oracle
     oracle.build()
-    out = {"about": "CPU oracle (binary32 build) state of two seeded 10x10-grid runs; "
+    out = {"about": "CPU oracle (binary32 build) state of three seeded runs; "
                     "written by make_oracle_snapshots.py; floats as C99 hex", "row": list(ROW), "cases": {}}
     for name, cps in CASES.items():
         w = case_workload(name)
+        oracle.set_threads(0 if name in LONG else 1)
         sim = oracle.OracleSim(w)
-        ids = sample_ids(w.n_vehicles)
+        ids = case_sample_ids(name, w.n_vehicles)
         snaps, t = [], 0
         for cp in cps:
             sim.step(cp - t)

@@ -65,16 +65,24 @@ def test_stored_traffic_needs_the_same_sources_and_workload(tmp_path):
     assert bench.stored_traffic("perturbed_grid_ring", path=str(tmp_path / "missing.json")) is None
 
 
-def test_committed_record_is_well_formed():
-    """The committed record: counters of k_tile_step on the default workload,
-    probe scales near what a plain add reads and writes, and measured bytes at
-    least the algorithmic 48 B per vehicle-update of a config-2 step."""
-    with open(bench.TRAFFIC_FILE) as f:
-        tr = json.load(f)
-    assert tr["workload"] == "perturbed_grid_ring" and tr["kernels"] == ["k_tile_step"]
-    assert len(tr["sources"]) == 16
-    assert 0.9 <= tr["write_scale"] <= 1.1 and 0.9 <= tr["fetch_scale"] / 2.0 <= 1.1
-    assert tr["bytes_per_step"] == pytest.approx(
-        1024.0 * (tr["fetch_kib_per_dispatch"]["k_tile_step"] * tr["fetch_scale"]
-                  + tr["write_kib_per_dispatch"]["k_tile_step"] * tr["write_scale"]), rel=1e-12)
-    assert tr["bytes_per_step"] > 3.0e6
+def test_committed_records_are_well_formed():
+    """Each committed record: counters of k_tile_step on the workload its file
+    is named for, probe scales near what a plain add reads and writes, and
+    bytes per step that follow from the two counters and their scales."""
+    import glob
+    files = glob.glob(os.path.join(ROOT, "profiles", "tile_kernels_traffic_*.json"))
+    for fn in files:
+        with open(fn) as f:
+            tr = json.load(f)
+        assert fn == bench.traffic_file(tr["workload"]) and tr["kernels"] == ["k_tile_step"]
+        assert len(tr["sources"]) == 16
+        assert 0.9 <= tr["write_scale"] <= 1.1 and 0.9 <= tr["fetch_scale"] / 2.0 <= 1.1
+        assert tr["bytes_per_step"] == pytest.approx(
+            1024.0 * (tr["fetch_kib_per_dispatch"]["k_tile_step"] * tr["fetch_scale"]
+                      + tr["write_kib_per_dispatch"]["k_tile_step"] * tr["write_scale"]), rel=1e-12)
+        assert tr["bytes_per_step"] > 0.0
+
+
+def test_cpu_info_names_the_host():
+    info = bench.cpu_info()
+    assert info["nproc"] >= 1 and isinstance(info["cpu_model"], str)

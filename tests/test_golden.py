@@ -5,9 +5,9 @@
   bounds and schedule, the 2 s stop of case 1), each with its citation.  The
   tests check them through what the oracle, the seeded workloads and the
   calibration module do, not by re-reading their source constants.
-* oracle_snapshots.json: the oracle's state at a few steps of two seeded runs,
-  written by make_oracle_snapshots.py (which calls only the oracle).  The
-  oracle must reproduce it bit for bit."""
+* oracle_snapshots.json: the oracle's state at a few steps of three seeded
+  runs, written by make_oracle_snapshots.py (which calls only the oracle).
+  The oracle must reproduce it bit for bit."""
 import importlib.util
 import json
 import math
@@ -145,27 +145,37 @@ def test_case1_stop_duration(oracle_mod):
     assert c["arrived"] == 1 and c["holds"] == hops * math.ceil(C["stop_s"] / C["dt_s"])
 
 
-@pytest.mark.parametrize("case", ["grid10x10_case2", "grid10x10_case1_4classes_spread"])
+@pytest.mark.parametrize("case", ["grid10x10_case2", "grid10x10_case1_4classes_spread",
+                                  "perturbed_grid_ring_peak"])
 def test_oracle_reproduces_snapshots(oracle_mod, case):
     m = snapshot_module()
     snap = load_snapshots()
     assert snap["row"] == list(m.ROW)
+    assert set(snap["cases"]) == set(m.CASES)
     rec = snap["cases"][case]
     w = m.case_workload(case)
     assert w.n_vehicles == rec["n_vehicles"]
-    sim = oracle_mod.OracleSim(w)
-    ids = m.sample_ids(w.n_vehicles)
-    t = 0
-    for cp in rec["checkpoints"]:
-        sim.step(cp["t"] - t)
-        t = cp["t"]
-        got = m.snapshot(sim.state(), sim.counters(), ids)
-        assert got["counters"] == cp["counters"], t
-        assert got["vehicles"] == cp["vehicles"], t
-        assert got["digest"] == cp["digest"] and got["digest_times"] == cp["digest_times"], t
+    oracle_mod.set_threads(0 if case in m.LONG else 1)
+    try:
+        sim = oracle_mod.OracleSim(w)
+        ids = m.case_sample_ids(case, w.n_vehicles)
+        t = 0
+        for cp in rec["checkpoints"]:
+            sim.step(cp["t"] - t)
+            t = cp["t"]
+            got = m.snapshot(sim.state(), sim.counters(), ids)
+            assert got["counters"] == cp["counters"], t
+            assert got["vehicles"] == cp["vehicles"], t
+            assert got["digest"] == cp["digest"] and got["digest_times"] == cp["digest_times"], t
+    finally:
+        oracle_mod.set_threads(1)
+    last = rec["checkpoints"][-1]["counters"]
+    if case in m.LONG:
+        # the morning peak: tens of thousands of vehicles on the road
+        assert last["departed"] - last["arrived"] > 50_000
+        return
     # the runs cover what they are meant to: every vehicle arrives; under
     # case 1 each crossing follows at least ceil(2 s / dt) holds
-    last = rec["checkpoints"][-1]["counters"]
     assert last["departed"] == last["arrived"] == rec["n_vehicles"]
     stop = math.ceil(C["stop_s"] / C["dt_s"])
     if "case1" in case:

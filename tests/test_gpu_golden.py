@@ -1,5 +1,6 @@
 """The HIP path against the stored oracle snapshots (tests/golden/): the same
-two seeded 10x10-grid runs (case 2; case 1 with 4 classes and a v0 spread),
+seeded runs (10x10 grid in case 2; case 1 with 4 classes and a v0 spread;
+the full-size perturbed grid with ring highway through its 08:00 peak),
 stepped through the C ABI with the graph launches the bench uses.  Counters
 and discrete state bit-exact; x and v bitwise (the binary32 contract, whole
 state through its digest); entry and arrival times within 1e-9."""
@@ -19,12 +20,13 @@ def M():
     return M
 
 
-@pytest.mark.parametrize("case", ["grid10x10_case2", "grid10x10_case1_4classes_spread"])
+@pytest.mark.parametrize("case", ["grid10x10_case2", "grid10x10_case1_4classes_spread",
+                                  "perturbed_grid_ring_peak"])
 def test_gpu_matches_stored_oracle_snapshots(M, case):
     m = snapshot_module()
     rec = load_snapshots()["cases"][case]
     w = m.case_workload(case)
-    ids = m.sample_ids(w.n_vehicles)
+    ids = m.case_sample_ids(case, w.n_vehicles)
     sim = M.Sim(w)
     n_f = 1 + len(m.INT_FIELDS) + len(m.F32_FIELDS)
     t = 0
