@@ -606,7 +606,14 @@ def bench_plain(args, M, torch, stream):
 
     sim = M.Sim(w, stream=stream)
     t_ff = time.perf_counter()
-    sim.step(start)                          # untimed: the run from its first step to 08:00
+    done = 0
+    while done < start:                      # untimed: the run from its first step to 08:00
+        k = min(2400, start - done)
+        sim.step(k)
+        done += k
+        if args.progress:
+            torch.cuda.synchronize()
+            print(f"run to 08:00: step {done}", flush=True)
     sim.step(args.warmup)
     torch.cuda.synchronize()
     active0 = sim.n_active
