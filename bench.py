@@ -186,6 +186,32 @@ def summarize_pmc(directory: str) -> dict:
     return {"files": len(files), "kernels": out}
 
 
+def summarize_trace(directory: str, last: int = 0) -> dict:
+    """Per-kernel dispatch counts and mean durations (us) from a `rocprofv3
+    --kernel-trace --output-format csv` directory, over every dispatch and
+    over the last `last` dispatches of each kernel (the timed window of a run
+    that is first stepped untimed to its start)."""
+    import csv
+    import glob
+    files = glob.glob(os.path.join(directory, "**", "*kernel_trace.csv"), recursive=True)
+    per = {}
+    for fn in files:
+        with open(fn, newline="") as f:
+            for row in csv.DictReader(f):
+                name = row.get("Kernel_Name", "?")
+                per.setdefault(name, []).append((int(row["Start_Timestamp"]), int(row["End_Timestamp"])))
+    out = {}
+    for name, ev in per.items():
+        ev.sort()
+        dur = [(b - a) / 1e3 for a, b in ev]
+        k = {"dispatches": len(dur), "mean_us": sum(dur) / len(dur)}
+        if last > 0:
+            tail = dur[-last:]
+            k[f"mean_us_last_{len(tail)}"] = sum(tail) / len(tail)
+        out[name] = k
+    return {"files": len(files), "kernels": out}
+
+
 def bench_ensemble(args, M, torch, stream):
     """64 what-if scenarios on the 10x10 grid (demand U[0.8, 1.2] x 200,000 of
     a 240,000 master list, 1 % of edges cut to one lane each), 2 h: one
@@ -491,12 +517,19 @@ def main():
                     help="run one plain device copy of this many MiB before the timed region "
                          "(a known-size reference for hardware byte counters)")
     ap.add_argument("--summarize-pmc", metavar="DIR", help="summarize a rocprofv3 --pmc csv directory and exit")
+    ap.add_argument("--summarize-trace", metavar="DIR",
+                    help="summarize a rocprofv3 --kernel-trace csv directory (see --last) and exit")
+    ap.add_argument("--last", type=int, default=0, help="--summarize-trace: also the mean of each kernel's "
+                                                         "last LAST dispatches")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_JSON", "WRITE_JSON"),
                     help="combine two --summarize-pmc outputs into the traffic record and exit")
     args = ap.parse_args()
     args.steps_given = "--steps" in sys.argv
     if args.summarize_pmc:
         print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
+        return
+    if args.summarize_trace:
+        print(json.dumps(summarize_trace(args.summarize_trace, args.last), indent=1))
         return
     if args.traffic_from:
         print(json.dumps(traffic_from(*args.traffic_from, probe_mib=args.copy_probe or 256,

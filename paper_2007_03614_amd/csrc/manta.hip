@@ -455,6 +455,12 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.lim = h->upload(net->speed_limit_mps, E);
             d.lanes = h->upload(h->lanes.data(), E);
             d.lane_base = h->upload(h->lane_base.data(), E + 1);
+            {
+                std::vector<EdgeC> ec(std::max(E, 1));
+                for (int e = 0; e < E; ++e)
+                    ec[e] = EdgeC{net->length_m[e], net->speed_limit_mps[e], h->lane_base[e], h->lanes[e]};
+                d.ec = h->upload(ec.data(), ec.size());
+            }
             // ---- classes (den = 2 sqrt(ab), rounded once in binary32)
             std::vector<ClassParams> cp(16);
             h->len_c.assign(p->n_classes, 0.f);
@@ -559,6 +565,21 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             std::vector<uint32_t> rid(N);
             for (int i = 0; i < N; ++i) rid[i] = rng_id ? rng_id[i] : (uint32_t)i;
             d.rid = h->upload(rid.data(), N);
+            {   // the tile kernels compute a draw id as vehicle id - first vehicle of its scenario
+                const int np = d.edge_period;
+                const int ns = std::max(1, (E + np - 1) / np);
+                std::vector<int> voff(ns + 1, INT_MAX);
+                for (int i = 0; i < N; ++i) {
+                    const int k = h->redges[h->roff[i]] / np;
+                    voff[k] = std::min(voff[k], i);
+                }
+                for (int k = 0; k <= ns; ++k)
+                    if (voff[k] == INT_MAX) voff[k] = 0;
+                for (int i = 0; i < N; ++i)
+                    if (rid[i] != (uint32_t)(i - voff[h->redges[h->roff[i]] / np]))
+                        throw Fail{SIM_EUNSUPPORTED, "draw ids are not consecutive within a scenario"};
+                d.scen_voff = h->upload(voff.data(), voff.size());
+            }
             // ---- capacity of the largest edge (vehicles never overlap)
             long long max_edge = 1;
             for (int e = 0; e < E; ++e)
@@ -611,6 +632,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.rear = h->dev<LaneRear>(NL);
             d.post = h->dev<LanePost>(NL);
             d.outbox = h->dev<Outbox>(NL);
+            d.req_stamp = h->dev<int>(NL);
             d.win = h->dev<unsigned long long>(NL);
             d.exit_stamp = h->dev<int>(NL);
             d.enter_stamp = h->dev<int>(NL);
@@ -629,6 +651,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             HIP_OK(hipMemset(d.rear, 0xFF, sizeof(LaneRear) * NL));
             HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * NL));
             HIP_OK(hipMemset(d.outbox, 0xFF, sizeof(Outbox) * NL));
+            HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * NL));
             HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
@@ -941,6 +964,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         HIP_OK(hipMemcpy(d.rear, rear.data(), sizeof(LaneRear) * h->n_lanes, hipMemcpyHostToDevice));
         HIP_OK(hipMemset(d.post, 0xFF, sizeof(LanePost) * h->n_lanes));
         HIP_OK(hipMemset(d.outbox, 0xFF, sizeof(Outbox) * h->n_lanes));
+        HIP_OK(hipMemset(d.req_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * h->n_lanes));
         HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));

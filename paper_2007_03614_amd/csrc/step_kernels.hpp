@@ -36,9 +36,9 @@ constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parame
 constexpr int kTileCapLds = 384;         // tiles up to this size are staged in LDS (4 workgroups per CU)
 constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
-constexpr int kCommitLanes = 8;         // threads per edge in k_commit (an edge has at most 8 lanes)
+constexpr int kCommitLanes = 8;         // lanes of an edge at most
 constexpr int kCommitNT = 256;           // threads per commit workgroup
-constexpr int kEdgeBlock = kCommitNT / kCommitLanes;   // edges per commit workgroup
+constexpr int kEdgeBlock = kCommitNT;    // edges per commit workgroup (one thread per edge)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
 constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
 constexpr unsigned long long kBarrierTimeout = 20000000ull;   // 0.2 s of the 100 MHz clock
@@ -158,6 +158,15 @@ struct EntryRec {
     int pad;
 };
 
+// The constants of one edge in one 16-byte record: a vehicle's edge and its
+// next edge cost one load each in the tile kernel.
+struct EdgeC {
+    float L;          // length, m
+    float lim;        // speed limit, m/s
+    int lane_base;    // first global lane
+    int lanes;
+};
+
 struct Dev {
     Ctl* ctl;
     unsigned long long* counters;
@@ -167,6 +176,7 @@ struct Dev {
     const float* lim;
     const int* lanes;
     const int* lane_base;
+    const EdgeC* ec;            // the four above, packed per edge
     // vehicles (static)
     int n_veh;
     const int64_t* roff;
@@ -186,6 +196,7 @@ struct Dev {
                                 //   its departure step}
     int nq;
     const uint32_t* rid;        // id used in the random-number counter
+    const int* scen_voff;       // first vehicle of each scenario (the id of the draws is the id within it)
     int max_dep;
     const ClassParams* cp;
     float dt;
@@ -217,6 +228,7 @@ struct Dev {
     LaneRear* rear;
     LanePost* post;
     Outbox* outbox;
+    int* req_stamp;             // the step in which the lane's front last wrote its Outbox
     unsigned long long* win;
     int* exit_stamp;
     int* enter_stamp;
@@ -274,11 +286,9 @@ struct TileBuf {
     uint32_t* lanes2;   // lanes of the edge | lanes of the next edge << 8
     int* lbe;           // first global lane of the edge
     int* lbf;           // first global lane of the next edge (0 if none)
-    float* alpha;       // anticipation time of the vehicle (Eqs. (3)-(4))
-    uint32_t* rid;      // counter id of its draws
 };
 
-constexpr int kTileBytesPerVeh = 100;  // 25 four-byte arrays (plus a few words within the 64-byte slack)
+constexpr int kTileBytesPerVeh = 92;   // 23 four-byte arrays (plus a few words within the 64-byte slack)
 __host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * kTileBytesPerVeh + 64; }
 
 __device__ inline TileBuf carve(char* base, int cap) {
@@ -309,8 +319,6 @@ __device__ inline TileBuf carve(char* base, int cap) {
     b.lanes2 = (uint32_t*)take(cap);
     b.lbe = (int*)take(cap);
     b.lbf = (int*)take(cap);
-    b.alpha = (float*)take(cap);
-    b.rid = (uint32_t*)take(cap);
     return b;
 }
 
@@ -509,15 +517,22 @@ __device__ inline void draw_task(const DrawQ& dq, int round, uint32_t rid, int q
     else atomicAdd(&slot[q], (int)philox_words(seed, t, rid, stream, blk));
 }
 
+// The counter id of a vehicle's draws: its id within its scenario (the
+// scenario of an ensemble member is its edge's copy of the network).
+__device__ inline uint32_t draw_id(const Dev& d, uint32_t vid, int e) {
+    return vid - (uint32_t)d.scen_voff[e / d.edge_period];
+}
+
 template <int NT>
-__device__ inline void draw_run(const DrawQ& dq, int round, uint64_t seed, int t, const uint32_t* rid, int* u1,
+__device__ inline void draw_run(const Dev& d, const DrawQ& dq, int round, int t, const TileBuf& b, int* u1,
                                 int* na, int* nb) {
     const int nt = min(dq.n[round], dq.cap);
     for (int i = threadIdx.x; i < nt; i += NT) {
         const uint32_t tk = dq.task[i];
         const int q = (int)(tk >> 4), st = (int)((tk >> 2) & 3u), blk = (int)(tk & 3u);
         int* slot = st == 1 ? u1 : (st == 2 ? na : nb);
-        atomicAdd(&slot[q], (int)philox_words(seed, t, rid[q], st, blk));
+        const uint32_t rid = draw_id(d, b.vid[q], (int)(b.el[q] >> 4));
+        atomicAdd(&slot[q], (int)philox_words(d.seed, t, rid, st, blk));
     }
 }
 
@@ -602,17 +617,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.el[q] = ((uint32_t)e << 4) | (uint32_t)m_lane(m);
         b.meta[q] = m;
         b.nxt[q] = f;
-        const float L = d.L[e];
+        const EdgeC ce = d.ec[e];
+        const EdgeC cf = f >= 0 ? d.ec[f] : EdgeC{0.0f, 0.0f, 0, 0};
+        const float L = ce.L;
         b.L[q] = L;
-        const float lim = d.lim[e];
-        b.lbe[q] = d.lane_base[e];
-        b.lanes2[q] = (uint32_t)d.lanes[e] | ((f >= 0 ? (uint32_t)d.lanes[f] : 0u) << 8);
-        b.lbf[q] = f >= 0 ? d.lane_base[f] : 0;
-        const uint32_t id = S.vid[s];
-        b.alpha[q] = d.alpha[id];
-        const uint32_t rid = d.rid[id];
-        b.rid[q] = rid;
-        b.lim[q] = lim;
+        b.lbe[q] = ce.lane_base;
+        b.lanes2[q] = (uint32_t)ce.lanes | ((uint32_t)cf.lanes << 8);
+        b.lbf[q] = cf.lane_base;
+        b.lim[q] = ce.lim;
         u1[q] = 0;
         na[q] = 0;
         nb[q] = 0;
@@ -620,15 +632,17 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             const float dd = L - x;
             if (dd > kX0) {
                 const float dm = dd - kX0;
-                if (dm * dm < kZCut) draw_task(dq, 0, rid, q, 1, 0, u1, d.seed, t);
+                if (dm * dm < kZCut) draw_task(dq, 0, draw_id(d, b.vid[q], e), q, 1, 0, u1, d.seed, t);
             }
         }
     }
     __syncthreads();
-    draw_run<NT>(dq, 0, d.seed, t, b.rid, u1, na, nb);
+    draw_run<NT>(d, dq, 0, t, b, u1, na, nb);
     if (kSpread && d.v0_spread != 0.0f)   // each driver's own limit on its edge (Sec. IV)
-        for (int q = tid; q < n; q += NT)
-            b.lim[q] = driver_limit(b.lim[q], d.v0_spread, d.seed, (int)(b.el[q] >> 4), d.edge_period, b.rid[q]);
+        for (int q = tid; q < n; q += NT) {
+            const int e = (int)(b.el[q] >> 4);
+            b.lim[q] = driver_limit(b.lim[q], d.v0_spread, d.seed, e, d.edge_period, draw_id(d, b.vid[q], e));
+        }
 
     // ---- runs of S_t (tile order: edge, lane, then x and id descending)
     {
@@ -718,18 +732,21 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 }
                 if (desire) {                                            // Eqs. (3)-(4)
                     const float g0 = desired_gap(vi);
-                    const float ai = b.alpha[q];
+                    // anticipation times, loaded only by the vehicles that get here
+                    const float ai = d.alpha[b.vid[q]];
+                    const float a_la = la >= 0 ? d.alpha[b.vid[la]] : 0.0f;
+                    const float a_lb = lb >= 0 ? d.alpha[b.vid[lb]] : 0.0f;
                     int ra = kGapYes, rb = kGapYes;
                     if (la >= 0) {
                         const float G = (b.x[la] - scp[m_cls(b.meta[la])].len) - xi;
-                        const float c = crit_gap(g0, b.alpha[la], vi, ai, b.v[la]);
+                        const float c = crit_gap(g0, a_la, vi, ai, b.v[la]);
                         ra = gap_outcome(G, c);
                         Ga[q] = G;
                         ca[q] = c;
                     }
                     if (lb >= 0) {
                         const float G = (xi - cpi.len) - b.x[lb];
-                        const float c = crit_gap(g0, ai, vi, b.alpha[lb], b.v[lb]);
+                        const float c = crit_gap(g0, ai, vi, a_lb, b.v[lb]);
                         rb = gap_outcome(G, c);
                         Gb[q] = G;
                         cb[q] = c;
@@ -741,9 +758,10 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                             if (allowed_lp) m &= ~((1u << 4) | (127u << 8));   // mand = 0, ww = 0
                         } else {                                 // decided by the noise
                             moved = kPending | (ra == kGapDraw ? kDrawA : 0) | (rb == kGapDraw ? kDrawB : 0);
+                            const uint32_t rid = draw_id(d, b.vid[q], (int)(el >> 4));
                             for (int k = 0; k < 3; ++k) {
-                                if (ra == kGapDraw) draw_task(dq, 1, b.rid[q], q, 2, k, na, d.seed, t);
-                                if (rb == kGapDraw) draw_task(dq, 1, b.rid[q], q, 3, k, nb, d.seed, t);
+                                if (ra == kGapDraw) draw_task(dq, 1, rid, q, 2, k, na, d.seed, t);
+                                if (rb == kGapDraw) draw_task(dq, 1, rid, q, 3, k, nb, d.seed, t);
                             }
                         }
                     }
@@ -757,7 +775,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         b.meta[q] = m;
     }
     __syncthreads();
-    draw_run<NT>(dq, 1, d.seed, t, b.rid, u1, na, nb);
+    draw_run<NT>(d, dq, 1, t, b, u1, na, nb);
     __syncthreads();
     if (tid < 2) dq.n[tid] = 0;   // lists of the next tile (several barriers away)
 
@@ -990,6 +1008,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                         ob.key = ((unsigned long long)(uint32_t)hs << 32) | ob.vid;
                     }
                     d.outbox[gl] = ob;
+                    d.req_stamp[gl] = t;
                 }
             }
         }
@@ -1175,8 +1194,9 @@ __device__ inline void admit_items(const Dev& d, int t) {
     const int total = nl + d.nq;
     for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
         if (i < nl) {
+            if (d.req_stamp[i] != t) continue;            // most lanes: one 4-byte load
             const Outbox ob = d.outbox[i];
-            if (ob.stamp != t || ob.target < 0) continue;   // no request, or an arrival
+            if (ob.target < 0) continue;                  // an arrival
             bool ok = transfer_eligible(d, ob, t);
             if (d.imode == 1) {
                 // case 1: only after standing stop_steps at the line (the key's
@@ -1228,223 +1248,163 @@ __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
     admit_items<kBigNT>(d, t);
 }
 
-// Sort eight (key, value) pairs by key, ascending, with the 19-comparator
-// network for eight inputs (Knuth, TAOCP vol. 3, 5.3.4); every index is a
-// constant, so the pairs stay in registers.
-__device__ inline void sort8_by_key(uint32_t* k, double* v) {
-    constexpr int kPairs[19][2] = {{0, 1}, {2, 3}, {4, 5}, {6, 7}, {0, 2}, {1, 3}, {4, 6}, {5, 7}, {1, 2}, {5, 6},
-                                   {0, 4}, {3, 7}, {1, 5}, {2, 6}, {1, 4}, {3, 6}, {2, 4}, {3, 5}, {3, 4}};
-#pragma unroll
-    for (int p = 0; p < 19; ++p) {
-        const int i = kPairs[p][0], j = kPairs[p][1];
-        const bool sw = k[i] > k[j];
-        const uint32_t ki = sw ? k[j] : k[i], kj = sw ? k[i] : k[j];
-        const double vi = sw ? v[j] : v[i], vj = sw ? v[i] : v[j];
-        k[i] = ki;
-        k[j] = kj;
-        v[i] = vi;
-        v[j] = vj;
-    }
-}
-
-// One thread per lane slot: eight threads per edge (an edge has at most 8
-// lanes), so the lanes of an edge are committed in parallel and the edge's
-// sums are reduced across its eight threads with shuffles.  A lane thread:
+// One thread per edge, over its lanes (most edges have one or two).  For a
+// lane the thread
 //   * settles its front's end-of-edge request: arrival, admitted transfer
 //     (an entry record on the next edge), or held at the stop line;
-//   * inserts the departure whose key won its lane;
+//   * inserts the departure whose key won the lane;
 //   * counts its vehicles for the next layout.
-// The edge's travel-time sum adds the exits in ascending vehicle id.
-__device__ inline void commit_block(const Dev& d, int blk, int t, int par, CounterAcc& acc, Scan4* wsh4) {
+// The edge's travel-time sum adds the exits in ascending vehicle id (at most
+// one per lane; kept in LDS and sorted there when an edge has several).
+// Lanes without a request cost three 4-byte stamps and their post-move count.
+__device__ inline void commit_block(const Dev& d, int blk, int t, int par, CounterAcc& acc, Scan4* wsh4,
+                                    uint32_t* xid, double* xtt) {
     const Slots S = d.s[par];
-    const int l = (int)(threadIdx.x & (kCommitLanes - 1));
-    const int e = blk * kEdgeBlock + (int)(threadIdx.x / kCommitLanes);
-    int nl = 0, base = 0;
-    double tts = 0.0;                              // the edge's travel-time sum and count (lane 0)
-    unsigned long long ttc = 0;
+    const int e = blk * kEdgeBlock + (int)threadIdx.x;
+    uint32_t* myid = xid + threadIdx.x * kCommitLanes;
+    double* mytt = xtt + threadIdx.x * kCommitLanes;
+    int c = 0, nex = 0;
     if (e < d.n_edges) {
-        nl = d.lanes[e];
-        base = d.lane_base[e];
-        if (l == 0) {
-            tts = d.tt_sum[e];
-            ttc = d.tt_cnt[e];
-        }
-    }
-    const bool lane_ok = l < nl;
-    const int gl = base + l;
-
-    // loads of this lane, independent of each other
-    Outbox ob;
-    ob.stamp = -1;
-    int pcnt = 0;
-    bool claimed = false;
-    unsigned long long w = ~0ull;
-    bool transfer_in = false;                      // case 1: this node's crossing enters this lane
-    if (lane_ok) {
-        ob = d.outbox[gl];
-        const LanePost p = d.post[gl];
-        pcnt = p.stamp == t ? p.cnt : 0;
-        claimed = d.enter_stamp[gl] == t;
-        w = d.win[gl];
+        const EdgeC ce = d.ec[e];
+        const int nl = ce.lanes, base = ce.lane_base;
+        int node_win = -1;                         // case 1: lane index of this node's winning crossing
         if (d.imode == 1) {
             const unsigned long long wn = d.win_node[d.efrom[e]];
-            if (wn != ~0ull) transfer_in = d.outbox[(int)(wn & ((1ull << 26) - 1))].target == gl;
+            if (wn != ~0ull) node_win = d.outbox[(int)(wn & ((1ull << 26) - 1))].target;
         }
-    }
-    const bool req = lane_ok && ob.stamp == t;
-
-    // the front's request
-    bool exits = false, won = false, arrived = false;
-    double dtt = 0.0, tau = 0.0;
-    int kk = 0;
-    int64_t r0 = 0;
-    if (req) {
-        // every load of this request first, then the decisions and stores
-        const uint32_t m = S.meta[ob.slot];
-        const float xs = S.x[ob.slot], vs = S.v[ob.slot];
-        const int hs = d.held_since[ob.vid];
-        const double tin = d.tau_in[ob.vid];
-        if (ob.target >= 0) {                      // prefetch the route for an entry record
-            kk = d.cursor[ob.vid] + 1;
-            r0 = d.roff[ob.vid];
-        }
-        if (d.imode == 1) {
-            won = ob.target >= 0 && ob.elig && d.win_node[ob.elig - 1] == ob.key;
-            if (won) d.rr[ob.elig - 1] = (int)((ob.tl_cls >> 16) & 255u);   // the pair just served
-        } else {
-            won = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
-        }
-        if (d.trace)
-            d.trace[(size_t)(t % d.trace_period) * d.trace_stride + ob.slot].kb |=
-                (ob.target < 0 ? TB_ARRIVE : (won ? TB_EXIT : TB_HELD)) << 8;
-        if (ob.target < 0) {                       // arrival at the route end
-            arrived = exits = true;
-            d.status[ob.vid] = kArrived;
-            d.fin_x[ob.vid] = xs;
-            d.fin_v[ob.vid] = vs;
-            d.fin_meta[ob.vid] = m;
-        } else if (won) {
-            exits = true;
-        } else {                                   // held at the stop line
-            S.x[ob.slot] = d.L[e];
-            S.v[ob.slot] = 0.0f;
-            S.meta[ob.slot] = m | (1u << 5);
-            if (hs < 0) d.held_since[ob.vid] = t;
-        }
-        // counted outside the branches: an increment of a different counter
-        // in each branch would be merged into one store through a computed
-        // index, which moves the counters to scratch memory
-        acc.c[cArrived] += arrived ? 1u : 0u;
-        acc.c[cTransfers] += won ? 1u : 0u;
-        acc.c[cWaivedExits] += (won && !lane_allowed(m, ob.nxt, l)) ? 1u : 0u;
-        acc.c[cHolds] += exits ? 0u : 1u;
-        if (exits) {
-            d.exit_stamp[gl] = t;
-            tau = ((double)t + (double)ob.phi) * (double)d.dt;
-            dtt = tau - tin;
-        }
-    }
-
-    // travel times of the edge's exits, added in ascending vehicle id by the
-    // edge's first thread: the eight (id, time) pairs of the edge are sorted
-    // by a 19-comparator network with fixed register indices
-    {
-        uint32_t kv[kCommitLanes];
-        double kd[kCommitLanes];
-        const uint32_t key = exits ? ob.vid : 0xFFFFFFFFu;
-#pragma unroll
-        for (int j = 0; j < kCommitLanes; ++j) {
-            kv[j] = (uint32_t)__shfl((int)key, j, kCommitLanes);
-            kd[j] = __shfl(dtt, j, kCommitLanes);
-        }
-        bool any = false;
-#pragma unroll
-        for (int j = 0; j < kCommitLanes; ++j) any = any || kv[j] != 0xFFFFFFFFu;
-        if (l == 0 && any) {
-            sort8_by_key(kv, kd);
-            double sum = tts;
-            int nex = 0;
-#pragma unroll
-            for (int j = 0; j < kCommitLanes; ++j)
-                if (kv[j] != 0xFFFFFFFFu) {
-                    sum += kd[j];
-                    ++nex;
+        for (int l = 0; l < nl; ++l) {
+            const int gl = base + l;
+            const LanePost p = d.post[gl];
+            const bool req = d.req_stamp[gl] == t;
+            bool claimed = d.enter_stamp[gl] == t;
+            const int pcnt = p.stamp == t ? p.cnt : 0;
+            bool exits = false;
+            if (req) {
+                const Outbox ob = d.outbox[gl];
+                // every load of this request first, then the decisions and stores
+                const uint32_t m = S.meta[ob.slot];
+                const float xs = S.x[ob.slot], vs = S.v[ob.slot];
+                const int hs = d.held_since[ob.vid];
+                const double tin = d.tau_in[ob.vid];
+                int kk = 0;
+                int64_t r0 = 0;
+                if (ob.target >= 0) {              // the route, for an entry record
+                    kk = d.cursor[ob.vid] + 1;
+                    r0 = d.roff[ob.vid];
                 }
+                bool won;
+                if (d.imode == 1) {
+                    won = ob.target >= 0 && ob.elig && d.win_node[ob.elig - 1] == ob.key;
+                    if (won) d.rr[ob.elig - 1] = (int)((ob.tl_cls >> 16) & 255u);   // the pair just served
+                } else {
+                    won = ob.target >= 0 && ob.elig && d.win[ob.target] == ob.key;
+                }
+                const bool arrived = ob.target < 0;
+                if (d.trace)
+                    d.trace[(size_t)(t % d.trace_period) * d.trace_stride + ob.slot].kb |=
+                        (arrived ? TB_ARRIVE : (won ? TB_EXIT : TB_HELD)) << 8;
+                exits = arrived || won;
+                if (arrived) {                     // arrival at the route end
+                    d.status[ob.vid] = kArrived;
+                    d.fin_x[ob.vid] = xs;
+                    d.fin_v[ob.vid] = vs;
+                    d.fin_meta[ob.vid] = m;
+                } else if (!won) {                 // held at the stop line
+                    S.x[ob.slot] = ce.L;
+                    S.v[ob.slot] = 0.0f;
+                    S.meta[ob.slot] = m | (1u << 5);
+                    if (hs < 0) d.held_since[ob.vid] = t;
+                }
+                // counted outside the branches: an increment of a different
+                // counter in each branch would be merged into one store through
+                // a computed index, which moves the counters to scratch memory
+                acc.c[cArrived] += arrived ? 1u : 0u;
+                acc.c[cTransfers] += won ? 1u : 0u;
+                acc.c[cWaivedExits] += (won && !lane_allowed(m, ob.nxt, l)) ? 1u : 0u;
+                acc.c[cHolds] += exits ? 0u : 1u;
+                if (exits) {
+                    d.exit_stamp[gl] = t;
+                    const double tau = ((double)t + (double)ob.phi) * (double)d.dt;
+                    myid[nex] = ob.vid;
+                    mytt[nex] = tau - tin;
+                    ++nex;
+                    if (arrived) d.t_arr[ob.vid] = tau;
+                    else d.tau_in[ob.vid] = tau;
+                }
+                if (won) {                         // entry record, stored at the target lane
+                    const int64_t pos = r0 + kk + 1;   // route index of the edge after ob.nxt
+                    EntryRec r;
+                    r.x = ob.xp;
+                    r.v = ob.v;
+                    r.vid = ob.vid;
+                    r.edge = ob.nxt;
+                    r.gl = ob.target;
+                    r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)((ob.tl_cls >> 8) & 255u),
+                                    d.rmask[r0 + kk]);
+                    r.nxt = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
+                    r.pad = 0;
+                    d.cursor[ob.vid] = kk;
+                    d.held_since[ob.vid] = -1;
+                    d.ent[ob.target] = r;
+                }
+            }
+            // the departure whose key won this lane; in case 1 only departures
+            // claim lanes, and this node's crossing into the lane comes first
+            const bool transfer_in = node_win == gl;
+            if (claimed && !transfer_in) {
+                const unsigned long long w = d.win[gl];
+                if (w >> 63) {
+                    const int vid = (int)(uint32_t)w;
+                    const int4 vq = d.vq[vid];     // vid is the head of queue vq.x
+                    const int64_t q0 = d.roff[vid];
+                    d.qhead[vq.x] = vq.y + 1;
+                    d.qhd[vq.x] = vq.z >= 0 ? make_int2(vq.w, vq.z) : make_int2(INT_MAX, -1);
+                    EntryRec r;
+                    r.x = 0.0f;
+                    r.v = 0.0f;
+                    r.vid = (uint32_t)vid;
+                    r.edge = e;                    // the queue's lane is on the first route edge
+                    r.gl = gl;
+                    r.meta = m_make(l, false, false, 0, d.cls[vid], d.rmask[q0]);
+                    r.nxt = (q0 + 1 < d.roff[vid + 1]) ? d.redges[q0 + 1] : -1;
+                    r.pad = 0;
+                    d.status[vid] = kActive;
+                    d.cursor[vid] = 0;
+                    d.held_since[vid] = -1;
+                    d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
+                    d.ent[gl] = r;
+                    acc.c[cDeparted]++;
+                }
+            }
+            if (transfer_in && !claimed) d.enter_stamp[gl] = t;   // the scatter takes the crossing's record
+            claimed = claimed || transfer_in;
+            // next layout: this lane's count and its offset in the edge
+            const int nc = pcnt - (exits ? 1 : 0) + (claimed ? 1 : 0);
+            d.lane_rel[gl] = c;
+            d.lane_newcnt[gl] = nc;
+            c += nc;
+        }
+        if (nex > 0) {
+            // travel times of the edge's exits, added in ascending vehicle id
+            for (int i = 1; i < nex; ++i)
+                for (int j = i; j > 0 && myid[j - 1] > myid[j]; --j) {
+                    const uint32_t ti = myid[j];
+                    myid[j] = myid[j - 1];
+                    myid[j - 1] = ti;
+                    const double tt = mytt[j];
+                    mytt[j] = mytt[j - 1];
+                    mytt[j - 1] = tt;
+                }
+            double sum = d.tt_sum[e];
+            for (int i = 0; i < nex; ++i) sum += mytt[i];
             d.tt_sum[e] = sum;
-            d.tt_cnt[e] = ttc + (unsigned long long)nex;
+            d.tt_cnt[e] += (unsigned long long)nex;
         }
     }
-    if (exits) {
-        if (arrived) d.t_arr[ob.vid] = tau;
-        else d.tau_in[ob.vid] = tau;
-    }
-
-    // the departure whose key won this lane (the winning key of a claimed lane);
-    // in case 1 only departures claim lanes, and a crossing into the lane
-    // comes first
-    const bool ins = lane_ok && claimed && (w >> 63) && !transfer_in;
-    const int ins_vid = ins ? (int)(uint32_t)w : 0;
-    if (transfer_in && !claimed) d.enter_stamp[gl] = t;   // the scatter takes the crossing's record
-    claimed = claimed || transfer_in;
-
-    // next layout: this lane's count, its offset in the edge, the edge's count
-    const int nc = pcnt - (exits ? 1 : 0) + (claimed ? 1 : 0);
-    int inc = nc;
-#pragma unroll
-    for (int dd = 1; dd < kCommitLanes; dd <<= 1) {
-        const int o = __shfl_up(inc, dd, kCommitLanes);
-        if (l >= dd) inc += o;
-    }
-    const int c = __shfl(inc, kCommitLanes - 1, kCommitLanes);   // vehicles of the edge
-    if (lane_ok) {
-        d.lane_rel[gl] = inc - nc;
-        d.lane_newcnt[gl] = nc;
-    }
-
-    // entry records, one per claimed lane, stored at that lane: a transfer
-    // won out of this lane (at its target), a departure into this lane
-    if (won) {
-        const int64_t pos = r0 + kk + 1;           // route index of the edge after ob.nxt
-        EntryRec r;
-        r.x = ob.xp;
-        r.v = ob.v;
-        r.vid = ob.vid;
-        r.edge = ob.nxt;
-        r.gl = ob.target;
-        r.meta = m_make((int)(ob.tl_cls & 255u), false, false, 0, (int)((ob.tl_cls >> 8) & 255u), d.rmask[r0 + kk]);
-        r.nxt = pos < d.roff[ob.vid + 1] ? d.redges[pos] : -1;
-        r.pad = 0;
-        d.cursor[ob.vid] = kk;
-        d.held_since[ob.vid] = -1;
-        d.ent[ob.target] = r;
-    }
-    if (ins) {
-        const int vid = ins_vid;
-        const int4 vq = d.vq[vid];                 // vid is the head of queue vq.x
-        const int64_t q0 = d.roff[vid];
-        d.qhead[vq.x] = vq.y + 1;
-        d.qhd[vq.x] = vq.z >= 0 ? make_int2(vq.w, vq.z) : make_int2(INT_MAX, -1);
-        EntryRec r;
-        r.x = 0.0f;
-        r.v = 0.0f;
-        r.vid = (uint32_t)vid;
-        r.edge = e;                                // the queue's lane is on the first route edge
-        r.gl = gl;
-        r.meta = m_make(l, false, false, 0, d.cls[vid], d.rmask[q0]);
-        r.nxt = (q0 + 1 < d.roff[vid + 1]) ? d.redges[q0 + 1] : -1;
-        r.pad = 0;
-        d.status[vid] = kActive;
-        d.cursor[vid] = 0;
-        d.held_since[vid] = -1;
-        d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
-        d.ent[gl] = r;
-        acc.c[cDeparted]++;
-    }
-
-    // offsets of the edges in the workgroup (one value per edge, at its lane 0)
-    Scan4 run = wg_exclusive_scan4<kCommitNT>(Scan4{l == 0 ? c : 0, -1, -1, -1}, wsh4);
-    if (l == 0 && e < d.n_edges) d.edge_rel[e] = run.s;
-    if (threadIdx.x == kCommitNT - 1) d.blk_sum[blk] = run.s + (l == 0 ? c : 0);
+    // offsets of the edges in the workgroup
+    const Scan4 run = wg_exclusive_scan4<kCommitNT>(Scan4{c, -1, -1, -1}, wsh4);
+    if (e < d.n_edges) d.edge_rel[e] = run.s;
+    if (threadIdx.x == kCommitNT - 1) d.blk_sum[blk] = run.s + c;
 }
 
 __device__ inline void flush_commit_counters(const Dev& d, const CounterAcc& acc, unsigned* shc) {
@@ -1455,12 +1415,14 @@ __device__ inline void flush_commit_counters(const Dev& d, const CounterAcc& acc
 __global__ void __launch_bounds__(kCommitNT) k_commit(Dev d) {
     __shared__ unsigned shc[cNumCounters];
     __shared__ Scan4 wsh4[kCommitNT / 64];
+    __shared__ uint32_t xid[kCommitNT * kCommitLanes];     // exits of each thread's edge
+    __shared__ double xtt[kCommitNT * kCommitLanes];
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     __syncthreads();
     const int t = d.ctl->t_b, par = t & 1;
     CounterAcc acc;
     acc.zero();
-    commit_block(d, blockIdx.x, t, par, acc, wsh4);
+    commit_block(d, blockIdx.x, t, par, acc, wsh4, xid, xtt);
     flush_commit_counters(d, acc, shc);
 }
 
@@ -1597,10 +1559,9 @@ __device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* 
             is_rear = (nr == ncnt - 1) && !entered;
         } else {                                  // a lane claimed this step takes its entry
             gl = i - nold;
-            const bool entered = d.enter_stamp[gl] == t;
+            if (d.enter_stamp[gl] != t) continue;  // most lanes: one 4-byte load
             const EntryRec r = d.ent[gl];
             const int ncnt = d.lane_newcnt[gl];
-            if (!entered) continue;
             nr = ncnt - 1;                        // the entry is the new rear
             is_rear = true;
             x = r.x;

@@ -86,3 +86,19 @@ def test_committed_records_are_well_formed():
 def test_cpu_info_names_the_host():
     info = bench.cpu_info()
     assert info["nproc"] >= 1 and isinstance(info["cpu_model"], str)
+
+
+def test_summarize_trace_means_and_last_window(tmp_path):
+    d = tmp_path / "tr" / "host"
+    d.mkdir(parents=True)
+    with open(d / "x_kernel_trace.csv", "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Start_Timestamp", "End_Timestamp"])
+        w.writeheader()
+        # five dispatches (listed out of start order) and one of another kernel
+        for k, us in [(3, 3), (0, 1), (4, 5), (1, 2), (2, 4)]:
+            w.writerow({"Kernel_Name": TILE, "Start_Timestamp": 1000 * k * 10, "End_Timestamp": 1000 * (k * 10 + us)})
+        w.writerow({"Kernel_Name": "k_commit(Dev)", "Start_Timestamp": 0, "End_Timestamp": 7000})
+    out = bench.summarize_trace(str(tmp_path / "tr"), last=2)
+    t = out["kernels"][TILE]
+    assert t["dispatches"] == 5 and t["mean_us"] == 3.0 and t["mean_us_last_2"] == 4.0   # in start order: 1 2 4 3 5
+    assert out["kernels"]["k_commit(Dev)"]["mean_us_last_1"] == 7.0
