@@ -245,7 +245,8 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     const dim3 b(kNT);
     const bool lds_scan = h->n_blk <= kScanLdsMax;
     if (!ev) {
-        hipLaunchKernelGGL(d.v0_spread != 0.0f ? k_tile_step_v0spread : k_tile_step, dim3(h->g_tile), b, 0, s, d);
+        hipLaunchKernelGGL(d.v0_spread != 0.0f ? k_tile_step_v0spread : k_tile_step, dim3(h->g_tile), dim3(kTileNT),
+                           0, s, d);
         hipLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, d);
         hipLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, d);
         if (lds_scan) {
@@ -256,8 +257,8 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
         }
         return;
     }
-    hipExtLaunchKernelGGL(d.v0_spread != 0.0f ? k_tile_step_v0spread : k_tile_step, dim3(h->g_tile), b, 0, s, ev[0],
-                          ev[1], 0, d);
+    hipExtLaunchKernelGGL(d.v0_spread != 0.0f ? k_tile_step_v0spread : k_tile_step, dim3(h->g_tile), dim3(kTileNT),
+                          0, s, ev[0], ev[1], 0, d);
     hipExtLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     if (lds_scan) {
         hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, ev[4], ev[5], 0, d);
@@ -590,11 +591,11 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 int dev = 0, cus = 0, per_cu = 0;
                 HIP_OK(hipGetDevice(&dev));
                 HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_step, kNT, 0));
+                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_step, kTileNT, 0));
                 d.tile_target = std::max(1, cus * std::max(per_cu, 1));
             }
             d.tile_window = 0;
-            h->g_tile = std::max(1, std::min(1024, (N + kTileWindowMin - 1) / kTileWindowMin));
+            h->g_tile = std::max(1, std::min(d.tile_target, (N + kTileWindowMin - 1) / kTileWindowMin));
             {   // k_big_admit: every workgroup resident (its grid barrier), enough threads
                 // for one admission item each where that fits
                 int dev = 0, cus = 0, per_cu = 0;
@@ -1063,11 +1064,25 @@ sim_status sim_backward(sim_handle* h, const double* dL_dmean_tt, double* dL_dpa
         traced.trace_period = R;
         traced.trace_stride = N;
         traced.nact_hist = nact;
+        // per-record parts and the look-ahead lists of one reverse step
+        const size_t NLs = (size_t)std::max(h->n_lanes, 1);
+        BwPart* part = (BwPart*)get(sizeof(BwPart) * (size_t)N);
+        int* lk_cnt = (int*)get(4 * NLs);
+        int* lk_rec = (int*)get(4 * NLs * kLookListCap);
+        double* lkx = (double*)get(8 * (size_t)N);
+        double* lkv = (double*)get(8 * (size_t)N);
+        int* lk_stamp = (int*)get(4 * (size_t)N);
+        HIP_OK(hipMemsetAsync(lk_cnt, 0, 4 * NLs, h->stream));
+        HIP_OK(hipMemsetAsync(lk_stamp, 0xFF, 4 * (size_t)N, h->stream));
         // one reverse step: (lx, lv) -> (nx, nv) for step index i of a segment
         auto reverse_step = [&](hipStream_t s, int i, double* ix, double* iv, double* ox, double* ov) {
-            hipLaunchKernelGGL(k_zero2, dim3(gbw), dim3(kNT), 0, s, ox, ov, N);
-            hipLaunchKernelGGL(k_backward, dim3(gbw), dim3(kNT), 0, s, saved, trace + (size_t)i * N, nact + i, i, NC,
-                               ix, iv, ox, ov, lt, dw, gpart);
+            const TraceRec* tr = trace + (size_t)i * N;
+            hipLaunchKernelGGL(k_backward, dim3(gbw), dim3(kNT), 0, s, saved, tr, nact + i, i, NC, ix, iv, part,
+                               lk_cnt, lk_rec, lt, dw, gpart, ox, ov, N);
+            hipLaunchKernelGGL(k_bw_looks, dim3(gbw), dim3(kNT), 0, s, tr, nact + i, i, part, lk_cnt, lk_rec, lkx,
+                               lkv, lk_stamp);
+            hipLaunchKernelGGL(k_bw_gather, dim3(gbw), dim3(kNT), 0, s, tr, nact + i, i, part, lkx, lkv, lk_stamp,
+                               ox, ov);
         };
         // Full segments replay captured graphs: the traced re-run (kGraphSteps
         // steps at a time) and the whole reverse sweep of R steps, for either
@@ -1139,6 +1154,14 @@ sim_status sim_backward(sim_handle* h, const double* dL_dmean_tt, double* dL_dpa
         for (int q = 0; q < 4; ++q) {
             if (ge[q]) (void)hipGraphExecDestroy(ge[q]);
             if (gg[q]) (void)hipGraphDestroy(gg[q]);
+        }
+        {   // a layout or trace check of the re-runs or of the sweep failed
+            Ctl c;
+            HIP_OK(hipMemcpy(&c, h->d.ctl, sizeof(Ctl), hipMemcpyDeviceToHost));
+            if (c.err) {
+                load_state(h, end_state, T);
+                throw Fail{SIM_EDEVICE, fmt("device check failed in the reverse sweep (code %d)", c.err)};
+            }
         }
         load_state(h, end_state, T);
         std::vector<double> gp((size_t)gbw * np);
@@ -1350,7 +1373,7 @@ sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
         };
         std::vector<Cand> cands;
         for (int w : {0, 64, 128, 256})
-            for (int g1 : {512, 1024})
+            for (int g1 : {std::max(1, h->d.tile_target / 2), h->d.tile_target})
                 for (int g2 : {h->g_big_min, h->g_big_max})
                     for (int g4 : {1024, 4096}) {
                         const int g1c = std::max(1, std::min(g1, (N + (w ? w : kTileWindowMin) - 1) /
@@ -1492,10 +1515,13 @@ struct DevBufs {   // device buffers of one routing call, freed on every exit
 };
 }  // namespace
 
-extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* edge_cost, int32_t n_queries,
-                                          const int32_t* origin, const int32_t* dest, int64_t* route_off,
-                                          int32_t* route_edges, int64_t capacity, int64_t* n_route_edges) {
-    return guarded(nullptr, [&] {
+namespace {
+// The routes of Sec. II-C on the GPU; B provides the call's device buffers.
+template <class B>
+void shortest_routes_impl(B& b, const sim_network* net, const float* edge_cost, int32_t n_queries,
+                          const int32_t* origin, const int32_t* dest, int64_t* route_off, int32_t* route_edges,
+                          int64_t capacity, int64_t* n_route_edges) {
+    {
         auto bad = [](std::string m) { throw Fail{SIM_EINVAL, std::move(m)}; };
         if (!net || !edge_cost || !route_off || !n_route_edges || n_queries < 0) bad("null argument");
         if (n_queries > 0 && (!origin || !dest)) bad("null argument");
@@ -1530,17 +1556,16 @@ extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* e
         }
         const int nd = (int)dests.size();
         if ((double)nd * V * 4.0 > 16e9) throw Fail{SIM_EUNSUPPORTED, "labels of all destinations above 16 GB"};
-        DevBufs b;
-        int* d_off = b.get<int>(V + 1);
-        int* d_oe = b.get<int>(E);
-        int* d_to = b.get<int>(E);
-        float* d_cost = b.get<float>(E);
-        int* d_dest = b.get<int>(nd);
-        float* d_dist = b.get<float>((size_t)nd * V);
-        int* d_slot = b.get<int>(n_queries);
-        int* d_o = b.get<int>(n_queries);
-        int* d_d = b.get<int>(n_queries);
-        int* d_len = b.get<int>(n_queries);
+        int* d_off = b.template get<int>(V + 1);
+        int* d_oe = b.template get<int>(E);
+        int* d_to = b.template get<int>(E);
+        float* d_cost = b.template get<float>(E);
+        int* d_dest = b.template get<int>(nd);
+        float* d_dist = b.template get<float>((size_t)nd * V);
+        int* d_slot = b.template get<int>(n_queries);
+        int* d_o = b.template get<int>(n_queries);
+        int* d_d = b.template get<int>(n_queries);
+        int* d_len = b.template get<int>(n_queries);
         HIP_OK(hipMemcpy(d_off, out_off.data(), 4 * (size_t)(V + 1), hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d_oe, out_edge.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
         HIP_OK(hipMemcpy(d_to, net->edge_to, 4 * (size_t)E, hipMemcpyHostToDevice));
@@ -1563,8 +1588,8 @@ extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* e
                     pto[(size_t)j * V + v] = has ? net->edge_to[out_edge[k]] : v;
                     pcost[(size_t)j * V + v] = has ? edge_cost[out_edge[k]] : INFINITY;
                 }
-            int* d_pto = b.get<int>((size_t)km * V);
-            float* d_pcost = b.get<float>((size_t)km * V);
+            int* d_pto = b.template get<int>((size_t)km * V);
+            float* d_pcost = b.template get<float>((size_t)km * V);
             HIP_OK(hipMemcpy(d_pto, pto.data(), 4 * (size_t)km * V, hipMemcpyHostToDevice));
             HIP_OK(hipMemcpy(d_pcost, pcost.data(), 4 * (size_t)km * V, hipMemcpyHostToDevice));
             if (km == 4 && V <= 10 * kRouteNT)   // adjacency in registers
@@ -1592,12 +1617,24 @@ extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* e
         if (!route_edges || capacity < route_off[n_queries])
             bad(fmt("route_edges holds %lld edges, the routes need %lld", (long long)capacity,
                     (long long)route_off[n_queries]));
-        int64_t* d_roff = b.get<int64_t>(n_queries + 1);
-        int* d_re = b.get<int>((size_t)route_off[n_queries]);
+        int64_t* d_roff = b.template get<int64_t>(n_queries + 1);
+        int* d_re = b.template get<int>((size_t)route_off[n_queries]);
         HIP_OK(hipMemcpy(d_roff, route_off, 8 * (size_t)(n_queries + 1), hipMemcpyHostToDevice));
         hipLaunchKernelGGL(k_route_walk, dim3(gw), dim3(256), 0, 0, V, d_off, d_oe, d_to, d_cost, d_dist, d_slot, d_o,
                            d_d, n_queries, 1, d_len, (const int64_t*)d_roff, d_re);
         HIP_OK(hipGetLastError());
         HIP_OK(hipMemcpy(route_edges, d_re, 4 * (size_t)route_off[n_queries], hipMemcpyDeviceToHost));
+    }
+}
+
+}  // namespace
+
+extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* edge_cost, int32_t n_queries,
+                                          const int32_t* origin, const int32_t* dest, int64_t* route_off,
+                                          int32_t* route_edges, int64_t capacity, int64_t* n_route_edges) {
+    return guarded(nullptr, [&] {
+        DevBufs b;
+        shortest_routes_impl(b, net, edge_cost, n_queries, origin, dest, route_off, route_edges, capacity,
+                             n_route_edges);
     });
 }

@@ -34,6 +34,7 @@ constexpr int kWaves = kNT / 64;
 constexpr int kTileWindowMax = 256;      // a tile = the edges whose first slot lies in a window of
 constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256)
 constexpr int kTileCapLds = 384;         // tiles up to this size are staged in LDS (4 workgroups per CU)
+constexpr int kTileNT = 256;             // threads per tile workgroup
 constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
 constexpr int kCommitLanes = 8;         // lanes of an edge at most
@@ -94,7 +95,8 @@ __device__ inline StepHead step_head(const Ctl* c) {
     return StepHead{v.x, v.y, v.z, v.w};
 }
 
-enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8, kErrBarrier = 16 };
+enum : int { kErrTileTooBig = 1, kErrNewPos = 2, kErrScatter = 4, kErrPermutation = 8, kErrBarrier = 16,
+             kErrTrace = 32 };
 
 struct Slots {
     float* x;
@@ -122,7 +124,7 @@ struct TraceRec {
     float xn;         // position after Phase 2
     int edge;
     uint32_t kb;      // kind | branch bits << 8 (TB_*)
-    float pad;
+    int look_gl;      // LOOK: the global lane whose start-of-step rear is the partner; else -1
 };
 enum : uint32_t { TB_F = 1, TB_D = 2, TB_S = 4, TB_B = 8, TB_C = 16, TB_W = 32, TB_EXIT = 64, TB_ARRIVE = 128,
                   TB_HELD = 256 };
@@ -872,7 +874,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const ClassParams cpi = scp[m_cls(m)];
         const bool allowed_l = lane_allowed(m, f, lam);
         int kind;
-        int partner = -1;
+        int partner = -1, look_gl = -1;
         float s = 0.0f, vl = 0.0f, rear_j = 0.0f;
         if (j >= 0) {
             kind = kVeh;
@@ -894,6 +896,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 s = (b.L[q] - xi) + r.xm;
                 vl = r.v;
                 partner = (int)r.vid;
+                look_gl = b.lbf[q] + lf;
             } else {
                 kind = kFree;
             }
@@ -953,7 +956,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             tr.xn = xnew;
             tr.edge = e;
             tr.kb = (uint32_t)kind | (tb << 8);
-            tr.pad = 0.0f;
+            tr.look_gl = look_gl;
             d.trace[(size_t)(t % d.trace_period) * d.trace_stride + dst] = tr;
         }
         b.pel[newpos] = elam;
@@ -1033,8 +1036,8 @@ __device__ inline int tile_window(const Dev& d, int n) {
 template <bool kSpread>
 __device__ inline void tile_step(const Dev& d) {
     __shared__ __align__(16) char lds[kTileCapLds * kTileBytesPerVeh + 64];
-    __shared__ Scan4 wsh4[kWaves];
-    __shared__ int wsh[2 * kWaves];
+    __shared__ Scan4 wsh4[kTileNT / 64];
+    __shared__ int wsh[2 * (kTileNT / 64)];
     __shared__ unsigned shc[cNumCounters];
     __shared__ ClassParams scp[16];
     __shared__ uint32_t dtask[kTileDrawTasks];
@@ -1065,7 +1068,7 @@ __device__ inline void tile_step(const Dev& d) {
     for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
         const int w0 = k * W, w1 = min(n, w0 + W);
         int a0, a1;
-        tile_bounds<kNT>(edge, w0, w1, n, wsh, a0, a1);
+        tile_bounds<kTileNT>(edge, w0, w1, n, wsh, a0, a1);
         if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
         const int cnt = a1 - a0;
         if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
@@ -1073,7 +1076,7 @@ __device__ inline void tile_step(const Dev& d) {
             continue;
         }
         if (cnt <= kTileCapLds) {
-            process_tile<kNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
+            process_tile<kTileNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
         } else if (threadIdx.x == 0) {
             const int q = atomicAdd(&d.ctl->n_big[par], 1);
             d.big_list[2 * q] = a0;
@@ -1083,9 +1086,9 @@ __device__ inline void tile_step(const Dev& d) {
     flush_counters_lds(d, acc, shc);
 }
 
-__global__ void __launch_bounds__(kNT) k_tile_step(Dev d) { tile_step<false>(d); }
+__global__ void __launch_bounds__(kTileNT) k_tile_step(Dev d) { tile_step<false>(d); }
 // the same with per-driver free-flow limits (v0_spread > 0)
-__global__ void __launch_bounds__(kNT) k_tile_step_v0spread(Dev d) { tile_step<true>(d); }
+__global__ void __launch_bounds__(kTileNT) k_tile_step_v0spread(Dev d) { tile_step<true>(d); }
 
 // Tiles above kTileCapLds: 1,024-thread workgroups with kBigCapLds vehicles
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
@@ -1655,15 +1658,42 @@ __device__ inline double idm_partials(double v, double v0, double vl, double s, 
     return phi - a * q * q;
 }
 
+// The reverse sweep of one step in three kernels, with no floating-point
+// atomics, so the result is the same bit for bit on every run:
+//   k_backward   each record's own part of (nx, nv) and its part for its
+//                partner (leader, or look-ahead rear), written per record;
+//                a look-ahead record joins the list of the lane it looked into;
+//   k_bw_looks   the first record of each such list adds the list's parts in
+//                record order for the lane's start-of-step rear;
+//   k_bw_gather  every vehicle: own part + the part of the record behind it
+//                in its lane (its follower, whose leader it is) + its
+//                look-ahead sum.
+// A VEH or clamp record's leader is the record just before it in the traced
+// layout (the post-lane-change order of edge, lane, x and id); k_backward
+// checks this and flags a layout error otherwise.
+constexpr int kLookListCap = 16;   // look-ahead records into one lane in one step, at most
+
+struct BwPart {
+    double sx, sv;    // the record's own vehicle
+    double px, pv;    // its partner
+};
+
 __global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, const int* n_ptr, int t, int n_classes,
-                                                 const double* lx, const double* lv, double* nx, double* nv,
-                                                 double* lt, const double* w, double* gpart) {
+                                                 const double* lx, const double* lv, BwPart* part, int* lk_cnt,
+                                                 int* lk_rec, double* lt, const double* w, double* gpart,
+                                                 double* ox, double* ov, int n_all) {
     __shared__ double red[kNT];
     double g[kParamMax];
     const int np = 5 * n_classes;
     for (int k = 0; k < np; ++k) g[k] = 0.0;
     const double dt = (double)d.dt;
     const int n = *n_ptr;
+    // the step's output adjoints start at zero (k_bw_gather writes those of
+    // the vehicles active at the step's start)
+    for (int i = blockIdx.x * kNT + threadIdx.x; i < n_all; i += gridDim.x * kNT) {
+        ox[i] = 0.0;
+        ov[i] = 0.0;
+    }
     for (int r = blockIdx.x * kNT + threadIdx.x; r < n; r += gridDim.x * kNT) {
         const TraceRec R = rec[r];
         const uint32_t bits = R.kb >> 8;
@@ -1672,6 +1702,7 @@ __global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, co
         const double L = (double)d.L[e];
         const double x = R.x, v = R.v, xn = R.xn;
         double mx = lx[i], mv = lv[i];
+        BwPart P{0.0, 0.0, 0.0, 0.0};
         if (bits & (TB_HELD | TB_W | TB_ARRIVE)) {
             mx = 0.0;
             mv = 0.0;
@@ -1681,50 +1712,55 @@ __global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, co
             if (xn != x) {
                 const double dd = xn - x;
                 mx += gt * dt * (-(L - x) / (dd * dd));
-                atomicAdd(&nx[i], gt * dt * ((L - xn) / (dd * dd)));
+                P.sx = gt * dt * ((L - xn) / (dd * dd));
             }
             lt[i] = -w[e];
         }
-        if (bits & (TB_HELD | TB_W)) continue;
-        const int c = d.cls[i];
-        const ClassParams cp = d.cp[c];
-        const double lim = (double)driver_limit(d.lim[e], d.v0_spread, d.seed, e, d.edge_period, d.rid[i]);
-        const double v0 = (double)cp.v0f * lim;
-        double pd[8];
-        const double acc = idm_partials(v, v0, (double)R.vl, (double)R.s, cp, kind, bits, pd);
-        double macc = 0.0, ax = 0.0, av = 0.0;
-        if (bits & TB_C) {                         // clamped to the leader's rear
-            atomicAdd(&nx[j], mx);
-            mx = 0.0;
+        if (!(bits & (TB_HELD | TB_W))) {
+            const int c = d.cls[i];
+            const ClassParams cp = d.cp[c];
+            const double lim = (double)driver_limit(d.lim[e], d.v0_spread, d.seed, e, d.edge_period, d.rid[i]);
+            const double v0 = (double)cp.v0f * lim;
+            double pd[8];
+            const double acc = idm_partials(v, v0, (double)R.vl, (double)R.s, cp, kind, bits, pd);
+            double macc = 0.0, ax = 0.0, av = 0.0;
+            if (bits & TB_C) {                     // clamped to the leader's rear
+                P.px = mx;
+                mx = 0.0;
+            }
+            if (bits & TB_B) {                     // exact stop
+                ax += mx;
+                av += mx * (-v / acc);
+                macc += mx * (v * v / (2.0 * acc * acc));
+            } else {
+                ax += mx;
+                av += mx * dt + mv;
+                macc += mx * 0.5 * dt * dt + mv * dt;
+            }
+            av += macc * pd[0];
+            if (kind == kVeh || kind == kLook) {
+                ax -= macc * pd[2];
+                P.px += macc * pd[2];
+                P.pv += macc * pd[1];
+            } else if (kind == kStop) {
+                ax -= macc * pd[2];
+            }
+            P.sx += ax;
+            P.sv += av;
+            g[5 * c + 0] += macc * pd[3] * lim;
+            g[5 * c + 1] += macc * pd[4];
+            g[5 * c + 2] += macc * pd[5];
+            g[5 * c + 3] += macc * pd[6];
+            g[5 * c + 4] += macc * pd[7];
         }
-        if (bits & TB_B) {                         // exact stop
-            ax += mx;
-            av += mx * (-v / acc);
-            macc += mx * (v * v / (2.0 * acc * acc));
-        } else {
-            ax += mx;
-            av += mx * dt + mv;
-            macc += mx * 0.5 * dt * dt + mv * dt;
+        part[r] = P;
+        if ((kind == kVeh || (bits & TB_C)) && !(bits & (TB_HELD | TB_W)) && (r == 0 || (int)rec[r - 1].vid != j))
+            atomicOr(&d.ctl->err, kErrTrace);     // the leader is not the record just before
+        if (kind == kLook && !(bits & (TB_HELD | TB_W))) {
+            const int k = atomicAdd(&lk_cnt[R.look_gl], 1);
+            if (k < kLookListCap) lk_rec[(size_t)R.look_gl * kLookListCap + k] = r;
+            else atomicOr(&d.ctl->err, kErrTrace);
         }
-        av += macc * pd[0];
-        if (kind == kVeh) {
-            ax -= macc * pd[2];
-            atomicAdd(&nx[j], macc * pd[2]);
-            atomicAdd(&nv[j], macc * pd[1]);
-        } else if (kind == kStop) {
-            ax -= macc * pd[2];
-        } else if (kind == kLook) {
-            ax -= macc * pd[2];
-            atomicAdd(&nx[j], macc * pd[2]);
-            atomicAdd(&nv[j], macc * pd[1]);
-        }
-        atomicAdd(&nx[i], ax);
-        atomicAdd(&nv[i], av);
-        g[5 * c + 0] += macc * pd[3] * lim;
-        g[5 * c + 1] += macc * pd[4];
-        g[5 * c + 2] += macc * pd[5];
-        g[5 * c + 3] += macc * pd[6];
-        g[5 * c + 4] += macc * pd[7];
     }
     for (int k = 0; k < np; ++k) {                 // fixed-order tree per parameter
         red[threadIdx.x] = g[k];
@@ -1738,12 +1774,70 @@ __global__ void __launch_bounds__(kNT) k_backward(Dev d, const TraceRec* rec, co
     }
 }
 
-// nx = nv = 0 before a step of the reverse sweep (a kernel, not a memset, so
-// that it can sit in a captured graph)
-__global__ void __launch_bounds__(kNT) k_zero2(double* a, double* b, int n) {
-    for (int i = blockIdx.x * kNT + threadIdx.x; i < n; i += gridDim.x * kNT) {
-        a[i] = 0.0;
-        b[i] = 0.0;
+// Look-ahead sums: the list of a lane is sorted by record index and added in
+// that order by its first record, for the lane's start-of-step rear (the
+// partner of every record in the list); the list is then emptied.
+__global__ void __launch_bounds__(kNT) k_bw_looks(const TraceRec* rec, const int* n_ptr, int t, const BwPart* part,
+                                                  int* lk_cnt, const int* lk_rec, double* lkx, double* lkv,
+                                                  int* lk_stamp) {
+    const int n = *n_ptr;
+    for (int r = blockIdx.x * kNT + threadIdx.x; r < n; r += gridDim.x * kNT) {
+        const TraceRec R = rec[r];
+        if ((int)(R.kb & 255u) != kLook || ((R.kb >> 8) & (TB_HELD | TB_W))) continue;
+        const int g = R.look_gl;
+        const int m = min(lk_cnt[g], kLookListCap);
+        int lst[kLookListCap];
+        int first = r;
+        for (int k = 0; k < kLookListCap; ++k) {
+            lst[k] = k < m ? lk_rec[(size_t)g * kLookListCap + k] : INT_MAX;
+            first = min(first, lst[k]);
+        }
+        if (first != r) continue;                  // another record of the list sums it
+        for (int a = 1; a < kLookListCap; ++a)     // insertion sort of the (few) record indices
+            for (int b = a; b > 0 && lst[b - 1] > lst[b]; --b) {
+                const int tmp = lst[b];
+                lst[b] = lst[b - 1];
+                lst[b - 1] = tmp;
+            }
+        double sx = 0.0, sv = 0.0;
+        for (int k = 0; k < m; ++k) {
+            sx += part[lst[k]].px;
+            sv += part[lst[k]].pv;
+        }
+        const int j = R.partner;
+        lkx[j] = sx;
+        lkv[j] = sv;
+        lk_stamp[j] = t;
+        lk_cnt[g] = 0;
+    }
+}
+
+// (nx, nv) of every vehicle that was active at the step's start, in a fixed
+// order: own part, then its follower's part, then its look-ahead sum.
+__global__ void __launch_bounds__(kNT) k_bw_gather(const TraceRec* rec, const int* n_ptr, int t, const BwPart* part,
+                                                   const double* lkx, const double* lkv, int* lk_stamp,
+                                                   double* nx, double* nv) {
+    const int n = *n_ptr;
+    for (int r = blockIdx.x * kNT + threadIdx.x; r < n; r += gridDim.x * kNT) {
+        const int i = (int)rec[r].vid;
+        const BwPart P = part[r];
+        double ax = P.sx, av = P.sv;
+        if (r + 1 < n) {
+            const TraceRec F = rec[r + 1];
+            const uint32_t fb = F.kb >> 8;
+            if (F.partner == i && ((int)(F.kb & 255u) == kVeh || (fb & TB_C)) && !(fb & (TB_HELD | TB_W))) {
+                const BwPart Q = part[r + 1];
+                ax += Q.px;
+                av += Q.pv;
+            }
+        }
+        if (lk_stamp[i] == t) {                    // consumed here: stamps repeat from segment to segment
+            ax += lkx[i];
+            av += lkv[i];
+            lk_stamp[i] = -1;
+        }
+        nx[i] = ax;
+        nv[i] = av;
     }
 }
 

@@ -58,18 +58,24 @@ def test_backward_matches_fp64_adjoint(M, oracle_mod, calib):
     loss, omean, og = o.replay(o.theta(w), target, ouse.astype(np.uint8), grad=True)
     og = og.reshape(-1, 5)
     rel = np.linalg.norm(g - og) / np.linalg.norm(og)
-    print("relative gradient error vs FP64 adjoint:", rel)
-    assert rel <= 1e-3
     big = np.abs(og) > 1e-3 * np.linalg.norm(og)
-    assert np.all(np.abs(g[big] - og[big]) <= 1e-3 * np.linalg.norm(og) + 1e-2 * np.abs(og[big]))
+    comp = np.abs(g[big] - og[big]) / np.abs(og[big])
+    print("relative gradient error vs FP64 adjoint:", rel, "largest per-component error:", comp.max())
+    assert rel <= 1e-3
+    # every component above 1e-3 of the gradient's norm within 1e-3 of itself
+    assert np.all(comp <= 1e-3), comp
 
 
-def test_checkpoint_interval_independent(M, calib):
+def test_checkpoint_interval_independent_and_reproducible(M, calib):
+    """The reverse sweep adds every part in a fixed order (no floating-point
+    atomics): the gradient is the same bit for bit whatever the checkpoint
+    interval, and from run to run."""
     w, target, tcnt = calib
     g120 = gpu_grad(M, w, target, tcnt, 120)[3]
+    assert np.array_equal(gpu_grad(M, w, target, tcnt, 120)[3], g120)
     for r in (45, STEPS):
         g = gpu_grad(M, w, target, tcnt, r)[3]
-        assert np.linalg.norm(g - g120) <= 1e-9 * np.linalg.norm(g120), r
+        assert np.array_equal(g, g120), r
 
 
 def test_backward_leaves_state_and_needs_record(M, c1, calib):
