@@ -268,6 +268,21 @@ sim_status sim_shortest_routes(const sim_network *net, const float *edge_cost, i
                                const int32_t *origin, const int32_t *dest, int64_t *route_off,
                                int32_t *route_edges, int64_t capacity, int64_t *n_route_edges);
 
+/* The same routes for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and errors as sim_shortest_routes, but every device
+ * buffer of the call (network copy, labels, queries, routes) is carved out of
+ * one fixed 64 MiB region that the library holds on each device it runs on
+ * until the process ends; no allocation is made.  A call that needs more
+ * (roughly: 4 bytes x nodes x distinct destinations, plus the network, the
+ * queries and 4 bytes per route edge) returns SIM_EINVAL and says so in
+ * sim_last_error(NULL).  Calls on one device share the region: calls that
+ * overlap in time on the same device (other host threads) race and must be
+ * serialised by the caller. */
+sim_status sim_shortest_routes_noalloc(const sim_network *net, const float *edge_cost, int32_t n_queries,
+                                       const int32_t *origin, const int32_t *dest, int64_t *route_off,
+                                       int32_t *route_edges, int64_t capacity, int64_t *n_route_edges);
+
 const char *sim_last_error(const sim_handle *h);
 
 /* Vehicle-updates done in tiles above one workgroup's LDS (inside

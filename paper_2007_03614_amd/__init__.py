@@ -111,11 +111,13 @@ KERNELS = ["k_tile_step", "k_big_admit", "k_commit", "k_scatter"]
 
 _lib.sim_shortest_routes.argtypes = [ctypes.POINTER(SimNetwork), P, I32, P, P, P, P, ctypes.c_int64, P]
 _lib.sim_shortest_routes.restype = I32
+_lib.sim_shortest_routes_noalloc.argtypes = _lib.sim_shortest_routes.argtypes
+_lib.sim_shortest_routes_noalloc.restype = I32
 
 EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
             "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",
             "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_get_schedule", "sim_backward",
-            "sim_big_tile_updates", "sim_shortest_routes",
+            "sim_big_tile_updates", "sim_shortest_routes", "sim_shortest_routes_noalloc",
             "sim_probe_fp32", "sim_probe_philox", "sim_probe_draws"]
 
 
@@ -435,9 +437,7 @@ def edge_mean_travel_time(theta, workload, steps, record_every=120, stream=None)
     return _edge_tt_function().apply(theta, workload, steps, record_every, stream)
 
 
-def shortest_routes(net, cost, origin, dest):
-    """Routes on the GPU minimising binary32 edge costs (sim_shortest_routes):
-    returns (route_off int64[n + 1], route_edges int32)."""
+def _routes(fn, net, cost, origin, dest):
     ef, et = _c(net.edge_from, np.int32), _c(net.edge_to, np.int32)
     z8 = np.zeros(net.n_edges, np.uint8)
     zo = np.zeros(net.n_edges + 1, np.int32)
@@ -448,11 +448,21 @@ def shortest_routes(net, cost, origin, dest):
     off = np.zeros(o.size + 1, np.int64)
     tot = np.zeros(1, np.int64)
     edges = np.zeros(max(1024, 128 * o.size), np.int32)
-    st = _lib.sim_shortest_routes(ctypes.byref(sn), _p(c), int(o.size), _p(o), _p(d), _p(off), _p(edges),
-                                  int(edges.size), _p(tot))
+    st = fn(ctypes.byref(sn), _p(c), int(o.size), _p(o), _p(d), _p(off), _p(edges), int(edges.size), _p(tot))
     if st != 0 and int(tot[0]) > edges.size:   # longer routes than guessed: again, sized
         edges = np.zeros(int(tot[0]), np.int32)
-        st = _lib.sim_shortest_routes(ctypes.byref(sn), _p(c), int(o.size), _p(o), _p(d), _p(off), _p(edges),
-                                      int(edges.size), _p(tot))
+        st = fn(ctypes.byref(sn), _p(c), int(o.size), _p(o), _p(d), _p(off), _p(edges), int(edges.size), _p(tot))
     _check(st)
     return off, edges[:int(tot[0])]
+
+
+def shortest_routes(net, cost, origin, dest):
+    """Routes on the GPU minimising binary32 edge costs (sim_shortest_routes):
+    returns (route_off int64[n + 1], route_edges int32)."""
+    return _routes(_lib.sim_shortest_routes, net, cost, origin, dest)
+
+
+def shortest_routes_noalloc(net, cost, origin, dest):
+    """The same through sim_shortest_routes_noalloc (no device allocation; the
+    call's buffers live in the library's fixed 64 MiB region)."""
+    return _routes(_lib.sim_shortest_routes_noalloc, net, cost, origin, dest)

@@ -8,6 +8,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -1516,6 +1517,23 @@ struct DevBufs {   // device buffers of one routing call, freed on every exit
 }  // namespace
 
 namespace {
+// Device memory of one routing call carved out of a fixed region (the
+// no-allocation entry point): 256-byte aligned pieces, SIM_EINVAL past its end.
+struct ScratchBufs {
+    char* base;
+    size_t cap, used = 0;
+    template <class T>
+    T* get(size_t n) {
+        const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
+        if (used + bytes > cap)
+            throw Fail{SIM_EINVAL, fmt("the call needs more than the %zu bytes of scratch of "
+                                       "sim_shortest_routes_noalloc", cap)};
+        T* q = (T*)(base + used);
+        used += bytes;
+        return q;
+    }
+};
+
 // The routes of Sec. II-C on the GPU; B provides the call's device buffers.
 template <class B>
 void shortest_routes_impl(B& b, const sim_network* net, const float* edge_cost, int32_t n_queries,
@@ -1627,6 +1645,28 @@ void shortest_routes_impl(B& b, const sim_network* net, const float* edge_cost, 
     }
 }
 
+// Scratch of sim_shortest_routes_noalloc: every device that runs it holds one
+// copy until the process ends.  Host code reaches a device's copy through the
+// address hipGetSymbolAddress returns on that device, never through the name.
+constexpr size_t kRouteScratchBytes = (size_t)64 << 20;
+__device__ __align__(256) unsigned char scratch[kRouteScratchBytes];
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+void* route_scratch() {
+    int dev = 0;
+    HIP_OK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) throw Fail{SIM_EUNSUPPORTED, fmt("device %d: too many devices", dev)};
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        HIP_OK(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        if (!ptr) throw Fail{SIM_EDEVICE, "no address for the routing scratch"};
+        g_scratch_ptr[dev] = ptr;
+    }
+    return g_scratch_ptr[dev];
+}
 }  // namespace
 
 extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* edge_cost, int32_t n_queries,
@@ -1634,6 +1674,16 @@ extern "C" sim_status sim_shortest_routes(const sim_network* net, const float* e
                                           int32_t* route_edges, int64_t capacity, int64_t* n_route_edges) {
     return guarded(nullptr, [&] {
         DevBufs b;
+        shortest_routes_impl(b, net, edge_cost, n_queries, origin, dest, route_off, route_edges, capacity,
+                             n_route_edges);
+    });
+}
+
+extern "C" sim_status sim_shortest_routes_noalloc(const sim_network* net, const float* edge_cost, int32_t n_queries,
+                                                  const int32_t* origin, const int32_t* dest, int64_t* route_off,
+                                                  int32_t* route_edges, int64_t capacity, int64_t* n_route_edges) {
+    return guarded(nullptr, [&] {
+        ScratchBufs b{(char*)route_scratch(), kRouteScratchBytes};
         shortest_routes_impl(b, net, edge_cost, n_queries, origin, dest, route_off, route_edges, capacity,
                              n_route_edges);
     });
