@@ -496,7 +496,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="metro",
                     choices=["metro", "perturbed_grid_ring", "grid10x10", "ensemble", "calibration",
-                             "calibration_search", "metro_scale", "reroute"])
+                             "calibration_search", "metro_scale", "reroute", "probe_r"])
     ap.add_argument("--start", type=int, default=-1,
                     help="plain workloads: step of the written start state (default: 08:00, the demand peak)")
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
@@ -557,6 +557,9 @@ def main():
     if args.workload == "metro_scale":
         print(json.dumps(bench_metro_scale(args, M, torch, stream)), flush=True)
         return
+    if args.workload == "probe_r":
+        print(json.dumps(bench_probe_r(args, M, torch, stream)), flush=True)
+        return
     if args.workload == "calibration_search":
         print(json.dumps(bench_calibration_search(args, M, torch, stream)), flush=True)
         return
@@ -604,6 +607,55 @@ def _window(sim, M, torch, stream, steps, progress, kernels_only):
         upd, total_ms, end_state = upd_t, event_ms, sim.state()
     assert upd_t == upd, (upd_t, upd)
     return total_ms, upd, kernel_ms, event_ms, big, end_state
+
+
+def bench_probe_r(args, M, torch, stream):
+    """Roofline probe: the metropolitan network 8 times over in one ensemble
+    handle, every lane filled in steady state at 30 % of jam density (about
+    46M vehicles, every one active), so that the step's data (about 1.3 GB of
+    vehicle records read and written per step) cannot stay in the 256 MB
+    last-level cache.  The state is written, `warmup` steps run untimed, then
+    `steps` steps are timed on the graph path and again kernel by kernel."""
+    import workloads as W
+    t0 = time.perf_counter()
+    copies = 8
+    w, st = W.probe_r(density=0.3)
+    n = w.n_vehicles
+    scen = [(n, np.zeros(0, np.int32))] * copies
+    print(f"probe R: {copies} x {n} vehicles on {copies} x {w.net.n_edges} edges "
+          f"({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    if args.copy_probe > 0:
+        src = torch.ones(args.copy_probe * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.add(src, 0.5, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
+    sim = M.Sim(w, scenarios=scen, stream=stream)
+    sim.write_state(W.replicate_state(st, w.net.n_edges, copies))
+    print(f"handle created and state written ({time.perf_counter() - t0:.1f} s)", file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    torch.cuda.synchronize()
+    active0 = sim.n_active
+    total_ms, upd, kernel_ms, event_ms, big_upd, _ = _window(sim, M, torch, stream, args.steps, args.progress,
+                                                               args.kernels_only)
+    sim.close()
+    tile_ms = kernel_ms["k_tile_step"]
+    achieved = BYTES_PER_UPDATE * (upd - big_upd) / (tile_ms / 1e3) / 1e9
+    return {
+        "metric": "vehicle-updates/sec (1 GPU)", "value": upd / (total_ms / 1e3), "unit": "vehicle-updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": total_ms / args.steps,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "probe_r", "copies": copies, "vehicles": n * copies,
+                   "edges": w.net.n_edges * copies, "density": 0.3, "active_at_timed_start": int(active0),
+                   "steps": args.steps, "vehicle_updates": int(upd)},
+        "roofline": {"bound": "hbm", "kernel": "k_tile_step", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": stored_traffic("probe_r"),
+                     "bytes_per_update": BYTES_PER_UPDATE, "us_per_launch": 1e3 * tile_ms / args.steps,
+                     "big_tile_updates": big_upd},
+        "kernel_us_per_step": {k: round(1e3 * v / args.steps, 3) for k, v in kernel_ms.items()},
+        "event_path_ms_per_step": event_ms / args.steps,
+    }
 
 
 def bench_plain(args, M, torch, stream):

@@ -928,4 +928,72 @@ def loaded_state(w: Workload, t0: int, speed_frac: float = 0.6, gap_m: float = 2
     return state, info
 
 
+# --------------------------------------------------------------------------- roofline probe
+def probe_r(replica_net: Network = None, density: float = 0.3, route_len: int = 12, seed: int = 0,
+            params: Params = None):
+    """A network filled in steady state, to measure the step where its data
+    cannot stay in the last-level cache: on every lane of every edge,
+    vehicles spaced evenly at `density` x jam density (one vehicle per
+    length + 2 m of lane), each at the equilibrium speed of a 1.5 s time
+    headway to the one ahead (at most the limit), all active from step 0.
+    Each vehicle's route starts at its edge and continues `route_len` - 1
+    edges by a random walk over the allowed moves (drawn uniformly).  Four
+    classes as the metropolitan workload.  Returns (workload, state); the
+    state is indexed by vehicle id and written with sim_write_state."""
+    net = replica_net if replica_net is not None else metro_network(seed=seed)
+    p = params or jitter_params(base_params(4, seed), 0.10, seed, purpose=_P_CLASSPAR)
+    r = _rng(seed, _P_PREFILL)
+    vlen = float(p.veh_len.max())
+    jam = vlen + 2.0
+    L = net.length.astype(np.float64)
+    lanes = net.lanes.astype(np.int64)
+    per_lane = np.floor(density * L / jam).astype(np.int64)          # vehicles on each lane of edge e
+    per_edge = per_lane * lanes
+    n = int(per_edge.sum())
+    e_of = np.repeat(np.arange(net.n_edges), per_edge)
+    first = np.concatenate([[0], np.cumsum(per_edge)[:-1]])
+    k_in_edge = np.arange(n) - np.repeat(first, per_edge)
+    pl = np.repeat(per_lane, per_edge)
+    lane = k_in_edge // np.maximum(pl, 1)
+    rank = k_in_edge % np.maximum(pl, 1)                              # 0 = front of the lane
+    spacing = L[e_of] / np.maximum(pl, 1)
+    x = L[e_of] - (rank + 0.5) * spacing
+    gap = spacing - vlen
+    v = np.clip(np.minimum(net.limit.astype(np.float64)[e_of], (gap - 2.0) / 1.5), 0.0, None)
+    # random-walk routes over the allowed moves
+    deg = np.diff(net.conn_off).astype(np.int64)
+    routes = np.empty((n, route_len), np.int32)
+    cur = e_of.astype(np.int64)
+    routes[:, 0] = cur
+    for k in range(1, route_len):
+        pick = np.floor(r.random(n) * deg[cur]).astype(np.int64)
+        cur = net.conn_to[net.conn_off[cur] + pick].astype(np.int64)
+        routes[:, k] = cur
+    route_off = np.arange(n + 1, dtype=np.int64) * route_len
+    vclass = r.integers(0, p.n_classes, size=n).astype(np.uint8)
+    alpha = r.uniform(0.05, 0.40, size=n).astype(np.float32)
+    w = Workload(f"probe_r_d{density}", net, route_off, routes.ravel(), np.zeros(n, np.int32), vclass, alpha, p,
+                 route_len * 8, info={"density": density, "vehicles": n})
+    state = dict(status=np.ones(n, np.uint8), edge=e_of.astype(np.int32), lane=lane.astype(np.int32),
+                 cursor=np.zeros(n, np.int32), x=x.astype(np.float32), v=v.astype(np.float32),
+                 held_since=np.full(n, -1, np.int32), mand=np.zeros(n, np.uint8), ww=np.zeros(n, np.int32),
+                 tau_in=np.zeros(n), t_arr=np.full(n, -1.0), counters=None, t=0)
+    return w, state
+
+
+def replicate_state(state: dict, n_edges: int, copies: int) -> dict:
+    """The state of an ensemble whose scenarios all take the whole master
+    demand: scenario k's vehicles follow scenario k - 1's, on its own copy of
+    the network (edge ids shifted by k x n_edges)."""
+    out = {}
+    for key, a in state.items():
+        if key in ("t", "counters"):
+            out[key] = a
+        elif key == "edge":
+            out[key] = np.concatenate([a + k * n_edges for k in range(copies)]).astype(np.int32)
+        else:
+            out[key] = np.concatenate([a] * copies)
+    return out
+
+
 CONFIGS = {"grid10x10": config1, "perturbed_grid_ring": config2, "metro": config3}
