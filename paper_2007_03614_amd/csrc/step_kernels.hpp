@@ -1187,51 +1187,65 @@ __device__ inline void grid_barrier(const Dev& d, unsigned* counter, bool releas
     __syncthreads();
 }
 
+// Admission of the request of lane i's front (eligibility, then the claim
+// of the target lane, or in case 1 the node's crossing key).
+template <int NT>
+__device__ inline void admit_request(const Dev& d, int i, int t) {
+    const Outbox ob = d.outbox[i];
+    if (ob.target < 0) return;                    // an arrival
+    bool ok = transfer_eligible(d, ob, t);
+    if (d.imode == 1) {
+        // case 1: only after standing stop_steps at the line (the key's
+        // step is the held-since step, t if not held); one crossing per
+        // node, its (in, out) pairs served round-robin after the last
+        // served one: key = (distance in the cycle, held since, source lane)
+        const int e = d.s[t & 1].edge[ob.slot], f = ob.nxt;
+        const int node = d.efrom[f], nmv = d.nm[node];
+        const int pr = d.pair_base[e] + d.out_idx[f];
+        int dd = (pr - d.rr[node] - 1) % nmv;
+        if (dd < 0) dd += nmv;
+        const int hs = (int)(ob.key >> 32);
+        ok = ok && t - hs >= d.stop_steps;
+        const unsigned long long nk = ((unsigned long long)dd << 58) |
+                                      ((unsigned long long)(uint32_t)hs << 26) | (unsigned long long)i;
+        d.outbox[i].key = nk;
+        d.outbox[i].elig = ok ? 1 + node : 0;
+        d.outbox[i].tl_cls = ob.tl_cls | ((uint32_t)pr << 16);
+        if (ok) atomicMin(&d.win_node[node], nk);
+        return;
+    }
+    d.outbox[i].elig = ok ? 1 : 0;
+    if (ok) claim(d, ob.target, ob.key, t);
+}
+
 // One item per lane (its front may have asked to leave the edge this step)
 // and one per departure queue.  A request is eligible if it does not overlap
 // the target lane's rear after the move; a due queue head if the lane's rear
-// leaves it s0 at x = 0.
+// leaves it s0 at x = 0.  Each thread takes its items four at a time and
+// loads their stamps (queue heads) together, so that the loads overlap.
 template <int NT>
 __device__ inline void admit_items(const Dev& d, int t) {
-    const int nl = d.n_lanes_total;
-    const int total = nl + d.nq;
-    for (int i = blockIdx.x * NT + threadIdx.x; i < total; i += gridDim.x * NT) {
-        if (i < nl) {
-            if (d.req_stamp[i] != t) continue;            // most lanes: one 4-byte load
-            const Outbox ob = d.outbox[i];
-            if (ob.target < 0) continue;                  // an arrival
-            bool ok = transfer_eligible(d, ob, t);
-            if (d.imode == 1) {
-                // case 1: only after standing stop_steps at the line (the key's
-                // step is the held-since step, t if not held); one crossing per
-                // node, its (in, out) pairs served round-robin after the last
-                // served one: key = (distance in the cycle, held since, source lane)
-                const int e = d.s[t & 1].edge[ob.slot], f = ob.nxt;
-                const int node = d.efrom[f], nmv = d.nm[node];
-                const int pr = d.pair_base[e] + d.out_idx[f];
-                int dd = (pr - d.rr[node] - 1) % nmv;
-                if (dd < 0) dd += nmv;
-                const int hs = (int)(ob.key >> 32);
-                ok = ok && t - hs >= d.stop_steps;
-                const unsigned long long nk = ((unsigned long long)dd << 58) |
-                                              ((unsigned long long)(uint32_t)hs << 26) | (unsigned long long)i;
-                d.outbox[i].key = nk;
-                d.outbox[i].elig = ok ? 1 + node : 0;
-                d.outbox[i].tl_cls = ob.tl_cls | ((uint32_t)pr << 16);
-                if (ok) atomicMin(&d.win_node[node], nk);
-                continue;
-            }
-            d.outbox[i].elig = ok ? 1 : 0;
-            if (ok) claim(d, ob.target, ob.key, t);
-        } else {
-            const int q = i - nl;
-            const int2 hd = d.qhd[q];
-            if (hd.x <= t) {
-                const int gl = d.qlane[q];
-                const LanePost p = d.post[gl];
-                if (p.stamp != t || p.rear_xm >= d.qs0[q])
-                    claim(d, gl, (1ull << 63) | ((unsigned long long)(uint32_t)hd.x << 32) | (uint32_t)hd.y, t);
-            }
+    constexpr int kU = 4;
+    const int nl = d.n_lanes_total, nq = d.nq;
+    const int stride = gridDim.x * NT;
+    for (int i0 = blockIdx.x * NT + threadIdx.x; i0 < nl; i0 += kU * stride) {
+        int st[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) st[u] = i0 + u * stride < nl ? d.req_stamp[i0 + u * stride] : -1;
+        for (int u = 0; u < kU; ++u)
+            if (st[u] == t) admit_request<NT>(d, i0 + u * stride, t);
+    }
+    for (int q0 = blockIdx.x * NT + threadIdx.x; q0 < nq; q0 += kU * stride) {
+        int2 hd[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) hd[u] = q0 + u * stride < nq ? d.qhd[q0 + u * stride] : make_int2(INT_MAX, -1);
+        for (int u = 0; u < kU; ++u) {
+            if (hd[u].x > t) continue;
+            const int q = q0 + u * stride;
+            const int gl = d.qlane[q];
+            const LanePost p = d.post[gl];
+            if (p.stamp != t || p.rear_xm >= d.qs0[q])
+                claim(d, gl, (1ull << 63) | ((unsigned long long)(uint32_t)hd[u].x << 32) | (uint32_t)hd[u].y, t);
         }
     }
 }
@@ -1526,7 +1540,9 @@ __device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* 
     const int* boff;
     int nnew;
     if (kLds) {
-        nnew = scan_block_sums<kNT>(d.blk_sum, d.n_blk, soff, wsh4, totp);
+        // every block sum loaded at once into LDS and scanned there (one round:
+        // at most kScanLdsMax blocks take this path)
+        nnew = scan_block_sums_staged<kNT>(d.blk_sum, d.n_blk, soff, soff, kScanLdsMax, wsh4, totp);
         boff = soff;
         if (blockIdx.x == 0 && threadIdx.x == 0) finish_step(d, t, par, nnew);
     } else {
