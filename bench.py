@@ -159,30 +159,34 @@ def cpu_baseline(w, state0, warmup: int, steps: int, threads: int):
             "vehicle_updates": int(upd), "s": dt}, s.counters(), s.state()
 
 
-def summarize_pmc(directory: str) -> dict:
+def summarize_pmc(directory: str, last: int = 0) -> dict:
     """Per-kernel means of the counters in a `rocprofv3 --pmc --output-format
-    csv` directory: {kernel: {"dispatches": n, counter: mean per dispatch}}.
-    Device copies (`__amd_rocclr_copyBuffer`) are kept per grid size, so a
-    copy of known size can calibrate byte counters."""
+    csv` directory: {kernel: {"dispatches": n, counter: mean per dispatch}};
+    with last > 0 over each kernel's last `last` dispatches only (the timed
+    window of a run stepped untimed to its start).  Device copies
+    (`__amd_rocclr_copyBuffer`) are kept per grid size, so a copy of known
+    size can calibrate byte counters."""
     import csv
     import glob
     files = glob.glob(os.path.join(directory, "**", "*counter_collection.csv"), recursive=True)
-    acc = {}
+    rows = {}
     for fn in files:
         with open(fn, newline="") as f:
             for row in csv.DictReader(f):
                 name = row.get("Kernel_Name", "?")
                 if "copyBuffer" in name:
                     name = f"{name} grid={row.get('Grid_Size', '?')}"
-                key = (name, row.get("Counter_Name", "?"))
-                a = acc.setdefault(key, [0.0, 0, set()])
-                a[0] += float(row.get("Counter_Value", 0.0))
-                a[1] += 1
+                did = next((row[k] for k in row if k and k.lower() in ("dispatch_id", "dispatch_index")), "0")
+                rows.setdefault((name, row.get("Counter_Name", "?")), []).append(
+                    (int(did), float(row.get("Counter_Value", 0.0))))
     out = {}
-    for (name, ctr), (tot, n, _) in acc.items():
+    for (name, ctr), vals in rows.items():
+        vals.sort()
+        if last > 0:
+            vals = vals[-last:]
         k = out.setdefault(name, {})
-        k["dispatches"] = max(k.get("dispatches", 0), n)
-        k[ctr] = tot / n
+        k["dispatches"] = max(k.get("dispatches", 0), len(vals))
+        k[ctr] = sum(v for _, v in vals) / len(vals)
     return {"files": len(files), "kernels": out}
 
 
@@ -496,7 +500,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--workload", default="metro",
                     choices=["metro", "perturbed_grid_ring", "grid10x10", "ensemble", "calibration",
-                             "calibration_search", "metro_scale", "reroute", "probe_r"])
+                             "calibration_search", "metro_scale", "reroute", "probe_r", "reroute_metro"])
     ap.add_argument("--start", type=int, default=-1,
                     help="plain workloads: step of the written start state (default: 08:00, the demand peak)")
     ap.add_argument("--reps", type=int, default=2, help="calibration: timed repetitions after one warm-up")
@@ -519,14 +523,14 @@ def main():
     ap.add_argument("--summarize-pmc", metavar="DIR", help="summarize a rocprofv3 --pmc csv directory and exit")
     ap.add_argument("--summarize-trace", metavar="DIR",
                     help="summarize a rocprofv3 --kernel-trace csv directory (see --last) and exit")
-    ap.add_argument("--last", type=int, default=0, help="--summarize-trace: also the mean of each kernel's "
-                                                         "last LAST dispatches")
+    ap.add_argument("--last", type=int, default=0, help="--summarize-trace / --summarize-pmc: the mean of each "
+                                                         "kernel's last LAST dispatches")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_JSON", "WRITE_JSON"),
                     help="combine two --summarize-pmc outputs into the traffic record and exit")
     args = ap.parse_args()
     args.steps_given = "--steps" in sys.argv
     if args.summarize_pmc:
-        print(json.dumps(summarize_pmc(args.summarize_pmc), indent=1))
+        print(json.dumps(summarize_pmc(args.summarize_pmc, args.last), indent=1))
         return
     if args.summarize_trace:
         print(json.dumps(summarize_trace(args.summarize_trace, args.last), indent=1))
@@ -556,6 +560,9 @@ def main():
         return
     if args.workload == "metro_scale":
         print(json.dumps(bench_metro_scale(args, M, torch, stream)), flush=True)
+        return
+    if args.workload == "reroute_metro":
+        print(json.dumps(bench_reroute_metro(args, M, torch, stream)), flush=True)
         return
     if args.workload == "probe_r":
         print(json.dumps(bench_probe_r(args, M, torch, stream)), flush=True)
@@ -607,6 +614,42 @@ def _window(sim, M, torch, stream, steps, progress, kernels_only):
         upd, total_ms, end_state = upd_t, event_ms, sim.state()
     assert upd_t == upd, (upd_t, upd)
     return total_ms, upd, kernel_ms, event_ms, big, end_state
+
+
+def bench_reroute_metro(args, M, torch, stream):
+    """Routes of the metropolitan demand on the GPU: every one of its 3.2M
+    trips routed by sim_shortest_routes on free-flow costs (224,202 nodes,
+    16,321 distinct destinations, labels in device memory), timed end to end
+    (host copies included).  The CPU side is the generator's multithreaded
+    Dijkstra (per destination) on a sample of the trips."""
+    import workloads as W
+    w = W.config3()
+    net = w.net
+    cost = (net.length / net.limit).astype(np.float32)
+    o = net.edge_from[w.route_edges[w.route_off[:-1]]].astype(np.int32)
+    d = net.edge_to[w.route_edges[w.route_off[1:] - 1]].astype(np.int32)
+    M.shortest_routes(net, cost, o[:2000], d[:2000])            # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    off, edges = M.shortest_routes(net, cost, o, d)
+    t1 = time.perf_counter()
+    line = {
+        "metric": "routes/s (sim_shortest_routes, 1 GPU)", "value": o.size / (t1 - t0), "unit": "routes/s",
+        "n_gpus": 1, "steps": 0, "warmup": 1, "ms_per_step": None, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": "reroute_metro", "queries": int(o.size), "destinations": int(np.unique(d).size),
+                   "nodes": int(net.n_nodes), "edges": int(net.n_edges), "route_edges": int(edges.size),
+                   "s": t1 - t0},
+    }
+    if args.cpu_steps > 0:
+        k = 200_000
+        t2 = time.perf_counter()
+        W.shortest_routes_to(net, o[:k], d[:k])
+        t3 = time.perf_counter()
+        line["cpu_baseline"] = {"value": k / (t3 - t2), "unit": "routes/s", "cores": min(16, os.cpu_count() or 1),
+                                "kind": "generator Dijkstra (per destination, binary heap, FP64 costs)",
+                                "sample": f"the first {k} trips", **cpu_info()}
+    return line
 
 
 def bench_probe_r(args, M, torch, stream):

@@ -261,8 +261,11 @@ sim_status sim_destroy(sim_handle *h);
  * U-turns every route is a valid route for sim_create.
  * Output (host memory): route_off [n_queries + 1] and route_edges [capacity];
  * *n_route_edges is set to the total even when capacity is too small (then
- * SIM_EINVAL).  Errors: SIM_EINVAL (bad input, origin == destination, no
- * route), SIM_EUNSUPPORTED (more than 16,000 nodes), SIM_ENOMEM, SIM_EDEVICE.
+ * SIM_EINVAL).  Up to 16,000 nodes the labels of a destination sit in one
+ * workgroup's LDS; above, in device memory (4 bytes x nodes x distinct
+ * destinations, at most 16 GB).  Errors: SIM_EINVAL (bad input, origin ==
+ * destination, no route), SIM_EUNSUPPORTED (labels above 16 GB), SIM_ENOMEM,
+ * SIM_EDEVICE.
  * Needs no handle; runs on the current device and synchronises it. */
 sim_status sim_shortest_routes(const sim_network *net, const float *edge_cost, int32_t n_queries,
                                const int32_t *origin, const int32_t *dest, int64_t *route_off,

@@ -1503,6 +1503,7 @@ sim_status sim_probe_draws(uint64_t seed, const int64_t* t, const int64_t* id, f
 namespace {
 struct DevBufs {   // device buffers of one routing call, freed on every exit
     std::vector<void*> p;
+    size_t left() const { return SIZE_MAX; }
     template <class T>
     T* get(size_t n) {
         void* q = nullptr;
@@ -1522,6 +1523,7 @@ namespace {
 struct ScratchBufs {
     char* base;
     size_t cap, used = 0;
+    size_t left() const { return cap - used; }
     template <class T>
     T* get(size_t n) {
         const size_t bytes = (std::max<size_t>(n, 1) * sizeof(T) + 255) & ~(size_t)255;
@@ -1545,7 +1547,6 @@ void shortest_routes_impl(B& b, const sim_network* net, const float* edge_cost, 
         if (n_queries > 0 && (!origin || !dest)) bad("null argument");
         const int V = net->n_nodes, E = net->n_edges;
         if (V <= 0 || E <= 0 || !net->edge_from || !net->edge_to) bad("network must have nodes and edges");
-        if (V > kRouteMaxNodes) throw Fail{SIM_EUNSUPPORTED, fmt("more than %d nodes", kRouteMaxNodes)};
         for (int e = 0; e < E; ++e) {
             if (net->edge_from[e] < 0 || net->edge_from[e] >= V || net->edge_to[e] < 0 || net->edge_to[e] >= V)
                 bad(fmt("edge %d: node out of range", e));
@@ -1595,7 +1596,25 @@ void shortest_routes_impl(B& b, const sim_network* net, const float* edge_cost, 
         int max_deg = 0;
         for (int v = 0; v < V; ++v) max_deg = std::max(max_deg, out_off[v + 1] - out_off[v]);
         const dim3 gd(std::min(nd, 2048));
-        if (max_deg <= 8) {   // padded adjacency, slot-major: [j * V + v]
+        if (V > kRouteMaxNodes) {   // labels in global memory, relaxed from a frontier
+            std::vector<int> in_off(V + 1, 0), in_edge(E), fill_in(V, 0);
+            for (int e = 0; e < E; ++e) ++in_off[net->edge_to[e] + 1];
+            for (int v = 0; v < V; ++v) in_off[v + 1] += in_off[v];
+            for (int e = 0; e < E; ++e) in_edge[in_off[net->edge_to[e]] + fill_in[net->edge_to[e]]++] = e;
+            int* d_ioff = b.template get<int>(V + 1);
+            int* d_iedge = b.template get<int>(E);
+            int* d_from = b.template get<int>(E);
+            HIP_OK(hipMemcpy(d_ioff, in_off.data(), 4 * (size_t)(V + 1), hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d_iedge, in_edge.data(), 4 * (size_t)E, hipMemcpyHostToDevice));
+            HIP_OK(hipMemcpy(d_from, net->edge_from, 4 * (size_t)E, hipMemcpyHostToDevice));
+            // frontier (2 V) and marks (V) per workgroup, as many workgroups as fit
+            const size_t per_wg = 3 * 4 * (size_t)V + 512;
+            const int g = (int)std::max<size_t>(1, std::min<size_t>({(size_t)nd, (size_t)1024, b.left() / per_wg}));
+            int* d_fq = b.template get<int>((size_t)g * 2 * V);
+            int* d_mk = b.template get<int>((size_t)g * V);
+            hipLaunchKernelGGL(k_route_dist_global, dim3(g), dim3(kRouteNT), 0, 0, V, d_ioff, d_iedge, d_from, d_cost,
+                               d_dest, nd, d_dist, d_fq, d_mk);
+        } else if (max_deg <= 8) {   // padded adjacency, slot-major: [j * V + v]
             const int km = max_deg <= 4 ? 4 : 8;
             std::vector<int> pto((size_t)km * V);
             std::vector<float> pcost((size_t)km * V);

@@ -164,6 +164,77 @@ __global__ void __launch_bounds__(kRouteNT) k_route_dist_regs(int V, const int* 
     }
 }
 
+// Networks above kRouteMaxNodes: one workgroup per destination with its
+// labels in global memory (row q of dist_out), relaxed from a frontier -- the
+// nodes whose label dropped in the last round push the drop to the tails of
+// their in-edges (a label-correcting search; with positive costs it ends at
+// the same binary32 fixed point as any other relaxation order, see above).
+// A node enters the next frontier once per round (mark holds the round of
+// its last push).  Labels are positive floats, so their bit patterns order
+// like the values and atomicMin on the integer view takes the minimum.
+// Labels, marks and frontier entries are read and written only by atomics
+// at device scope (performed in L2, never served stale from a CU's L1), and
+// every thread waits for its memory operations before each barrier.
+// Per workgroup: frontier space 2 * V and marks V (fq, mk at blockIdx * V).
+__device__ inline int ld_l2(const int* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_l2(int* p, int v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void settle_and_sync() {
+    __builtin_amdgcn_s_waitcnt(0);   // this thread's loads, stores and atomics are done
+    __syncthreads();
+}
+
+__global__ void __launch_bounds__(kRouteNT) k_route_dist_global(int V, const int* in_off, const int* in_edge,
+                                                               const int* edge_from, const float* cost,
+                                                               const int* dests, int nd, float* dist_out, int* fq,
+                                                               int* mk) {
+    __shared__ int n_next;
+    int* fa = fq + (size_t)blockIdx.x * 2 * V;
+    int* fb = fa + V;
+    int* mark = mk + (size_t)blockIdx.x * V;
+    for (int q = blockIdx.x; q < nd; q += gridDim.x) {
+        const int d = dests[q];
+        int* idist = (int*)(dist_out + (size_t)q * V);
+        for (int v = threadIdx.x; v < V; v += kRouteNT) {
+            st_l2(&idist[v], __float_as_int(v == d ? 0.0f : INFINITY));
+            st_l2(&mark[v], -1);
+        }
+        if (threadIdx.x == 0) {
+            st_l2(&fa[0], d);
+            n_next = 0;
+        }
+        settle_and_sync();
+        int n_cur = 1;
+        int* cur = fa;
+        int* nxt = fb;
+        for (int round = 0; n_cur > 0; ++round) {
+            for (int i = threadIdx.x; i < n_cur; i += kRouteNT) {
+                const int u = ld_l2(&cur[i]);
+                const float du = __int_as_float(ld_l2(&idist[u]));
+                for (int k = in_off[u]; k < in_off[u + 1]; ++k) {
+                    const int e = in_edge[k];
+                    const int v = edge_from[e];
+                    const float c = cost[e] + du;
+                    const int old = atomicMin(&idist[v], __float_as_int(c));
+                    if (c < __int_as_float(old) && atomicExch(&mark[v], round) != round)
+                        st_l2(&nxt[atomicAdd(&n_next, 1)], v);
+                }
+            }
+            settle_and_sync();
+            n_cur = n_next;
+            __syncthreads();   // every thread has read the count before it is reset
+            if (threadIdx.x == 0) n_next = 0;
+            int* t = cur;
+            cur = nxt;
+            nxt = t;
+        }
+        __syncthreads();
+    }
+}
+
 // One thread per query: walk from the origin to the destination over the
 // labels of its destination (slot).  fill == 0: write the number of edges to
 // len[q] (-1: origin == destination, unreachable, or longer than V edges);

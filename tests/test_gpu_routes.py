@@ -139,18 +139,60 @@ def test_reroute_future_departures_continues_like_the_oracle(M, oracle_mod):
 def test_routes_at_the_node_limit(M, oracle_mod):
     """A 125 x 128 grid has 16,000 nodes, the most whose labels one
     workgroup's LDS holds: routes on perturbed costs still equal the oracle's
-    (corner to corner, about 250 edges).  One node more is refused."""
+    (corner to corner, about 250 edges)."""
     net = W.grid_network(125, 128)
     assert net.n_nodes == 16000
     cost = ((net.length / net.limit) * np.random.default_rng(9).uniform(0.5, 2.0, net.n_edges)).astype(np.float32)
     o = np.array([0, 127, 8000, 15999, 15872, 64], np.int32)
     d = np.array([15999, 15872, 15999, 0, 127, 8000], np.int32)
     _check(M, oracle_mod, net, cost, o, d)
-    big = W.grid_network(127, 127)
-    assert big.n_nodes > 16000
-    with pytest.raises(M.SimError):
-        M.shortest_routes(big, np.full(big.n_edges, 1.0, np.float32), np.array([0], np.int32),
-                          np.array([5], np.int32))
+
+
+@pytest.mark.parametrize("which", ["grid", "metro"])
+def test_routes_above_the_node_limit_equal_the_oracle(M, oracle_mod, which):
+    """Above 16,000 nodes the labels live in device memory and are relaxed
+    from a frontier: a 127 x 127 grid (16,129 nodes) and the metropolitan
+    recipe on a 130 x 131 lattice (17,030 nodes), routes edge for edge equal
+    to the oracle's on perturbed costs."""
+    if which == "grid":
+        net = W.grid_network(127, 127)
+    else:
+        net = W.metro_network(rows=130, cols=131, n_segments=int(round(274_504 * 130 * 131 / (473 * 474))), seed=4)
+    assert net.n_nodes > 16000
+    cost = ((net.length / net.limit) * np.random.default_rng(13).uniform(0.5, 2.0, net.n_edges)).astype(np.float32)
+    rng = np.random.default_rng(14)
+    V = net.n_nodes
+    o = np.concatenate([[0, V - 1], rng.integers(0, V, 18)]).astype(np.int32)
+    d = np.concatenate([[V - 1, 0], rng.integers(0, V, 18)]).astype(np.int32)
+    d[o == d] = (d[o == d] + 1) % V
+    _check(M, oracle_mod, net, cost, o, d)
+
+
+def test_routes_for_the_metropolitan_demand(M):
+    """The full metropolitan network (224,202 nodes): the GPU's routes for
+    4,000 of its trips on free-flow costs are continuous, join origin to
+    destination, and cost (binary32, summed from the destination back) no
+    more than the generator's CPU route of the same trip -- they are the
+    shortest in that arithmetic, so any other route costs at least as much."""
+    w = W.config3()
+    net = w.net
+    cost = (net.length / net.limit).astype(np.float32)
+    sel = np.random.default_rng(15).choice(w.n_vehicles, 4000, replace=False)
+    o = net.edge_from[w.route_edges[w.route_off[sel]]].astype(np.int32)
+    d = net.edge_to[w.route_edges[w.route_off[sel + 1] - 1]].astype(np.int32)
+    off, edges = M.shortest_routes(net, cost, o, d)
+
+    def c32(r):
+        acc = np.float32(0.0)
+        for e in r[::-1]:
+            acc = np.float32(cost[e] + acc)
+        return acc
+    for q in range(sel.size):
+        r = edges[off[q]:off[q + 1]]
+        assert net.edge_from[r[0]] == o[q] and net.edge_to[r[-1]] == d[q]
+        assert (net.edge_to[r[:-1]] == net.edge_from[r[1:]]).all()
+        ref = w.route_edges[w.route_off[sel[q]]:w.route_off[sel[q] + 1]]
+        assert c32(r) <= c32(ref), q
 
 
 def _grid_with_hub(n_spokes):
