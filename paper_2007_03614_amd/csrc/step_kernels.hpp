@@ -713,11 +713,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 const uint32_t mask = f < 0 ? 0xFFu : m_mask(m);
                 bool desire = !allowed_l && (lane_distance(mask, lp) < lane_distance(mask, l));
                 const bool allowed_lp = lane_allowed(m, f, lp);
-                if (!desire && allowed_lp && !(m_mand(m) && !allowed_l)) {
+                const int lc = (q > 0 && b.el[q - 1] == el) ? q - 1 : -1;
+                // with no leader in its own lane a vehicle already has the free
+                // acceleration, which no leader in the other lane can beat
+                // (Eq. (1) only subtracts from it): no incentive to compute
+                if (!desire && allowed_lp && !(m_mand(m) && !allowed_l) && lc >= 0) {
                     const float v0 = cpi.v0f * b.lim[q];
                     unsigned br = 0;
                     float acc_cur, acc_new;
-                    const int lc = (q > 0 && b.el[q - 1] == el) ? q - 1 : -1;
                     if (lc >= 0) {
                         const float s = (b.x[lc] - scp[m_cls(b.meta[lc])].len) - xi;
                         acc_cur = idm_acc(vi, v0, b.v[lc], s, cpi, kVeh, br);
@@ -821,54 +824,72 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const int f = b.nxt[q];
         const int lanes_e = (int)(b.lanes2[q] & 255u);
         const uint32_t e0 = el & ~15u;
-        // leader candidates and rank in the post-change lane
-        int c1 = -1, c2 = -1, rank;
-        const int mu = lam - dir;   // lane whose movers enter lam
+        // leader and position in the post-change order.  On an edge where no
+        // vehicle changes lanes (most edges of a step) both stay as in S_t:
+        // the leader is the vehicle before in the same run, the position q.
         const int k0 = b.rk[q];
         const int rs = b.run_st[k0];
-        int sl;                     // start of lam's run in S_t (lower bound if empty)
+        int j, newpos, lane_start;
+        bool quiet = false;
         if (!mv) {
-            sl = rs;
-            if (q > 0 && b.lasts[q - 1] >= rs) c1 = b.lasts[q - 1];
-            int mov_ahead = 0;
-            if (mu >= 0 && mu < lanes_e) {
-                const uint32_t emu = e0 | (uint32_t)mu;
-                const int kmu = run_lower(b, nruns, k0, emu);
-                const int st = b.run_st[kmu];
-                const int p2 = (b.run_el[kmu] == emu) ? run_insert(b, st, b.run_st[kmu + 1], xi, id) : st;
-                if (p2 > 0 && b.lastm[p2 - 1] >= st) c2 = b.lastm[p2 - 1];
-                mov_ahead = b.mpref[p2] - b.mpref[st];
+            const int es_q = b.run_st[run_lower(b, nruns, k0, e0)];
+            const int ee_q = b.run_st[run_lower(b, nruns, k0, e0 + 16u)];   // first slot of the next edge
+            quiet = b.mpref[ee_q] == b.mpref[es_q];
+            if (quiet) {
+                j = q > rs ? q - 1 : -1;
+                newpos = q;
+                lane_start = rs;
             }
-            rank = ((q - rs) - (b.mpref[q] - b.mpref[rs])) + mov_ahead;
-        } else {
-            const int p = b.pos[q];
-            const int st = b.run_st[run_lower(b, nruns, k0, elam)];
-            sl = st;
-            if (p > 0 && b.lasts[p - 1] >= st) c1 = b.lasts[p - 1];
-            if (q > 0 && b.lastm[q - 1] >= rs) c2 = b.lastm[q - 1];
-            rank = ((p - st) - (b.mpref[p] - b.mpref[st])) + (b.mpref[q] - b.mpref[rs]);
         }
-        int j = c1;
-        if (c2 >= 0) {
-            if (j < 0) j = c2;
-            else if (b.x[c2] < b.x[j] || (b.x[c2] == b.x[j] && b.vid[c2] < b.vid[j])) j = c2;
+        if (!quiet) {
+            // leader candidates and rank in the post-change lane
+            int c1 = -1, c2 = -1, rank;
+            const int mu = lam - dir;   // lane whose movers enter lam
+            int sl;                     // start of lam's run in S_t (lower bound if empty)
+            if (!mv) {
+                sl = rs;
+                if (q > 0 && b.lasts[q - 1] >= rs) c1 = b.lasts[q - 1];
+                int mov_ahead = 0;
+                if (mu >= 0 && mu < lanes_e) {
+                    const uint32_t emu = e0 | (uint32_t)mu;
+                    const int kmu = run_lower(b, nruns, k0, emu);
+                    const int st = b.run_st[kmu];
+                    const int p2 = (b.run_el[kmu] == emu) ? run_insert(b, st, b.run_st[kmu + 1], xi, id) : st;
+                    if (p2 > 0 && b.lastm[p2 - 1] >= st) c2 = b.lastm[p2 - 1];
+                    mov_ahead = b.mpref[p2] - b.mpref[st];
+                }
+                rank = ((q - rs) - (b.mpref[q] - b.mpref[rs])) + mov_ahead;
+            } else {
+                const int p = b.pos[q];
+                const int st = b.run_st[run_lower(b, nruns, k0, elam)];
+                sl = st;
+                if (p > 0 && b.lasts[p - 1] >= st) c1 = b.lasts[p - 1];
+                if (q > 0 && b.lastm[q - 1] >= rs) c2 = b.lastm[q - 1];
+                rank = ((p - st) - (b.mpref[p] - b.mpref[st])) + (b.mpref[q] - b.mpref[rs]);
+            }
+            j = c1;
+            if (c2 >= 0) {
+                if (j < 0) j = c2;
+                else if (b.x[c2] < b.x[j] || (b.x[c2] == b.x[j] && b.vid[c2] < b.vid[j])) j = c2;
+            }
+            // post-change vehicles of this edge in lanes below lam
+            const int es = b.run_st[run_lower(b, nruns, k0, e0)];
+            int below = sl - es;
+            if (dir < 0) {
+                const int ee = b.run_st[run_lower(b, nruns, k0, elam + 1)];
+                below += b.mpref[ee] - b.mpref[sl];
+            } else if (lam >= 1) {
+                const int s0 = b.run_st[run_lower(b, nruns, k0, elam - 1)];
+                below -= b.mpref[sl] - b.mpref[s0];
+            }
+            newpos = es + below + rank;
+            lane_start = es + below;
         }
-        // post-change vehicles of this edge in lanes below lam
-        const int es = b.run_st[run_lower(b, nruns, k0, e0)];
-        int below = sl - es;
-        if (dir < 0) {
-            const int ee = b.run_st[run_lower(b, nruns, k0, elam + 1)];
-            below += b.mpref[ee] - b.mpref[sl];
-        } else if (lam >= 1) {
-            const int s0 = b.run_st[run_lower(b, nruns, k0, elam - 1)];
-            below -= b.mpref[sl] - b.mpref[s0];
-        }
-        const int newpos = es + below + rank;
         if (newpos < 0 || newpos >= n) {   // cannot happen if the layout is consistent
             atomicOr(&d.ctl->err, kErrNewPos);
             continue;
         }
-        b.moved[q] = es + below;   // start of the post-change lane's run (moved[q] is not read again)
+        b.moved[q] = lane_start;   // start of the post-change lane's run (moved[q] is not read again)
 
         // kind and gap (A1-A8, A17)
         const ClassParams cpi = scp[m_cls(m)];
