@@ -140,7 +140,9 @@ sim_status sim_set_allocator(void *(*alloc)(size_t bytes, void *ctx),
  * (from(f) == to(e)) with a non-empty lane mask inside the lanes of e, every
  * route non-empty with consecutive edges joined by a move, depart_step >= 0,
  * class ids in range, alpha finite in [0, 0.40], parameters finite and in the
- * bounds above.  Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_EUNSUPPORTED. */
+ * bounds above.  Errors: SIM_EINVAL, SIM_ENOMEM, SIM_EDEVICE, SIM_EUNSUPPORTED (also for
+ * 2^24 lanes or more in all, or an edge that could hold more than 32,767
+ * vehicles at the shortest vehicle length). */
 sim_status sim_create(const sim_network *net, const sim_routes *routes, const sim_idm_params *params,
                       sim_handle **out);
 

@@ -396,6 +396,20 @@ sim_status sim_create(const sim_network* net, const sim_routes* r, const sim_idm
 }  // extern "C"
 
 namespace {
+// Workgroups of a kernel whose LDS fits one CU, with each workgroup's LDS
+// rounded up to 1 KiB: the occupancy query alone has reported one workgroup
+// more than fits for a tile kernel just below a sixth of the CU's LDS, and a
+// persistent grid sized on that runs its surplus workgroups in a second wave.
+int lds_fit(const void* kernel, int dev) {
+    hipFuncAttributes fa;
+    HIP_OK(hipFuncGetAttributes(&fa, kernel));
+    int lds_cu = 0;
+    HIP_OK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
+    const size_t per = (fa.sharedSizeBytes + 1023) / 1024 * 1024;
+    if (per == 0 || lds_cu <= 0) return INT_MAX;
+    return std::max(1, (int)((size_t)lds_cu / per));
+}
+
 // rng_id: per-vehicle draw id (null: the vehicle id); edge_period: the
 // draws keyed by an edge use the edge id modulo this (the edges of one
 // scenario in an ensemble's union network, else the edge count)
@@ -422,6 +436,8 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 h->lane_base[e + 1] = h->lane_base[e] + net->n_lanes[e];
             }
             const int NL = h->lane_base[E];
+            if (NL >= (1 << kLaneBaseBits))   // a lane index and a lane count share one word in the tiles
+                throw Fail{SIM_EUNSUPPORTED, fmt("%d lanes: at most %d", NL, (1 << kLaneBaseBits) - 1)};
             h->n_lanes = NL;
             const int NC = net->conn_off[E];
             h->conn_off.assign(net->conn_off, net->conn_off + E + 1);
@@ -587,12 +603,15 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             for (int e = 0; e < E; ++e)
                 max_edge = std::max(max_edge, (long long)h->lanes[e] * ((long long)(h->L[e] / len_min) + 1));
             const long long cap_all = std::min<long long>(std::max(N, 1), (long long)kTileWindowMax - 1 + max_edge);
+            if (cap_all > kTileIndexMax)
+                throw Fail{SIM_EUNSUPPORTED, fmt("a tile may hold %lld vehicles: at most %d", cap_all, kTileIndexMax)};
             d.big_cap = (int)std::max<long long>(kTileCapLds + 1, cap_all);
             {   // tile workgroups resident at once on this device
                 int dev = 0, cus = 0, per_cu = 0;
                 HIP_OK(hipGetDevice(&dev));
                 HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
                 HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_tile_step, kTileNT, 0));
+                per_cu = std::min(per_cu, lds_fit((const void*)k_tile_step, dev));
                 d.tile_target = std::max(1, cus * std::max(per_cu, 1));
             }
             d.tile_window = 0;
@@ -603,6 +622,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 HIP_OK(hipGetDevice(&dev));
                 HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
                 HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_big_admit, kBigNT, 0));
+                per_cu = std::min(per_cu, lds_fit((const void*)k_big_admit, dev));
                 h->g_big_max = std::max(1, cus * std::max(per_cu, 1));
                 const long long items = (long long)NL + (long long)h->nq;
                 h->g_big_min = (int)std::max(1LL, std::min<long long>(h->g_big_max, (items + kBigNT - 1) / kBigNT));

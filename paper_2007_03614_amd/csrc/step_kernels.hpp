@@ -14,7 +14,7 @@
 //   k_tile_step   Phases 1-2 per tile of whole edges, staged in LDS
 //   k_big_admit   the same for tiles above 384 vehicles (1,024 threads), then
 //                 eligibility + atomicMin of a 64-bit priority key per lane
-//   k_commit      eight threads per edge, one per lane: winners, losers,
+//   k_commit      one thread per edge, over its lanes: winners, losers,
 //                 arrivals, departures, travel-time sums, new lane counts and
 //                 edge offsets within the workgroup
 //   (k_blkscan    offsets of the commit workgroups, on large networks)
@@ -33,7 +33,8 @@ constexpr int kNT = 256;                 // threads per workgroup (4 waves)
 constexpr int kWaves = kNT / 64;
 constexpr int kTileWindowMax = 256;      // a tile = the edges whose first slot lies in a window of
 constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256)
-constexpr int kTileCapLds = 384;         // tiles up to this size are staged in LDS (4 workgroups per CU)
+constexpr int kTileCapLds = 304;         // tiles up to this size are staged in LDS (6 workgroups per CU)
+constexpr int kTileIndexMax = 32767;     // vehicles of a tile at most (16-bit indices in LDS)
 constexpr int kTileNT = 256;             // threads per tile workgroup
 constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
@@ -41,7 +42,7 @@ constexpr int kCommitLanes = 8;         // lanes of an edge at most
 constexpr int kCommitNT = 256;           // threads per commit workgroup
 constexpr int kEdgeBlock = kCommitNT;    // edges per commit workgroup (one thread per edge)
 constexpr int kBigNT = 1024;             // threads per workgroup for tiles above kTileCapLds
-constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (138 KiB)
+constexpr int kBigCapLds = 1408;         // vehicles per big tile piece staged in LDS (110 KiB)
 constexpr unsigned long long kBarrierTimeout = 20000000ull;   // 0.2 s of the 100 MHz clock
 constexpr int kScanLdsMax = 8192;        // edge blocks whose offsets k_scatter scans in LDS (32 KiB)
 constexpr int kCounterCopies = 1024;     // each counter is spread over 1,024 slots (few colliding atomics)
@@ -268,11 +269,10 @@ struct TileBuf {
     uint32_t* el;       // edge << 4 | lane (S_t)
     uint32_t* meta;
     int* nxt;
-    int* pos;           // Phase 1: insertion point in the target lane's run
-    int* moved;
+    int* pm;            // Phase 1: insertion point in the target lane's run | decision code << 16;
+                        //   Phase 2: start of the post-change lane's run
     int* mpref;         // movers before index q (n + 1 entries)
-    int* lastm;         // last mover at or before q in the tile, or -1
-    int* lasts;         // last stayer at or before q, or -1
+    int* lml;           // last mover (low 16 bits) and last stayer (high 16 bits) at or before q, or -1
     int* rk;            // index of q's run (maximal group of one edge and lane in S_t)
     uint32_t* run_el;   // per run: edge << 4 | lane; run_el[nruns] = ~0
     int* run_st;        // per run: first index; run_st[nruns] = n
@@ -284,13 +284,19 @@ struct TileBuf {
     // per-vehicle copies of its edge's constants, loaded with the vehicle so
     // that later phases find them in LDS
     float* L;           // edge length
-    float* lim;         // edge speed limit
-    uint32_t* lanes2;   // lanes of the edge | lanes of the next edge << 8
-    int* lbe;           // first global lane of the edge
-    int* lbf;           // first global lane of the next edge (0 if none)
+    float* lim;         // edge speed limit; after Phase 2 the vehicle's new speed
+    uint32_t* lbe;      // first global lane of the edge | its lanes << 24
+    uint32_t* lbf;      // the same for the next edge (0 if none)
 };
 
-constexpr int kTileBytesPerVeh = 92;   // 23 four-byte arrays (plus a few words within the 64-byte slack)
+// lane words: first global lane (below 2^24) and lane count in one word
+constexpr int kLaneBaseBits = 24;
+__device__ inline int lw_base(uint32_t w) { return (int)(w & ((1u << kLaneBaseBits) - 1u)); }
+__device__ inline int lw_lanes(uint32_t w) { return (int)(w >> kLaneBaseBits); }
+__device__ inline int lastm_of(const int* lml, int i) { return (int)(short)(lml[i] & 0xFFFF); }
+__device__ inline int lasts_of(const int* lml, int i) { return lml[i] >> 16; }
+
+constexpr int kTileBytesPerVeh = 80;   // 20 four-byte arrays (plus a few words within the 64-byte slack)
 __host__ __device__ inline size_t tile_bytes(int cap) { return (size_t)cap * kTileBytesPerVeh + 64; }
 
 __device__ inline TileBuf carve(char* base, int cap) {
@@ -303,11 +309,9 @@ __device__ inline TileBuf carve(char* base, int cap) {
     b.el = (uint32_t*)take(cap);
     b.meta = (uint32_t*)take(cap);
     b.nxt = (int*)take(cap);
-    b.pos = (int*)take(cap);
-    b.moved = (int*)take(cap);
+    b.pm = (int*)take(cap);
     b.mpref = (int*)take(cap + 1);
-    b.lastm = (int*)take(cap);
-    b.lasts = (int*)take(cap);
+    b.lml = (int*)take(cap);
     b.rk = (int*)take(cap);
     b.run_el = (uint32_t*)take(cap + 1);
     b.run_st = (int*)take(cap + 1);
@@ -318,9 +322,8 @@ __device__ inline TileBuf carve(char* base, int cap) {
     b.inv = (int*)take(cap);
     b.L = (float*)take(cap);
     b.lim = (float*)take(cap);
-    b.lanes2 = (uint32_t*)take(cap);
-    b.lbe = (int*)take(cap);
-    b.lbf = (int*)take(cap);
+    b.lbe = (uint32_t*)take(cap);
+    b.lbf = (uint32_t*)take(cap);
     return b;
 }
 
@@ -546,7 +549,7 @@ __device__ inline float uniform_of_word(uint32_t w) {
 // twelve uniforms minus 6) and binary32 rounding is monotone, so the noise
 // decides only when G is within 6 m of c.
 constexpr int kGapNo = 0, kGapYes = 1, kGapDraw = 2;
-constexpr int kPending = 2, kDrawA = 4, kDrawB = 8;   // Phase 1 states of b.moved
+constexpr int kPending = 2, kDrawA = 4, kDrawB = 8;   // Phase 1 decision codes (b.pm >> 16)
 
 __device__ inline int gap_outcome(float G, float c) {
     if (G < c - 6.0f) return kGapNo;
@@ -562,11 +565,11 @@ __device__ inline bool gap_with_noise(float G, float c, int word_sum) {
 }
 
 // The lane-change decision of vehicle q once its noise is drawn (Eqs. (3)-(4)):
-// b.moved[q] becomes 0 or 1.
+// its decision code becomes 0 or 1.
 __device__ inline void finish_pending(const TileBuf& b, int q, int dir, const float* Ga, const float* ca,
                                       const float* Gb, const float* cb, const int* na, const int* nb,
                                       CounterAcc& acc) {
-    const int code = b.moved[q];
+    const int code = b.pm[q] >> 16;
     if (!(code & kPending)) return;
     bool ok = true;
     if (code & kDrawA) ok = gap_with_noise(Ga[q], ca[q], na[q]);
@@ -579,7 +582,7 @@ __device__ inline void finish_pending(const TileBuf& b, int q, int dir, const fl
         const int lp = (int)(b.el[q] & 15u) + dir;
         if (lane_allowed(m, b.nxt[q], lp)) b.meta[q] = m & ~((1u << 4) | (127u << 8));
     }
-    b.moved[q] = moved;
+    b.pm[q] = (b.pm[q] & 0xFFFF) | (moved << 16);
 }
 
 // ---- Phases 1-2 for one tile ----------------------------------------------
@@ -599,9 +602,9 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     // workgroup at once, in two rounds: the uniforms of Eq. (2), listed while
     // S_t is loaded, then the noise of Eqs. (3)-(4), whose need depends on the
     // mandatory flag.
-    int* const u1 = b.lastm;                      // Eq. (2) uniform words (scratch until the scans)
-    int* const na = b.lasts;                      // noise word sums, leading side
-    int* const nb = b.mpref;                      // noise word sums, lagging side
+    int* const u1 = b.pm;                         // Eq. (2) uniform words (read before Phase 1 writes pm)
+    int* const na = b.mpref;                      // noise word sums, leading side (scratch until the scans)
+    int* const nb = b.lml;                        // noise word sums, lagging side
     float* const Ga = b.xn;                       // gaps and critical gaps of pending decisions
     float* const ca = (float*)b.fl;               // (scratch until Phase 2)
     float* const Gb = (float*)b.pel;
@@ -623,9 +626,8 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         const EdgeC cf = f >= 0 ? d.ec[f] : EdgeC{0.0f, 0.0f, 0, 0};
         const float L = ce.L;
         b.L[q] = L;
-        b.lbe[q] = ce.lane_base;
-        b.lanes2[q] = (uint32_t)ce.lanes | ((uint32_t)cf.lanes << 8);
-        b.lbf[q] = cf.lane_base;
+        b.lbe[q] = (uint32_t)ce.lane_base | ((uint32_t)ce.lanes << kLaneBaseBits);
+        b.lbf[q] = (uint32_t)cf.lane_base | ((uint32_t)cf.lanes << kLaneBaseBits);
         b.lim[q] = ce.lim;
         u1[q] = 0;
         na[q] = 0;
@@ -703,7 +705,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 }
             }
             const int lp = l + dir;
-            if (lp >= 0 && lp < (int)(b.lanes2[q] & 255u)) {
+            if (lp >= 0 && lp < lw_lanes(b.lbe[q])) {
                 const uint32_t elp = (el & ~15u) | (uint32_t)lp;
                 const int kp = run_lower(b, nruns, b.rk[q], elp);
                 pos = b.run_st[kp];
@@ -773,8 +775,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 }
             }
         }
-        b.moved[q] = moved;
-        b.pos[q] = pos;
+        b.pm[q] = pos | (moved << 16);   // u1[q] (the same word) was read above
         // only this vehicle's own mandatory/wait bits change; its class bits,
         // which neighbours read, stay the same
         b.meta[q] = m;
@@ -792,18 +793,17 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         for (int q = lo; q < hi; ++q) {
             // the decisions waiting for noise are finished by the thread that scans them
             finish_pending(b, q, dir, Ga, ca, Gb, cb, na, nb, acc);
-            const int mv = b.moved[q];
+            const int mv = b.pm[q] >> 16;
             loc.s += mv;
             if (mv) loc.a = q; else loc.b = q;
         }
         Scan4 run = wg_exclusive_scan4<NT>(loc, wsh4);
         for (int q = lo; q < hi; ++q) {
-            const int mv = b.moved[q];
+            const int mv = b.pm[q] >> 16;
             b.mpref[q] = run.s;
             run.s += mv;
             if (mv) run.a = q; else run.b = q;
-            b.lastm[q] = run.a;
-            b.lasts[q] = run.b;
+            b.lml[q] = (int)(((uint32_t)run.a & 0xFFFFu) | ((uint32_t)run.b << 16));
         }
         if (hi == n && lo < hi) b.mpref[n] = run.s;
         if (n == 0 && tid == 0) b.mpref[0] = 0;
@@ -815,14 +815,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     for (int q = tid; q < n; q += NT) {
         const uint32_t el = b.el[q];
         const int e = (int)(el >> 4), l = (int)(el & 15u);
-        const int mv = b.moved[q];
+        const int mv = b.pm[q] >> 16;
         const int lam = mv ? l + dir : l;
         const uint32_t elam = (el & ~15u) | (uint32_t)lam;
         const float xi = b.x[q], vi = b.v[q];
         const uint32_t id = b.vid[q];
         uint32_t m = b.meta[q];
         const int f = b.nxt[q];
-        const int lanes_e = (int)(b.lanes2[q] & 255u);
+        const int lanes_e = lw_lanes(b.lbe[q]);
         const uint32_t e0 = el & ~15u;
         // leader and position in the post-change order.  On an edge where no
         // vehicle changes lanes (most edges of a step) both stay as in S_t:
@@ -848,23 +848,23 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             int sl;                     // start of lam's run in S_t (lower bound if empty)
             if (!mv) {
                 sl = rs;
-                if (q > 0 && b.lasts[q - 1] >= rs) c1 = b.lasts[q - 1];
+                if (q > 0 && lasts_of(b.lml, q - 1) >= rs) c1 = lasts_of(b.lml, q - 1);
                 int mov_ahead = 0;
                 if (mu >= 0 && mu < lanes_e) {
                     const uint32_t emu = e0 | (uint32_t)mu;
                     const int kmu = run_lower(b, nruns, k0, emu);
                     const int st = b.run_st[kmu];
                     const int p2 = (b.run_el[kmu] == emu) ? run_insert(b, st, b.run_st[kmu + 1], xi, id) : st;
-                    if (p2 > 0 && b.lastm[p2 - 1] >= st) c2 = b.lastm[p2 - 1];
+                    if (p2 > 0 && lastm_of(b.lml, p2 - 1) >= st) c2 = lastm_of(b.lml, p2 - 1);
                     mov_ahead = b.mpref[p2] - b.mpref[st];
                 }
                 rank = ((q - rs) - (b.mpref[q] - b.mpref[rs])) + mov_ahead;
             } else {
-                const int p = b.pos[q];
+                const int p = b.pm[q] & 0xFFFF;
                 const int st = b.run_st[run_lower(b, nruns, k0, elam)];
                 sl = st;
-                if (p > 0 && b.lasts[p - 1] >= st) c1 = b.lasts[p - 1];
-                if (q > 0 && b.lastm[q - 1] >= rs) c2 = b.lastm[q - 1];
+                if (p > 0 && lasts_of(b.lml, p - 1) >= st) c1 = lasts_of(b.lml, p - 1);
+                if (q > 0 && lastm_of(b.lml, q - 1) >= rs) c2 = lastm_of(b.lml, q - 1);
                 rank = ((p - st) - (b.mpref[p] - b.mpref[st])) + (b.mpref[q] - b.mpref[rs]);
             }
             j = c1;
@@ -889,7 +889,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             atomicOr(&d.ctl->err, kErrNewPos);
             continue;
         }
-        b.moved[q] = lane_start;   // start of the post-change lane's run (moved[q] is not read again)
+        b.pm[q] = lane_start;   // start of the post-change lane's run (pm[q] is not read again)
 
         // kind and gap (A1-A8, A17)
         const ClassParams cpi = scp[m_cls(m)];
@@ -910,14 +910,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             s = b.L[q] - xi;
             vl = 0.0f;
         } else {
-            const int lf = min(lam, (int)(b.lanes2[q] >> 8) - 1);
-            const LaneRear r = d.rear[b.lbf[q] + lf];
+            const int lf = min(lam, lw_lanes(b.lbf[q]) - 1);
+            const LaneRear r = d.rear[lw_base(b.lbf[q]) + lf];
             if (r.stamp == t) {
                 kind = kLook;
                 s = (b.L[q] - xi) + r.xm;
                 vl = r.v;
                 partner = (int)r.vid;
-                look_gl = b.lbf[q] + lf;
+                look_gl = lw_base(b.lbf[q]) + lf;
             } else {
                 kind = kFree;
             }
@@ -965,7 +965,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         S.nxt[dst] = f;
         b.xn[q] = xnew;
         b.fl[q] = fl;
-        b.pos[q] = __float_as_int(vnew);   // pos[q] is read only by this thread, above
+        b.lim[q] = vnew;   // lim[q] is read only by this thread, above
         if (d.trace) {
             TraceRec tr;
             tr.vid = id;
@@ -996,10 +996,10 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                 atomicOr(&d.ctl->err, kErrPermutation);
             } else {
                 const int lam = (int)(el & 15u);
-                const int gl = b.lbe[q] + lam;
+                const int gl = lw_base(b.lbe[q]) + lam;
                 const float xnew = b.xn[q];
                 if (rear) {
-                    const int fr = b.moved[q];
+                    const int fr = b.pm[q];
                     LanePost lp;
                     lp.stamp = t;
                     lp.start = a0 + fr;
@@ -1016,7 +1016,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                     ob.slot = a0 + r;
                     ob.vid = b.vid[q];
                     ob.phi = (xnew == xo) ? 0.0f : (b.L[q] - xo) / (xnew - xo);
-                    ob.v = __int_as_float(b.pos[q]);
+                    ob.v = b.lim[q];
                     ob.nxt = f;
                     if (f < 0) {
                         ob.target = -1;
@@ -1024,8 +1024,8 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
                         ob.key = 0;
                         ob.tl_cls = 0;
                     } else {
-                        const int tl = min(lam, (int)(b.lanes2[q] >> 8) - 1);
-                        ob.target = b.lbf[q] + tl;
+                        const int tl = min(lam, lw_lanes(b.lbf[q]) - 1);
+                        ob.target = lw_base(b.lbf[q]) + tl;
                         ob.tl_cls = (uint32_t)tl | (m_cls(b.meta[q]) << 8);
                         ob.xp = xnew - b.L[q];
                         const int hs = m_held(b.meta[q]) ? d.held_since[ob.vid] : t;
@@ -1107,9 +1107,14 @@ __device__ inline void tile_step(const Dev& d) {
     flush_counters_lds(d, acc, shc);
 }
 
-__global__ void __launch_bounds__(kTileNT) k_tile_step(Dev d) { tile_step<false>(d); }
+// six workgroups per CU: at most 80 VGPRs, which the kernel fits without spills
+__global__ void __launch_bounds__(kTileNT) __attribute__((amdgpu_waves_per_eu(6))) k_tile_step(Dev d) {
+    tile_step<false>(d);
+}
 // the same with per-driver free-flow limits (v0_spread > 0)
-__global__ void __launch_bounds__(kTileNT) k_tile_step_v0spread(Dev d) { tile_step<true>(d); }
+__global__ void __launch_bounds__(kTileNT) __attribute__((amdgpu_waves_per_eu(6))) k_tile_step_v0spread(Dev d) {
+    tile_step<true>(d);
+}
 
 // Tiles above kTileCapLds: 1,024-thread workgroups with kBigCapLds vehicles
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
