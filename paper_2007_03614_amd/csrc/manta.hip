@@ -322,6 +322,8 @@ void load_state(sim_handle* h, const void* src, int t) {
         HIP_OK(hipMemcpyAsync(p, (const char*)src + o, b, hipMemcpyDeviceToDevice, h->stream));
         o += (b + 255) & ~(size_t)255;
     });
+    // big-tile marks of steps at or after t belong to the run being replaced
+    HIP_OK(hipMemsetAsync(h->d.big_lane, 0xFF, sizeof(int2) * (size_t)h->n_lanes, h->stream));
     h->t = t;
 }
 
@@ -668,6 +670,8 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.ctl = h->dev<Ctl>(1);
             d.counters = h->dev<unsigned long long>(cNumCounters * kCounterCopies);
             d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindowMin + 2));
+            d.big_lane = h->dev<int2>(NL);
+            d.big_defer = h->dev<unsigned long long>((size_t)NL + (size_t)h->nq);   // each item at most once
             d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big_max);
             // ---- initial values
             HIP_OK(hipMemset(d.rear, 0xFF, sizeof(LaneRear) * NL));
@@ -677,6 +681,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * NL));
             HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
+            HIP_OK(hipMemset(d.big_lane, 0xFF, sizeof(int2) * NL));
             HIP_OK(hipMemset(d.tt_sum, 0, sizeof(double) * E));
             HIP_OK(hipMemset(d.tt_cnt, 0, sizeof(unsigned long long) * E));
             HIP_OK(hipMemset(d.ctl, 0, sizeof(Ctl)));
@@ -990,6 +995,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         HIP_OK(hipMemset(d.win, 0xFF, sizeof(unsigned long long) * h->n_lanes));
         HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
+        HIP_OK(hipMemset(d.big_lane, 0xFF, sizeof(int2) * h->n_lanes));   // no big-tile marks of other runs
         if (d.imode == 1) {                        // the round-robin restarts
             HIP_OK(hipMemset(d.rr, 0xFF, sizeof(int) * (size_t)d.n_nodes));
             HIP_OK(hipMemset(d.win_node, 0xFF, sizeof(unsigned long long) * (size_t)d.n_nodes));

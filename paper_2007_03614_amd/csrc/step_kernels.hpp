@@ -80,8 +80,8 @@ struct Ctl {
     int n_big[2];     // tiles above kTileCapLds, listed for k_big_admit
     int err;          // non-zero: a layout bound check failed (see kErr*)
     int n_departed;   // vehicles admitted from the departure queues so far
-    unsigned big_done;   // workgroups of k_big_admit past their big tiles (steps with big tiles)
-    int pad0;
+    unsigned big_done;   // workgroups of k_big_admit past their admission pass or their big tiles
+    int n_defer;      // admission items left to the workgroups of the big tiles (this step)
     unsigned long long big_updates;   // vehicle-updates done in big tiles (measurement)
     int pad[2];
 };
@@ -248,6 +248,8 @@ struct Dev {
     // big tiles: (first, end) slot pairs, and global scratch for single
     // edges beyond the LDS of a workgroup
     int* big_list;
+    int2* big_lane;             // [lane] {step, big tile} of the last step the lane's edge was in a big tile
+    unsigned long long* big_defer;   // admission items whose target lane is in a big tile: tile << 32 | item
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
     // traced re-run of a segment that starts at a multiple of trace_period:
@@ -1040,6 +1042,20 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
 }
 
+// The lanes of a big tile's edges, stamped with the step and the tile's index
+// in the big-tile list: admission leaves requests into them to the
+// workgroup of that tile, which writes their post-move rears.
+template <int NT>
+__device__ inline void mark_big_lanes(const Dev& d, const int32_t* edge, int a0, int a1, int t, int k) {
+    for (int s = a0 + (int)threadIdx.x; s < a1; s += NT) {
+        const int e = edge[s];
+        if (s == a0 || edge[s - 1] != e) {
+            const EdgeC c = d.ec[e];
+            for (int l = 0; l < c.lanes; ++l) d.big_lane[c.lane_base + l] = make_int2(t, k);
+        }
+    }
+}
+
 // Tile window of a step with n active vehicles: fixed by the schedule, or
 // (0) the smallest of 64 and 128 slots whose tiles fit in one round of
 // resident workgroups.
@@ -1079,6 +1095,7 @@ __device__ inline void tile_step(const Dev& d) {
         d.ctl->t_b = t;
         d.ctl->n_big[par ^ 1] = 0;
         d.ctl->big_done = 0;
+        d.ctl->n_defer = 0;
         if (d.trace) d.nact_hist[t % d.trace_period] = n;
     }
     __syncthreads();
@@ -1098,10 +1115,16 @@ __device__ inline void tile_step(const Dev& d) {
         }
         if (cnt <= kTileCapLds) {
             process_tile<kTileNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
-        } else if (threadIdx.x == 0) {
-            const int q = atomicAdd(&d.ctl->n_big[par], 1);
-            d.big_list[2 * q] = a0;
-            d.big_list[2 * q + 1] = a1;
+        } else {
+            if (threadIdx.x == 0) {
+                const int q = atomicAdd(&d.ctl->n_big[par], 1);
+                d.big_list[2 * q] = a0;
+                d.big_list[2 * q + 1] = a1;
+                wsh[0] = q;
+            }
+            __syncthreads();
+            mark_big_lanes<kTileNT>(d, edge, a0, a1, t, wsh[0]);
+            __syncthreads();                        // wsh is reused by the next tile
         }
     }
     flush_counters_lds(d, acc, shc);
@@ -1119,7 +1142,7 @@ __global__ void __launch_bounds__(kTileNT) __attribute__((amdgpu_waves_per_eu(6)
 // Tiles above kTileCapLds: 1,024-thread workgroups with kBigCapLds vehicles
 // of LDS; a tile is cut at edge boundaries into pieces that fit, and only a
 // single edge larger than the LDS runs from the global-memory scratch.
-__device__ inline void big_tiles(const Dev& d, int t, int par, int nbig) {
+__device__ __forceinline__ void big_tiles(const Dev& d, int t, int par, int nbig) {
     __shared__ __align__(16) char lds[kBigCapLds * kTileBytesPerVeh + 64];
     __shared__ Scan4 wsh4[kBigNT / 64];
     __shared__ int wsh[kBigNT / 64];
@@ -1213,12 +1236,29 @@ __device__ inline void grid_barrier(const Dev& d, unsigned* counter, bool releas
     __syncthreads();
 }
 
+// An item whose target lane is in big tile k: listed for that tile's workgroup.
+__device__ inline void defer_item(const Dev& d, int k, int item) {
+    const int slot = atomicAdd(&d.ctl->n_defer, 1);
+    d.big_defer[slot] = ((unsigned long long)(uint32_t)k << 32) | (uint32_t)item;
+}
+
 // Admission of the request of lane i's front (eligibility, then the claim
-// of the target lane, or in case 1 the node's crossing key).
-template <int NT>
+// of the target lane, or in case 1 the node's crossing key).  kDefer: lane i
+// in a big tile is left out (that tile's workgroup writes its request and
+// admits it), and a target lane in a big tile is left to that tile's
+// workgroup.
+template <int NT, bool kDefer>
 __device__ inline void admit_request(const Dev& d, int i, int t) {
+    if (kDefer && d.big_lane[i].x == t) return;
     const Outbox ob = d.outbox[i];
     if (ob.target < 0) return;                    // an arrival
+    if (kDefer) {
+        const int2 bl = d.big_lane[ob.target];
+        if (bl.x == t) {
+            defer_item(d, bl.y, i);
+            return;
+        }
+    }
     bool ok = transfer_eligible(d, ob, t);
     if (d.imode == 1) {
         // case 1: only after standing stop_steps at the line (the key's
@@ -1244,51 +1284,126 @@ __device__ inline void admit_request(const Dev& d, int i, int t) {
     if (ok) claim(d, ob.target, ob.key, t);
 }
 
+// Admission of a due departure-queue head (departure step hd.x, id hd.y):
+// it claims the queue's lane if the lane's rear leaves it s0 at x = 0.
+template <bool kDefer>
+__device__ inline void admit_head(const Dev& d, int q, int2 hd, int t) {
+    const int gl = d.qlane[q];
+    if (kDefer) {
+        const int2 bl = d.big_lane[gl];
+        if (bl.x == t) {
+            defer_item(d, bl.y, d.n_lanes_total + q);
+            return;
+        }
+    }
+    const LanePost p = d.post[gl];
+    if (p.stamp != t || p.rear_xm >= d.qs0[q])
+        claim(d, gl, (1ull << 63) | ((unsigned long long)(uint32_t)hd.x << 32) | (uint32_t)hd.y, t);
+}
+
 // One item per lane (its front may have asked to leave the edge this step)
-// and one per departure queue.  A request is eligible if it does not overlap
-// the target lane's rear after the move; a due queue head if the lane's rear
-// leaves it s0 at x = 0.  Each thread takes its items four at a time and
-// loads their stamps (queue heads) together, so that the loads overlap.
-template <int NT>
-__device__ inline void admit_items(const Dev& d, int t) {
+// and one per departure queue, over workgroups wg of nwg.  A request is
+// eligible if it does not overlap the target lane's rear after the move; a
+// due queue head if the lane's rear leaves it s0 at x = 0.  Each thread takes
+// its items four at a time and loads their stamps (queue heads) together, so
+// that the loads overlap.
+// The four stamps are read into one bit mask of due items, so that no
+// per-thread array is indexed by a runtime value (which would put it in
+// scratch memory).
+template <int NT, bool kDefer>
+__device__ inline void admit_items(const Dev& d, int t, int wg, int nwg) {
     constexpr int kU = 4;
     const int nl = d.n_lanes_total, nq = d.nq;
-    const int stride = gridDim.x * NT;
-    for (int i0 = blockIdx.x * NT + threadIdx.x; i0 < nl; i0 += kU * stride) {
-        int st[kU];
+    const int stride = nwg * NT;
+    for (int i0 = wg * NT + threadIdx.x; i0 < nl; i0 += kU * stride) {
+        unsigned due = 0;
 #pragma unroll
-        for (int u = 0; u < kU; ++u) st[u] = i0 + u * stride < nl ? d.req_stamp[i0 + u * stride] : -1;
-        for (int u = 0; u < kU; ++u)
-            if (st[u] == t) admit_request<NT>(d, i0 + u * stride, t);
-    }
-    for (int q0 = blockIdx.x * NT + threadIdx.x; q0 < nq; q0 += kU * stride) {
-        int2 hd[kU];
-#pragma unroll
-        for (int u = 0; u < kU; ++u) hd[u] = q0 + u * stride < nq ? d.qhd[q0 + u * stride] : make_int2(INT_MAX, -1);
         for (int u = 0; u < kU; ++u) {
-            if (hd[u].x > t) continue;
+            const int i = i0 + u * stride;
+            if (i < nl && d.req_stamp[i] == t) due |= 1u << u;
+        }
+        while (due) {
+            const int u = __builtin_ctz(due);
+            due &= due - 1;
+            admit_request<NT, kDefer>(d, i0 + u * stride, t);
+        }
+    }
+    for (int q0 = wg * NT + threadIdx.x; q0 < nq; q0 += kU * stride) {
+        unsigned due = 0;
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
             const int q = q0 + u * stride;
-            const int gl = d.qlane[q];
-            const LanePost p = d.post[gl];
-            if (p.stamp != t || p.rear_xm >= d.qs0[q])
-                claim(d, gl, (1ull << 63) | ((unsigned long long)(uint32_t)hd[u].x << 32) | (uint32_t)hd[u].y, t);
+            if (q < nq && d.qhd[q].x <= t) due |= 1u << u;
+        }
+        while (due) {
+            const int q = q0 + __builtin_ctz(due) * stride;
+            due &= due - 1;
+            admit_head<kDefer>(d, q, d.qhd[q], t);
         }
     }
 }
 
-// The tiles above one workgroup's LDS, then admission, in one launch (one
-// launch less per step).  Admission reads the post-move rears that big tiles
-// write, so on a step with big tiles all workgroups meet at a grid barrier in
-// between; most steps have none and skip it.
+// Admission that waits for big tile k: the requests of the tile's own lanes
+// and the items other workgroups left to it.  The workgroup first counts
+// itself done and waits until every workgroup has (the admission workgroups
+// after listing their items, the other big tiles after writing their
+// requests and rears), like the grid barrier and bounded the same way.
+__device__ inline void admit_big_tile(const Dev& d, int t, int par, int k) {
+    grid_barrier(d, &d.ctl->big_done, true);
+    const int a0 = d.big_list[2 * k], a1 = d.big_list[2 * k + 1];
+    const int32_t* edge = d.s[par].edge;
+    for (int s = a0 + (int)threadIdx.x; s < a1; s += kBigNT) {
+        const int e = edge[s];
+        if (s == a0 || edge[s - 1] != e) {
+            const EdgeC c = d.ec[e];
+            for (int l = 0; l < c.lanes; ++l)
+                if (d.req_stamp[c.lane_base + l] == t) admit_request<kBigNT, false>(d, c.lane_base + l, t);
+        }
+    }
+    const int nd = __hip_atomic_load(&d.ctl->n_defer, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int nl = d.n_lanes_total;
+    for (int j = threadIdx.x; j < nd; j += kBigNT) {
+        const unsigned long long en = __hip_atomic_load(&d.big_defer[j], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if ((int)(en >> 32) != k) continue;
+        const int item = (int)(uint32_t)en;
+        if (item < nl) admit_request<kBigNT, false>(d, item, t);
+        else admit_head<false>(d, item - nl, d.qhd[item - nl], t);
+    }
+}
+
+// The tiles above one workgroup's LDS, and admission, in one launch (one
+// launch less per step).  Admission reads the requests of the source lanes
+// and the post-move rears of the target lanes, which big tiles write.  With
+// fewer big tiles than workgroups, the workgroups past the big tiles take the
+// admission items of every other lane and queue, leave those whose target
+// lane is in a big tile to that tile's workgroup, make the list visible and
+// count themselves done without waiting; each big-tile workgroup, after its
+// tile, waits until all have counted and admits its own lanes' requests and
+// the items left to it.  Otherwise (every workgroup has a big tile) all of
+// them meet at a grid barrier between the tiles and admission.
 __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
     const int2 nb2 = *(const int2*)d.ctl->n_big;   // independent of the step number load
     const int t = d.ctl->t_a, par = t & 1;
     const int nbig = par ? nb2.y : nb2.x;
-    if (nbig > 0) {
-        big_tiles(d, t, par, nbig);
-        grid_barrier(d, &d.ctl->big_done, (int)blockIdx.x < nbig);   // workgroups that had a big tile
+    const bool all_big = nbig >= (int)gridDim.x;
+    if (nbig == 0) {
+        admit_items<kBigNT, false>(d, t, blockIdx.x, gridDim.x);
+    } else if (all_big || (int)blockIdx.x < nbig) {
+        big_tiles(d, t, par, nbig);                 // one call site: inlined, no call frame
+        if (all_big) {
+            grid_barrier(d, &d.ctl->big_done, true);
+            admit_items<kBigNT, false>(d, t, blockIdx.x, gridDim.x);
+        } else {
+            admit_big_tile(d, t, par, blockIdx.x);  // tile blockIdx.x
+        }
+    } else {
+        admit_items<kBigNT, true>(d, t, blockIdx.x - nbig, gridDim.x - nbig);
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            __threadfence();                        // the listed items first
+            atomicAdd(&d.ctl->big_done, 1u);
+        }
     }
-    admit_items<kBigNT>(d, t);
 }
 
 // One thread per edge, over its lanes (most edges have one or two).  For a

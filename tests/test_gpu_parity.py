@@ -172,6 +172,75 @@ def test_parity_dense_queue_big_tiles(M, oracle_mod):
     assert g.big_tile_updates() == c["active_sum"]
 
 
+def _long_edge_grid(n=12000, t0=2400, seed=7):
+    """A 3x3 grid of 2,500 m two-lane edges (a lane holds up to 333 vehicles
+    7.5 m apart), uniform O/D routes, departures U[0, 1,500 s).  The state at
+    t0 is built from the demand at 15 % of the limit, so most edges are dense
+    queues: tiles above the LDS cap ask to move into other big tiles and into
+    ordinary tiles, ordinary lanes ask to move into big tiles, and departures
+    still due wait at the entry lanes of big tiles."""
+    net = W.grid_network(rows=3, cols=3, spacing=2500.0, lanes=2)
+    r = np.random.default_rng(seed)
+    o = r.integers(0, net.n_nodes, n)
+    d = (o + r.integers(1, net.n_nodes, n)) % net.n_nodes
+    route_off, route_edges, ok = W.shortest_routes(net, o, d)
+    assert ok.all()
+    dep = r.integers(0, 3000, n).astype(np.int32)
+    w = W.Workload("long_edge_grid", net, route_off, route_edges, dep, np.zeros(n, np.uint8),
+                   r.uniform(0.05, 0.40, n).astype(np.float32), W.base_params(1), 0)
+    init, _ = W.loaded_state(w, t0, speed_frac=0.15)
+    return w, init
+
+
+def _schedule_cache(tmp_path, w, g):
+    """A schedule cache whose lines (one per size of the admission grid, the
+    largest valid one applied last) give k_big_admit more workgroups than the
+    network has edges, hence than big tiles."""
+    p = tmp_path / "sched.txt"
+    sch = g.schedule()
+    with open(p, "w") as f:
+        for g2 in (2, 4, 8, 16, 32, 64, 128, 256, 512, 1024):
+            f.write(f"manta-schedule E={w.net.n_edges} L={int(w.net.lanes.sum())} N={w.n_vehicles} S=1 -> "
+                    f"0 {sch[1]} {g2} {sch[3]}\n")
+    return str(p)
+
+
+@pytest.mark.parametrize("spread_admission", [False, True])
+def test_parity_big_tiles_with_transfers(M, oracle_mod, tmp_path, spread_admission):
+    """Big tiles that exchange vehicles with each other and with ordinary
+    tiles, and take departures, bit for bit with the oracle: with one
+    admission workgroup (every workgroup has a big tile: grid barrier, then
+    admission) and with more admission workgroups than big tiles (admission
+    of the other lanes alongside the big tiles, the rest by each tile's own
+    workgroup)."""
+    w, init = _long_edge_grid()
+    g = M.Sim(w)
+    if spread_admission:
+        g.autotune(_schedule_cache(tmp_path, w, g))
+        assert g.schedule()[2] > w.net.n_edges
+    else:
+        assert g.schedule()[2] == 1
+    o = oracle_mod.OracleSim(w)
+    g.write_state(init)
+    o.write_state(init["t"], init)
+    t = init["t"]
+    c0 = o.counters()
+    for cp in (t + 1, t + 2, t + 50, t + 200, t + 600):
+        g.step(cp - t)
+        o.step(cp - t)
+        t = cp
+        gs, os_ = g.state(), o.state()
+        assert compare_states(gs, os_, f"step {t}")
+        gc = dict(zip(M.COUNTERS, gs["counters"].tolist()))
+        assert gc == o.counters(), f"step {t}: counters {gc} vs {o.counters()}"
+    c = o.counters()
+    assert g.big_tile_updates() > 0
+    assert c["transfers"] > c0["transfers"] and c["departed"] > c0["departed"], (c0, c)
+    gsum, gcnt = g.edge_stats()
+    osum, ocnt = o.edge_stats()
+    assert np.array_equal(gcnt, ocnt) and np.array_equal(gsum, osum)
+
+
 def test_parity_scaled_config2(M, oracle_mod):
     """Config 2's recipe on a 30x30 grid + ring with 15,000 vehicles, full 3 h."""
     w = W.scaled_config2(n_vehicles=15000, rows=30, cols=30, n_steps=21600)
