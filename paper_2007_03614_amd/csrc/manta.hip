@@ -643,6 +643,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 d.s[b].edge = h->dev<int32_t>(NV);
                 d.s[b].meta = h->dev<uint32_t>(NV);
                 d.s[b].nxt = h->dev<int32_t>(NV);
+                d.s[b].gl = h->dev<int32_t>(NV);
             }
             d.ent = h->dev<EntryRec>(NL);
             d.status = h->dev<uint8_t>(NV);
@@ -660,9 +661,8 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.win = h->dev<unsigned long long>(NL);
             d.exit_stamp = h->dev<int>(NL);
             d.enter_stamp = h->dev<int>(NL);
-            d.lane_rel = h->dev<int>(NL);
+            d.lane_off = h->dev<int>(NL);
             d.lane_newcnt = h->dev<int>(NL);
-            d.edge_rel = h->dev<int>(E);
             d.blk_sum = h->dev<int>(h->n_blk);
             d.blk_off = h->dev<int>(h->n_blk);
             d.tt_sum = h->dev<double>(E);

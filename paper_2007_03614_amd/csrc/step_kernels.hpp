@@ -106,6 +106,7 @@ struct Slots {
     int32_t* edge;
     uint32_t* meta;
     int32_t* nxt;     // next route edge, -1 on the last edge
+    int32_t* gl;      // global lane after the lane change, written by the tile kernels for k_scatter
 };
 
 struct LaneRear {     // rear of a lane at the start of step `stamp`
@@ -235,10 +236,9 @@ struct Dev {
     unsigned long long* win;
     int* exit_stamp;
     int* enter_stamp;
-    int* lane_rel;              // next layout: lane start relative to its edge
+    int* lane_off;              // next layout: lane start relative to its commit block
     int* lane_newcnt;
     // per edge
-    int* edge_rel;              // next layout: edge start relative to its block
     int* blk_sum;
     int* blk_off;
     int n_blk;
@@ -965,6 +965,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         S.edge[dst] = e;
         S.meta[dst] = m;
         S.nxt[dst] = f;
+        S.gl[dst] = lw_base(b.lbe[q]) + lam;
         b.xn[q] = xnew;
         b.fl[q] = fl;
         b.lim[q] = vnew;   // lim[q] is read only by this thread, above
@@ -1416,15 +1417,17 @@ __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
 // one per lane; kept in LDS and sorted there when an edge has several).
 // Lanes without a request cost three 4-byte stamps and their post-move count.
 __device__ inline void commit_block(const Dev& d, int blk, int t, int par, CounterAcc& acc, Scan4* wsh4,
-                                    uint32_t* xid, double* xtt) {
+                                    uint32_t* xid, double* xtt, uint16_t* xnc) {
     const Slots S = d.s[par];
     const int e = blk * kEdgeBlock + (int)threadIdx.x;
     uint32_t* myid = xid + threadIdx.x * kCommitLanes;
     double* mytt = xtt + threadIdx.x * kCommitLanes;
-    int c = 0, nex = 0;
+    uint16_t* mync = xnc + threadIdx.x * kCommitLanes;
+    int c = 0, nex = 0, nl = 0, base = 0;
     if (e < d.n_edges) {
         const EdgeC ce = d.ec[e];
-        const int nl = ce.lanes, base = ce.lane_base;
+        nl = ce.lanes;
+        base = ce.lane_base;
         int node_win = -1;                         // case 1: lane index of this node's winning crossing
         if (d.imode == 1) {
             const unsigned long long wn = d.win_node[d.efrom[e]];
@@ -1536,9 +1539,9 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
             }
             if (transfer_in && !claimed) d.enter_stamp[gl] = t;   // the scatter takes the crossing's record
             claimed = claimed || transfer_in;
-            // next layout: this lane's count and its offset in the edge
+            // next layout: this lane's count (its offset follows the block scan)
             const int nc = pcnt - (exits ? 1 : 0) + (claimed ? 1 : 0);
-            d.lane_rel[gl] = c;
+            mync[l] = (uint16_t)nc;
             d.lane_newcnt[gl] = nc;
             c += nc;
         }
@@ -1559,9 +1562,13 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
             d.tt_cnt[e] += (unsigned long long)nex;
         }
     }
-    // offsets of the edges in the workgroup
+    // offsets of the edges in the workgroup, then of their lanes
     const Scan4 run = wg_exclusive_scan4<kCommitNT>(Scan4{c, -1, -1, -1}, wsh4);
-    if (e < d.n_edges) d.edge_rel[e] = run.s;
+    int o = run.s;
+    for (int l = 0; l < nl; ++l) {
+        d.lane_off[base + l] = o;
+        o += mync[l];
+    }
     if (threadIdx.x == kCommitNT - 1) d.blk_sum[blk] = run.s + c;
 }
 
@@ -1575,12 +1582,13 @@ __global__ void __launch_bounds__(kCommitNT) k_commit(Dev d) {
     __shared__ Scan4 wsh4[kCommitNT / 64];
     __shared__ uint32_t xid[kCommitNT * kCommitLanes];     // exits of each thread's edge
     __shared__ double xtt[kCommitNT * kCommitLanes];
+    __shared__ uint16_t xnc[kCommitNT * kCommitLanes];   // new counts of each thread's lanes
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     __syncthreads();
     const int t = d.ctl->t_b, par = t & 1;
     CounterAcc acc;
     acc.zero();
-    commit_block(d, blockIdx.x, t, par, acc, wsh4, xid, xtt);
+    commit_block(d, blockIdx.x, t, par, acc, wsh4, xid, xtt, xnc);
     flush_commit_counters(d, acc, shc);
 }
 
@@ -1666,6 +1674,30 @@ __global__ void __launch_bounds__(kBigNT) k_blkscan(Dev d) {
 }
 
 // ---- next layout -----------------------------------------------------------
+// One record of the next layout at slot dst, and the lane's rear for the
+// next step's look-ahead if it is the lane's last vehicle.
+__device__ inline void put_record(const Dev& d, const Slots& B, int dst, int nnew, float x, float v, uint32_t vid,
+                                  int edge, uint32_t meta, int nxt, bool is_rear, int gl, int t, const float* slen) {
+    if (dst < 0 || dst >= nnew) {
+        atomicOr(&d.ctl->err, kErrScatter);
+        return;
+    }
+    B.x[dst] = x;
+    B.v[dst] = v;
+    B.vid[dst] = vid;
+    B.edge[dst] = edge;
+    B.meta[dst] = meta;
+    B.nxt[dst] = nxt;
+    if (is_rear) {
+        LaneRear lr;
+        lr.xm = x - slen[m_cls(meta)];
+        lr.v = v;
+        lr.stamp = t + 1;
+        lr.vid = vid;
+        d.rear[gl] = lr;
+    }
+}
+
 // slot of a vehicle in the next layout:
 //   block offset + edge offset in block + lane offset in edge + rank in lane
 // kLds: the workgroup scans the block offsets itself into LDS (at most
@@ -1692,64 +1724,58 @@ __device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* 
         __syncthreads();                          // slen
     }
     const Slots A = d.s[par], B = d.s[par ^ 1];
-    for (int i = blockIdx.x * kNT + threadIdx.x; i < nold + nl; i += gridDim.x * kNT) {
-        float x, v;
-        uint32_t vid, meta;
-        int edge, nxt, gl, nr;
-        bool is_rear;
-        if (i < nold) {
-            meta = A.meta[i];                     // the whole record first, then its lane
-            edge = A.edge[i];
-            x = A.x[i];
-            v = A.v[i];
-            vid = A.vid[i];
-            nxt = A.nxt[i];
-            gl = d.lane_base[edge] + m_lane(meta);
-            const LanePost lp = d.post[gl];
-            const int ex = d.exit_stamp[gl] == t ? 1 : 0;
-            const int ncnt = d.lane_newcnt[gl];
-            const bool entered = d.enter_stamp[gl] == t;
+    // Item k is the record in slot k (k < nold) and lane k (k < nl), which
+    // takes the record that entered it if it was claimed this step.  Each
+    // round of loads of the two is issued together: the record with its lane
+    // and the lane's claim stamp; then the tables of the record's lane and
+    // the entry of a claimed lane.
+    const int nit = max(nold, nl);
+    for (int k = blockIdx.x * kNT + threadIdx.x; k < nit; k += gridDim.x * kNT) {
+        const bool hv = k < nold;
+        float x = 0.0f, v = 0.0f;
+        uint32_t vid = 0, meta = 0;
+        int edge = 0, nxt = 0, gl = 0;
+        if (hv) {
+            meta = A.meta[k];
+            edge = A.edge[k];
+            x = A.x[k];
+            v = A.v[k];
+            vid = A.vid[k];
+            nxt = A.nxt[k];
+            gl = A.gl[k];
+        }
+        const bool claimed = k < nl && d.enter_stamp[k] == t;
+        LanePost lp{};
+        int ex = 0, ncnt = 0, loff = 0;
+        bool entered = false;
+        if (hv) {
+            lp = d.post[gl];
+            ex = d.exit_stamp[gl] == t ? 1 : 0;
+            ncnt = d.lane_newcnt[gl];
+            entered = d.enter_stamp[gl] == t;
+            loff = d.lane_off[gl];
+        }
+        EntryRec en{};
+        int encnt = 0, enoff = 0;
+        if (claimed) {
+            en = d.ent[k];
+            encnt = d.lane_newcnt[k];
+            enoff = d.lane_off[k];
+        }
+        if (hv) {
+            const int r = k - lp.start;
             if (lp.stamp != t) {
                 atomicOr(&d.ctl->err, kErrScatter);
-                continue;
+            } else if (!(ex && r == 0)) {         // unless the lane's front left the edge
+                const int nr = r - ex;
+                put_record(d, B, boff[edge / kEdgeBlock] + loff + nr, nnew, x, v, vid, edge, meta, nxt,
+                           (nr == ncnt - 1) && !entered, gl, t, slen);
             }
-            const int r = i - lp.start;
-            if (ex && r == 0) continue;           // the lane's front left the edge
-            nr = r - ex;
-            is_rear = (nr == ncnt - 1) && !entered;
-        } else {                                  // a lane claimed this step takes its entry
-            gl = i - nold;
-            if (d.enter_stamp[gl] != t) continue;  // most lanes: one 4-byte load
-            const EntryRec r = d.ent[gl];
-            const int ncnt = d.lane_newcnt[gl];
-            nr = ncnt - 1;                        // the entry is the new rear
-            is_rear = true;
-            x = r.x;
-            v = r.v;
-            vid = r.vid;
-            meta = r.meta;
-            edge = r.edge;
-            nxt = r.nxt;
-            d.win[gl] = ~0ull;                    // lane free for the next step's claims
         }
-        const int dst = boff[edge / kEdgeBlock] + d.edge_rel[edge] + d.lane_rel[gl] + nr;
-        if (dst < 0 || dst >= nnew) {
-            atomicOr(&d.ctl->err, kErrScatter);
-            continue;
-        }
-        B.x[dst] = x;
-        B.v[dst] = v;
-        B.vid[dst] = vid;
-        B.edge[dst] = edge;
-        B.meta[dst] = meta;
-        B.nxt[dst] = nxt;
-        if (is_rear) {
-            LaneRear lr;
-            lr.xm = x - slen[m_cls(meta)];
-            lr.v = v;
-            lr.stamp = t + 1;
-            lr.vid = vid;
-            d.rear[gl] = lr;
+        if (claimed) {                            // the entry is the lane's new rear
+            put_record(d, B, boff[en.edge / kEdgeBlock] + enoff + encnt - 1, nnew, en.x, en.v, en.vid, en.edge,
+                       en.meta, en.nxt, true, k, t, slen);
+            d.win[k] = ~0ull;                     // lane free for the next step's claims
         }
     }
 }
