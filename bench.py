@@ -51,13 +51,18 @@ def kernel_source_digest() -> str:
 
 
 def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step",),
-                 probe_mib: int = 256, workload: str = "metro") -> dict:
+                 probe_mib: int = 256, workload: str = "metro", probe_jsons=None) -> dict:
     """HBM bytes per step of the tile kernel (launched once per step) from
     two --pmc summaries (FETCH_SIZE, WRITE_SIZE in KiB per dispatch),
     each counter scaled by what it reads for the copy probe (torch's add of
-    probe_mib MiB: reads and writes probe_mib MiB each)."""
+    probe_mib MiB: reads and writes probe_mib MiB each).  probe_jsons: the
+    (fetch, write) summaries holding the probe when the kernel's runs
+    collected counters over a window that leaves it out."""
     f = json.load(open(fetch_json))["kernels"]
     w = json.load(open(write_json))["kernels"]
+    pfj, pwj = probe_jsons or (fetch_json, write_json)
+    f_probe = json.load(open(pfj))["kernels"]
+    w_probe = json.load(open(pwj))["kernels"]
 
     def probe(d, key):
         p = [k for k in d if "add" in k.lower() and "fill" not in k.lower() and key in d[k]]
@@ -74,8 +79,8 @@ def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step",),
             out[kn] = d[ks[0]][key]
         return out
 
-    pf, pname = probe(f, "FETCH_SIZE")
-    pw, _ = probe(w, "WRITE_SIZE")
+    pf, pname = probe(f_probe, "FETCH_SIZE")
+    pw, _ = probe(w_probe, "WRITE_SIZE")
     kf, kw = per_kernel(f, "FETCH_SIZE"), per_kernel(w, "WRITE_SIZE")
     known = probe_mib * 1024.0
     fs, ws = known / pf, known / pw
@@ -83,6 +88,8 @@ def traffic_from(fetch_json: str, write_json: str, kernels=("k_tile_step",),
             "bytes_per_step": 1024.0 * sum(kf[k] * fs + kw[k] * ws for k in kernels),
             "fetch_kib_per_dispatch": kf, "write_kib_per_dispatch": kw,
             "probe": pname[:80], "probe_fetch_kib": pf, "probe_write_kib": pw,
+            "probe_from": [os.path.basename(os.path.dirname(os.path.abspath(x))) + "/" + os.path.basename(x)
+                           for x in (pfj, pwj)],
             "fetch_scale": fs, "write_scale": ws}
 
 
@@ -527,6 +534,8 @@ def main():
                                                          "kernel's last LAST dispatches")
     ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_JSON", "WRITE_JSON"),
                     help="combine two --summarize-pmc outputs into the traffic record and exit")
+    ap.add_argument("--probe-from", nargs=2, metavar=("FETCH_JSON", "WRITE_JSON"),
+                    help="--traffic-from: the summaries that hold the copy probe, if not those two")
     args = ap.parse_args()
     args.steps_given = "--steps" in sys.argv
     if args.summarize_pmc:
@@ -537,7 +546,7 @@ def main():
         return
     if args.traffic_from:
         print(json.dumps(traffic_from(*args.traffic_from, probe_mib=args.copy_probe or 256,
-                                      workload=args.workload), indent=1))
+                                      workload=args.workload, probe_jsons=args.probe_from), indent=1))
         return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the simulation is single-device; "
