@@ -201,8 +201,10 @@ sim_status sim_autotune(sim_handle *h, const char *cache_path, int32_t steps_per
 
 /* Current schedule, sched[4]: [tile_window, tile_workgroups,
  * big_tile_and_admission_workgroups, scatter_workgroups].  tile_window 0 (the
- * default) picks 64 or 128 slots at every step: the smallest whose tiles fit
- * in one round of the tile workgroups the device holds at once. */
+ * default) picks the window at every step: the fewest rounds of the tile
+ * workgroups the device holds at once that windows of at most 192 slots
+ * allow, with the smallest window (a multiple of 16, at least 64) that gives
+ * them.  A fixed window is a multiple of 16 in 64..256. */
 sim_status sim_get_schedule(const sim_handle *h, int32_t *sched);
 
 /* Stream for all later device work of h (a hipStream_t; NULL = null stream).

@@ -1346,7 +1346,7 @@ sim_status sim_get_schedule(const sim_handle* h, int32_t* sched) {
 
 namespace {
 bool set_schedule(sim_handle* h, int w, int g1, int g2, int g4) {
-    if (w != 0 && (w < kTileWindowMin || w > kTileWindowMax || (w & (w - 1)) != 0)) return false;
+    if (w != 0 && (w < kTileWindowMin || w > kTileWindowMax || (w % 16) != 0)) return false;
     if (g1 < 1 || g2 < h->g_big_min || g2 > h->g_big_max || g4 < 1 || g4 > h->g_scatter_max) return false;
     h->d.tile_window = w;
     h->g_tile = g1;

@@ -32,11 +32,11 @@ namespace manta {
 constexpr int kNT = 256;                 // threads per workgroup (4 waves)
 constexpr int kWaves = kNT / 64;
 constexpr int kTileWindowMax = 256;      // a tile = the edges whose first slot lies in a window of
-constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256)
+constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parameter, 64..256, a multiple of 16)
 constexpr int kTileCapLds = 304;         // tiles up to this size are staged in LDS (6 workgroups per CU)
 constexpr int kTileIndexMax = 32767;     // vehicles of a tile at most (16-bit indices in LDS)
 constexpr int kTileNT = 256;             // threads per tile workgroup
-constexpr int kTileWindowAuto = 128;     // largest window the per-step choice takes
+constexpr int kTileWindowAuto = 192;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
 constexpr int kCommitLanes = 8;         // lanes of an edge at most
 constexpr int kCommitNT = 256;           // threads per commit workgroup
@@ -1058,13 +1058,19 @@ __device__ inline void mark_big_lanes(const Dev& d, const int32_t* edge, int a0,
 }
 
 // Tile window of a step with n active vehicles: fixed by the schedule, or
-// (0) the smallest of 64 and 128 slots whose tiles fit in one round of
-// resident workgroups.
+// (0) chosen for the fewest rounds of the tile workgroups: a workgroup
+// runs its tiles one after another, so the step lasts as many tile chains as
+// the busiest workgroup has tiles.  R = the fewest rounds that windows of at
+// most kTileWindowAuto slots allow; the window is the smallest multiple of
+// 16 slots (at least kTileWindowMin) whose tiles fit in R rounds, since
+// larger windows make larger tiles and more of them above the LDS cap.
 __device__ inline int tile_window(const Dev& d, int n) {
     int W = d.tile_window;
     if (W == 0) {
-        W = kTileWindowMin;
-        while (W < kTileWindowAuto && (n + W - 1) / W > d.tile_target) W *= 2;
+        const long long tgt = gridDim.x;   // the tile workgroups (persistent: all resident)
+        const long long R = max(1LL, ((long long)n + kTileWindowAuto * tgt - 1) / (kTileWindowAuto * tgt));
+        const int w = (int)(((long long)n + R * tgt - 1) / (R * tgt));
+        W = max(kTileWindowMin, (w + 15) / 16 * 16);
     }
     return W;
 }
