@@ -3,16 +3,18 @@ edges, 3.2M trips): the HIP path through the C ABI against the CPU oracle.
 
 * Full size, from the 08:00 state built from the demand (about 465,000
   vehicles on the road), written into both sides: every vehicle's state and
-  every counter after 1, 20 and 100 steps.  With 549,008 edges the step runs
-  the large-network path (more than 262,144 edges: block offsets scanned by
-  their own kernel, the scatter without the per-block shortcut).
+  every counter after 1, 20 and 100 steps.
 * The same recipe on a 40 x 41 lattice with 30,000 trips, the whole 7 h run
-  from 05:00."""
+  from 05:00.
+* The roofline probe's network (8 copies of the metropolitan network in one
+  ensemble, 4.39M edges) at 5 % of jam density: the path for networks above
+  8,192 commit blocks (2.1M edges), where the block offsets come from their
+  own kernel and the scatter reads them from memory."""
 import numpy as np
 import pytest
 
 import workloads as W
-from test_gpu_parity import run_pair
+from test_gpu_parity import compare_states, run_pair
 
 pytestmark = pytest.mark.gpu
 
@@ -57,3 +59,42 @@ def test_parity_metro_recipe_small_lattice_whole_run(M, oracle_mod):
     print("metro 40x41 whole run:", c, "bitwise x, v:", bitwise)
     assert c["departed"] >= 0.99 * w.n_vehicles and c["arrived"] >= 0.95 * w.n_vehicles
     g.close()
+
+
+FIELDS = ("status", "lane", "cursor", "x", "v", "held_since", "mand", "ww", "tau_in", "t_arr")
+
+
+def test_parity_probe_network_above_the_lds_block_scan(M, oracle_mod):
+    """Eight copies of the metropolitan network in one ensemble (4,392,064
+    edges, 17,157 commit blocks), each lane at 5 % of jam density from the
+    probe's recipe (469,530 vehicles per copy): members 0 and 7 equal the
+    oracle's run of one copy vehicle for vehicle, and the ensemble's counters
+    are 8 times the oracle's, after 1, 10 and 40 steps."""
+    copies = 8
+    w, st = W.probe_r(density=0.05)
+    n, E = w.n_vehicles, w.net.n_edges
+    assert copies * E > 8192 * 256             # more commit blocks than one workgroup scans in LDS
+    ens = M.Sim(w, scenarios=[(n, np.zeros(0, np.int32))] * copies)
+    ens.write_state(W.replicate_state(st, E, copies))
+    o = oracle_mod.OracleSim(w)
+    o.write_state(0, st)
+    oracle_mod.set_threads(0)
+    try:
+        t = 0
+        for cp in (1, 10, 40):
+            ens.step(cp - t)
+            o.step(cp - t)
+            t = cp
+            es, os_ = ens.state(), o.state()
+            off = ens.offsets()
+            for k in (0, copies - 1):
+                sl = slice(int(off[k]), int(off[k + 1]))
+                member = {f: es[f][sl] for f in FIELDS}
+                member["edge"] = es["edge"][sl] - k * E    # every status reports an edge of its copy
+                assert compare_states(member, os_, f"member {k}, step {cp}")
+            oc = o.counters()
+            assert dict(zip(M.COUNTERS, es["counters"].tolist())) == {c: copies * v for c, v in oc.items()}, cp
+    finally:
+        oracle_mod.set_threads(1)
+    assert oc["transfers"] > 100_000 and oc["lane_changes"] > 10_000, oc
+    ens.close()
