@@ -631,7 +631,14 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 h->g_big = h->g_big_min;
             }
             h->g_scatter_max = std::max(1, std::min(4096, (N + kNT - 1) / kNT));
-            h->g_scatter = std::max(1, std::min(2048, (N + kNT - 1) / kNT));
+            {   // k_scatter: the workgroups resident at once, each scanning the block sums once
+                int dev = 0, cus = 0, per_cu = 0;
+                HIP_OK(hipGetDevice(&dev));
+                HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scatter<true>, kNT, 0));
+                per_cu = std::min(per_cu, lds_fit((const void*)k_scatter<true>, dev));
+                h->g_scatter = std::max(1, std::min(cus * std::max(per_cu, 1), h->g_scatter_max));
+            }
             h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
             d.n_blk = h->n_blk;
             // ---- dynamic state

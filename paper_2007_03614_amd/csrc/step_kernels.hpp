@@ -1439,11 +1439,19 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
             const unsigned long long wn = d.win_node[d.efrom[e]];
             if (wn != ~0ull) node_win = d.outbox[(int)(wn & ((1ull << 26) - 1))].target;
         }
+        // each lane's three stamps are loaded one lane ahead
+        LanePost pn = d.post[base];
+        int rn = d.req_stamp[base], en = d.enter_stamp[base];
         for (int l = 0; l < nl; ++l) {
             const int gl = base + l;
-            const LanePost p = d.post[gl];
-            const bool req = d.req_stamp[gl] == t;
-            bool claimed = d.enter_stamp[gl] == t;
+            const LanePost p = pn;
+            const bool req = rn == t;
+            bool claimed = en == t;
+            if (l + 1 < nl) {
+                pn = d.post[gl + 1];
+                rn = d.req_stamp[gl + 1];
+                en = d.enter_stamp[gl + 1];
+            }
             const int pcnt = p.stamp == t ? p.cnt : 0;
             bool exits = false;
             if (req) {
