@@ -589,6 +589,9 @@ def _window(sim, M, torch, stream, steps, progress, kernels_only):
     path ms, big-tile updates, state at the end)."""
     start_state = sim.state()
     before = int(start_state["counters"][0])
+    # both passes start from the written state (with flashing-red intersections a written state
+    # restarts the round-robin, so a pass that continued the run could take other decisions)
+    sim.write_state(start_state)
     total_ms = None
     if not kernels_only:                     # counter runs: the event-timed pass below is enough
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

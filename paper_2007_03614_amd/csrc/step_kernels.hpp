@@ -1226,6 +1226,10 @@ __device__ inline void claim(const Dev& d, int gl, unsigned long long key, int t
 // first: on a GPU whose XCDs have separate L2 caches that fence writes the
 // L2 back, the costly part of the barrier.
 __device__ inline void grid_barrier(const Dev& d, unsigned* counter, bool release) {
+    // A workgroup barrier waits for LDS operations only: every wave first
+    // waits for its own global stores, so that the fence of thread 0 below
+    // releases the whole workgroup's writes.
+    if (release) __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) {
         if (release) __threadfence();
@@ -1246,7 +1250,8 @@ __device__ inline void grid_barrier(const Dev& d, unsigned* counter, bool releas
 // An item whose target lane is in big tile k: listed for that tile's workgroup.
 __device__ inline void defer_item(const Dev& d, int k, int item) {
     const int slot = atomicAdd(&d.ctl->n_defer, 1);
-    d.big_defer[slot] = ((unsigned long long)(uint32_t)k << 32) | (uint32_t)item;
+    __hip_atomic_store(&d.big_defer[slot], ((unsigned long long)(uint32_t)k << 32) | (uint32_t)item,
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Admission of the request of lane i's front (eligibility, then the claim
@@ -1405,9 +1410,10 @@ __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
         }
     } else {
         admit_items<kBigNT, true>(d, t, blockIdx.x - nbig, gridDim.x - nbig);
+        __builtin_amdgcn_s_waitcnt(0);              // every wave's listed items and stores first
         __syncthreads();
         if (threadIdx.x == 0) {
-            __threadfence();                        // the listed items first
+            __threadfence();
             atomicAdd(&d.ctl->big_done, 1u);
         }
     }

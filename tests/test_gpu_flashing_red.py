@@ -51,6 +51,29 @@ def test_parity_scaled_config2_case1(M, oracle_mod):
     assert bitwise
 
 
+def test_parity_config2_case1_from_its_0800_state(M, oracle_mod):
+    """Full-size config 2 with flashing red at every node, run on the GPU to
+    08:00 (about 130,000 vehicles on the road); that state, written into a
+    new handle and into the oracle (both restart the round-robin), then 200
+    steps bit for bit, every vehicle and counter."""
+    w = case1(W.config2())
+    g = M.Sim(w)
+    assert g.schedule()[2] > 1
+    g.step(10_800)
+    st = g.state()
+    init = {k: st[k] for k in ("status", "edge", "lane", "cursor", "x", "v", "held_since", "mand", "ww",
+                               "tau_in", "t_arr")}
+    init.update(counters=np.zeros(len(M.COUNTERS), np.int64), t=int(st["t"]))
+    g.close()
+    oracle_mod.set_threads(0)
+    try:
+        g2, o, bitwise = run_pair(M, oracle_mod, w, [10_801, 10_850, 11_000], init=init)
+    finally:
+        oracle_mod.set_threads(1)
+    assert bitwise
+    assert o.counters()["transfers"] > 10_000
+
+
 def test_case1_resume_from_written_state(M, oracle_mod):
     """sim_write_state restarts the round-robin on both sides.  The written
     state is the oracle's own at step 900."""

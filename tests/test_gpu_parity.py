@@ -206,14 +206,17 @@ def _schedule_cache(tmp_path, w, g):
 
 
 @pytest.mark.parametrize("spread_admission", [False, True])
-def test_parity_big_tiles_with_transfers(M, oracle_mod, tmp_path, spread_admission):
+@pytest.mark.parametrize("intersection_mode", [0, 1])
+def test_parity_big_tiles_with_transfers(M, oracle_mod, tmp_path, spread_admission, intersection_mode):
     """Big tiles that exchange vehicles with each other and with ordinary
     tiles, and take departures, bit for bit with the oracle: with one
     admission workgroup (every workgroup has a big tile: grid barrier, then
     admission) and with more admission workgroups than big tiles (admission
     of the other lanes alongside the big tiles, the rest by each tile's own
-    workgroup)."""
+    workgroup); all green, and flashing red at every node (admission sets
+    each request's node key)."""
     w, init = _long_edge_grid()
+    w.params.intersection_mode = intersection_mode
     g = M.Sim(w)
     if spread_admission:
         g.autotune(_schedule_cache(tmp_path, w, g))
