@@ -191,13 +191,16 @@ sim_status sim_backward(sim_handle *h, const double *dL_dmean_tt, double *dL_dpa
 /* veh_off[n_scen + 1]: vehicles of scenario k are [veh_off[k], veh_off[k+1]). */
 sim_status sim_ensemble_offsets(const sim_handle *h, int32_t *n_scen, int32_t *veh_off);
 
-/* Pick the launch schedule (tile window, workgroups per kernel) by timing a
- * few steps of each candidate from the current state, which is restored
- * afterwards.  steps_per_trial >= 1.  The choice is appended to cache_path
- * (text, one line per network/demand size) and reused from there when the
- * same sizes come back; cache_path may be NULL.  Results of the simulation
- * never depend on the schedule. */
-sim_status sim_autotune(sim_handle *h, const char *cache_path, int32_t steps_per_trial);
+/* Pick the launch schedule (tile window, workgroups per kernel) by timing
+ * 20 steps of each candidate from the current state, which is restored
+ * afterwards.  The choice is appended to cache_path (text, one line per
+ * network/demand size) and reused from there when the same sizes come back;
+ * cache_path may be NULL.  Results of the simulation never depend on the
+ * schedule. */
+sim_status sim_autotune(sim_handle *h, const char *cache_path);
+
+/* The same with steps_per_trial (>= 1) steps per candidate. */
+sim_status sim_autotune_steps(sim_handle *h, const char *cache_path, int32_t steps_per_trial);
 
 /* Current schedule, sched[4]: [tile_window, tile_workgroups,
  * big_tile_and_admission_workgroups, scatter_workgroups].  tile_window 0 (the
@@ -244,6 +247,15 @@ sim_status sim_write_state(sim_handle *h, const sim_state *in);
 /* Per-edge sums of completed traversal times (s, FP64, accumulated each step
  * in ascending vehicle id) and traversal counts: [n_edges] each. */
 sim_status sim_read_edge_stats(sim_handle *h, double *tt_sum, int64_t *tt_count);
+
+/* Per-edge mean completed traversal time, the per-edge output that the
+ * calibration compares with observations (Sec. IV-A) and whose gradient
+ * sim_backward takes: sum / count computed on the device in FP64 (correctly
+ * rounded), 0 where nothing completed a traversal.  mean_s: [n_edges]
+ * (caller-owned, required); tt_count: [n_edges] or NULL.  Synchronizes the
+ * stream.  Errors: SIM_EINVAL (null handle or mean_s), SIM_ENOMEM (the
+ * handle's mean buffer, allocated at the first call), SIM_EDEVICE. */
+sim_status sim_read_edge_means(sim_handle *h, double *mean_s, int64_t *tt_count);
 
 /* Number of vehicles active at the start of the current step (synchronizes). */
 sim_status sim_n_active(sim_handle *h, int32_t *out);

@@ -92,8 +92,12 @@ _lib.sim_create_ensemble.argtypes = [ctypes.POINTER(SimNetwork), ctypes.POINTER(
 _lib.sim_create_ensemble.restype = I32
 _lib.sim_ensemble_offsets.argtypes = [P, P, P]
 _lib.sim_ensemble_offsets.restype = I32
-_lib.sim_autotune.argtypes = [P, ctypes.c_char_p, I32]
+_lib.sim_autotune.argtypes = [P, ctypes.c_char_p]
 _lib.sim_autotune.restype = I32
+_lib.sim_autotune_steps.argtypes = [P, ctypes.c_char_p, I32]
+_lib.sim_autotune_steps.restype = I32
+_lib.sim_read_edge_means.argtypes = [P, P, P]
+_lib.sim_read_edge_means.restype = I32
 _lib.sim_big_tile_updates.argtypes = [P, P]
 _lib.sim_big_tile_updates.restype = I32
 _lib.sim_get_schedule.argtypes = [P, P]
@@ -116,7 +120,8 @@ _lib.sim_shortest_routes_noalloc.restype = I32
 
 EXPORTED = ["sim_set_allocator", "sim_create", "sim_set_stream", "sim_step", "sim_step_timed", "sim_read_state",
             "sim_write_state", "sim_read_edge_stats", "sim_n_active", "sim_destroy", "sim_last_error",
-            "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_get_schedule", "sim_backward",
+            "sim_create_ensemble", "sim_ensemble_offsets", "sim_autotune", "sim_autotune_steps", "sim_get_schedule",
+            "sim_read_edge_means", "sim_backward",
             "sim_big_tile_updates", "sim_shortest_routes", "sim_shortest_routes_noalloc",
             "sim_probe_fp32", "sim_probe_philox", "sim_probe_draws"]
 
@@ -260,9 +265,12 @@ class Sim:
             self.set_stream(stream)
 
     def mean_travel_times(self):
-        """Per-edge mean completed traversal time (s) and traversal count."""
-        s, c = self.edge_stats()
-        return np.where(c > 0, s / np.maximum(c, 1), 0.0), c
+        """Per-edge mean completed traversal time (s, 0 where none completed)
+        and traversal count (sim_read_edge_means)."""
+        m = np.empty(self.n_edges, np.float64)
+        c = np.empty(self.n_edges, np.int64)
+        _check(_lib.sim_read_edge_means(self._h, _p(m), _p(c)), self._h)
+        return m, c
 
     def backward(self, dL_dmean: np.ndarray) -> np.ndarray:
         """dL/d(class parameters) as [n_classes, 5] (v0_factor, T, a, b, s0)
@@ -281,7 +289,7 @@ class Sim:
 
     def autotune(self, cache_path=None, steps_per_trial: int = 20) -> list:
         cp = cache_path.encode() if cache_path else None
-        _check(_lib.sim_autotune(self._h, cp, int(steps_per_trial)), self._h)
+        _check(_lib.sim_autotune_steps(self._h, cp, int(steps_per_trial)), self._h)
         return self.schedule()
 
     def big_tile_updates(self) -> int:

@@ -83,6 +83,7 @@ struct sim_handle {
     int g_tile = 1, g_big = 1, g_scatter = 1, n_blk = 1;
     int g_big_min = 1, g_big_max = 1, g_scatter_max = 1;
     int n_scen = 1;
+    double* tt_mean = nullptr;      // per-edge means (sim_read_edge_means), allocated at first use
     std::vector<int32_t> veh_off;   // ensemble: vehicles of scenario k
     // differentiable form: a snapshot of the dynamic state every rec_every steps
     int rec_every = 0;
@@ -1035,6 +1036,20 @@ sim_status sim_read_edge_stats(sim_handle* h, double* tt_sum, int64_t* tt_count)
     });
 }
 
+sim_status sim_read_edge_means(sim_handle* h, double* mean_s, int64_t* tt_count) {
+    if (!h || !mean_s) return SIM_EINVAL;
+    return guarded(h, [&] {
+        const int E = h->n_edges;
+        if (!h->tt_mean) h->tt_mean = h->dev<double>((size_t)E);
+        hipLaunchKernelGGL(k_edge_means, dim3((E + kNT - 1) / kNT), dim3(kNT), 0, h->stream, h->d.tt_sum, h->d.tt_cnt,
+                           h->tt_mean, E);
+        HIP_OK(hipGetLastError());
+        HIP_OK(hipStreamSynchronize(h->stream));
+        HIP_OK(hipMemcpy(mean_s, h->tt_mean, 8 * (size_t)E, hipMemcpyDeviceToHost));
+        if (tt_count) HIP_OK(hipMemcpy(tt_count, h->d.tt_cnt, 8 * (size_t)E, hipMemcpyDeviceToHost));
+    });
+}
+
 sim_status sim_destroy(sim_handle* h) {
     if (!h) return SIM_OK;
     (void)hipStreamSynchronize(h->stream);
@@ -1363,7 +1378,9 @@ bool set_schedule(sim_handle* h, int w, int g1, int g2, int g4) {
 }
 }  // namespace
 
-sim_status sim_autotune(sim_handle* h, const char* cache_path, int32_t steps) {
+sim_status sim_autotune(sim_handle* h, const char* cache_path) { return sim_autotune_steps(h, cache_path, 20); }
+
+sim_status sim_autotune_steps(sim_handle* h, const char* cache_path, int32_t steps) {
     if (!h || steps < 1) return SIM_EINVAL;
     return guarded(h, [&] {
         char key[160];

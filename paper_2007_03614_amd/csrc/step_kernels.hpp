@@ -2060,6 +2060,17 @@ __global__ void k_probe_fp32(int op, const float* a, const float* b, float* out,
     }
 }
 
+// Per-edge mean completed traversal time: the sum over the count (FP64,
+// correctly rounded), 0 where nothing completed a traversal.
+__global__ void __launch_bounds__(kNT) k_edge_means(const double* sum, const unsigned long long* cnt, double* mean,
+                                                    int n) {
+    const int i = blockIdx.x * kNT + threadIdx.x;
+    if (i < n) {
+        const unsigned long long c = cnt[i];
+        mean[i] = c ? sum[i] / (double)c : 0.0;
+    }
+}
+
 __global__ void k_probe_philox(const uint64_t* ctr, uint64_t k0, uint64_t k1, uint64_t* out, int64_t n) {
     for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const U64x4 r = philox4x64_10(ctr[4 * i], ctr[4 * i + 1], ctr[4 * i + 2], ctr[4 * i + 3], k0, k1);

@@ -107,3 +107,6 @@ def test_autotune_keeps_results_and_caches(M, c1, tmp_path):
     b = M.Sim(c1)
     assert b.autotune(cache, steps_per_trial=4) == sched   # read back from the cache
     assert open(cache).read().count("manta-schedule") == 1
+    c = M.Sim(c1)                                          # the two-argument form reads the same line
+    assert M._lib.sim_autotune(c._h, cache.encode()) == 0 and c.schedule() == sched
+    assert open(cache).read().count("manta-schedule") == 1

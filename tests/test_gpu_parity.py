@@ -259,6 +259,22 @@ def test_parity_config2_full_size_prefix(M, oracle_mod):
     assert bitwise
 
 
+def test_edge_means_on_the_device(M, oracle_mod, c1):
+    """sim_read_edge_means: sum / count per edge computed on the device equals
+    the division of sim_read_edge_stats' arrays and the oracle's means, bit
+    for bit, with 0 where no traversal completed."""
+    g = M.Sim(c1)
+    o = oracle_mod.OracleSim(c1)
+    g.step(1500)
+    o.step(1500)
+    mean, cnt = g.mean_travel_times()
+    s, c = g.edge_stats()
+    assert np.array_equal(cnt, c) and (c == 0).any() and (c > 0).any()
+    assert np.array_equal(mean, np.where(c > 0, s / np.maximum(c, 1), 0.0))
+    os_, oc = o.edge_stats()
+    assert np.array_equal(mean, np.where(oc > 0, os_ / np.maximum(oc, 1), 0.0))
+
+
 def test_determinism_and_resume(M, c1):
     a = M.Sim(c1)
     a.step(2000)
