@@ -124,6 +124,11 @@ enum {
     SIM_C_CLAMP,              /* positions clamped to the leader's rear */
     SIM_C_WRONG_LANE_HOLDS,   /* steps held at the stop line in a wrong lane */
     SIM_C_WAIVED_EXITS,       /* transfers from a wrong lane after the patience ran out */
+    SIM_C_GRIDLOCK_STEPS,     /* gridlock detector (failure detection, not part of the method): steps that end
+                               * a run of at least 600 consecutive stalled steps, a stalled step being one with
+                               * active vehicles at its start of which none changed position (in the update of
+                               * Eq. (1)) or lane, crossed to another edge or arrived, and with no departure.
+                               * sim_write_state restarts the run; in an ensemble the run is over all scenarios */
     SIM_N_COUNTERS
 };
 

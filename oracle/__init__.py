@@ -27,7 +27,7 @@ LIB64 = os.path.join(_HERE, "liboracle64.so")
 
 COUNTERS = ["active_sum", "departed", "arrived", "lane_changes", "transfers", "holds",
             "insert_denied", "mand_triggers", "stop_branch", "clamp", "wrong_lane_holds",
-            "waived_exits"]
+            "waived_exits", "gridlock_steps"]
 EV = dict(REQ=1, WIN=2, ARRIVE=4, WHOLD=8, CLAMP=16, STOPB=32, ELIG=64, INSERT_REQ=128,
           MOVED=256, MAND_TRIG=512)
 KIND = dict(FREE=0, VEH=1, STOP=2, LOOK=3)

@@ -74,8 +74,14 @@ enum { K_FREE = 0, K_VEH = 1, K_STOP = 2, K_LOOK = 3 };
 enum {
     C_ACTIVE_SUM, C_DEPARTED, C_ARRIVED, C_LANE_CHANGES, C_TRANSFERS, C_HOLDS,
     C_INSERT_DENIED, C_MAND_TRIGGERS, C_STOP_BRANCH, C_CLAMP, C_WRONG_LANE_HOLDS,
-    C_WAIVED_EXITS, C_N
+    C_WAIVED_EXITS, C_GRIDLOCK, C_N
 };
+/* Gridlock detector (failure detection; the paper describes none): a step
+ * stalls when vehicles were active at its start and none of them changed
+ * position or lane, none crossed to another edge or arrived, and none
+ * departed.  C_GRIDLOCK counts the steps that end a run of at least
+ * GRIDLOCK_STEPS stalled steps (5 minutes at dt = 0.5 s). */
+#define GRIDLOCK_STEPS 600
 /* event flags of the last step (for brute-force tests) */
 enum {
     EV_REQ = 1, EV_WIN = 2, EV_ARRIVE = 4, EV_WHOLD = 8, EV_CLAMP = 16, EV_STOPB = 32,
@@ -275,6 +281,7 @@ typedef struct orc_sim {
     REAL *x, *v;
     double *tau_in, *t_arr;
     int64_t cnt[C_N];
+    int stall_run;      /* consecutive stalled steps (gridlock detector) */
     double *tt_sum;
     int64_t *tt_cnt;
     /* per-step scratch */
@@ -475,6 +482,7 @@ static void step_once(orc_sim *S) {
         if (S->status[i] == ACTIVE) n_active++;
     }
     S->cnt[C_ACTIVE_SUM] += n_active;
+    const int64_t c_moves0 = S->cnt[C_TRANSFERS] + S->cnt[C_ARRIVED] + S->cnt[C_DEPARTED];
 
     /* S_t lane lists (front first); M_t rear of a lane = its last entry */
     build_lanes(S, S->lane, S->x);
@@ -574,8 +582,8 @@ static void step_once(orc_sim *S) {
 
     /* ---- Phase 2: leader on the post-change lane, Eq. (1), integration */
     build_lanes(S, S->nlane, S->x);
-    int64_t n_stopb = 0, n_clamp = 0, n_whold = 0;
-#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : n_stopb, n_clamp, n_whold)
+    int64_t n_stopb = 0, n_clamp = 0, n_whold = 0, n_moved = 0;
+#pragma omp parallel for schedule(dynamic, 4096) reduction(+ : n_stopb, n_clamp, n_whold, n_moved)
     for (int i = 0; i < n; i++) {
         if (S->status[i] != ACTIVE) continue;
         const int e = S->edge[i], l = S->nlane[i], f = next_edge(S, i), c = S->cls[i];
@@ -645,6 +653,7 @@ static void step_once(orc_sim *S) {
         }
         S->xn[i] = xnew;
         S->vn[i] = vnew;
+        if (xnew != S->x[i]) n_moved++;
     }
     S->cnt[C_STOP_BRANCH] += n_stopb;
     S->cnt[C_CLAMP] += n_clamp;
@@ -819,6 +828,11 @@ static void step_once(orc_sim *S) {
             if ((S->ev_flags[i] & EV_INSERT_REQ) && (S->ev_flags[i] & EV_WIN)) S->ins_step[i] = t;
         S->rec_off[t - S->rec_t0 + 1] = S->n_rec;
     }
+    /* gridlock detector */
+    const int moved = n_moved > 0 || n_lc > 0 ||
+                      S->cnt[C_TRANSFERS] + S->cnt[C_ARRIVED] + S->cnt[C_DEPARTED] != c_moves0;
+    S->stall_run = (n_active > 0 && !moved) ? S->stall_run + 1 : 0;
+    if (S->stall_run >= GRIDLOCK_STEPS) S->cnt[C_GRIDLOCK]++;
     S->t = t + 1;
 }
 
@@ -1089,6 +1103,7 @@ void orc_write_state(orc_sim *S, int32_t t, const uint8_t *status, const int32_t
     }
     if (S->rr)
         for (int v = 0; v < S->n_nodes; v++) S->rr[v] = -1;   /* the round-robin restarts */
+    S->stall_run = 0;                                         /* so does the gridlock detector */
 }
 
 void orc_counters(const orc_sim *S, int64_t *out) {

@@ -25,7 +25,7 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 COUNTERS = ["active_sum", "departed", "arrived", "lane_changes", "transfers", "holds",
             "insert_denied", "mand_triggers", "stop_branch", "clamp", "wrong_lane_holds",
-            "waived_exits"]
+            "waived_exits", "gridlock_steps"]
 STATUS = {"SIM_OK": 0, "SIM_EINVAL": -1, "SIM_ENOMEM": -2, "SIM_EDEVICE": -3, "SIM_ESTATE": -4,
           "SIM_EUNSUPPORTED": -5}
 _STATUS_NAME = {v: k for k, v in STATUS.items()}

@@ -17,6 +17,8 @@
 #include "routing.hpp"
 #include "step_kernels.hpp"
 
+static_assert(manta::cNumCounters == SIM_N_COUNTERS, "device counters and sim_state.counters differ");
+
 using namespace manta;
 
 namespace {
@@ -325,6 +327,7 @@ void load_state(sim_handle* h, const void* src, int t) {
     });
     // big-tile marks of steps at or after t belong to the run being replaced
     HIP_OK(hipMemsetAsync(h->d.big_lane, 0xFF, sizeof(int2) * (size_t)h->n_lanes, h->stream));
+    HIP_OK(hipMemsetAsync(h->d.moved_at, 0xFF, sizeof(int) * kMovedSlots, h->stream));
     h->t = t;
 }
 
@@ -679,6 +682,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.counters = h->dev<unsigned long long>(cNumCounters * kCounterCopies);
             d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindowMin + 2));
             d.big_lane = h->dev<int2>(NL);
+            d.moved_at = h->dev<int>(kMovedSlots);
             d.big_defer = h->dev<unsigned long long>((size_t)NL + (size_t)h->nq);   // each item at most once
             d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big_max);
             // ---- initial values
@@ -690,6 +694,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.big_lane, 0xFF, sizeof(int2) * NL));
+            HIP_OK(hipMemset(d.moved_at, 0xFF, sizeof(int) * kMovedSlots));
             HIP_OK(hipMemset(d.tt_sum, 0, sizeof(double) * E));
             HIP_OK(hipMemset(d.tt_cnt, 0, sizeof(unsigned long long) * E));
             HIP_OK(hipMemset(d.ctl, 0, sizeof(Ctl)));
@@ -1004,6 +1009,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         HIP_OK(hipMemset(d.exit_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.big_lane, 0xFF, sizeof(int2) * h->n_lanes));   // no big-tile marks of other runs
+        HIP_OK(hipMemset(d.moved_at, 0xFF, sizeof(int) * kMovedSlots));     // nor movement stamps
         if (d.imode == 1) {                        // the round-robin restarts
             HIP_OK(hipMemset(d.rr, 0xFF, sizeof(int) * (size_t)d.n_nodes));
             HIP_OK(hipMemset(d.win_node, 0xFF, sizeof(unsigned long long) * (size_t)d.n_nodes));

@@ -66,8 +66,14 @@ enum Status : uint8_t { kWaiting = 0, kActive = 1, kArrived = 2 };
 
 enum Counter {
     cActiveSum = 0, cDeparted, cArrived, cLaneChanges, cTransfers, cHolds, cInsertDenied,
-    cMandTriggers, cStopBranch, cClamp, cWrongLaneHolds, cWaivedExits, cNumCounters
+    cMandTriggers, cStopBranch, cClamp, cWrongLaneHolds, cWaivedExits, cGridlock, cNumCounters
 };
+// Gridlock detector (failure detection): a step stalls when vehicles were
+// active at its start and none of them changed position or lane, crossed to
+// another edge or arrived, and none departed; cGridlock counts the steps that
+// end a run of at least kGridlockSteps stalled steps (5 minutes at dt = 0.5 s).
+constexpr int kGridlockSteps = 600;
+constexpr int kMovedSlots = 64;          // one wavefront reads them all
 
 struct Ctl {
     // The step number, kept twice so that no kernel has to change a value its
@@ -83,7 +89,8 @@ struct Ctl {
     unsigned big_done;   // workgroups of k_big_admit past their admission pass or their big tiles
     int n_defer;      // admission items left to the workgroups of the big tiles (this step)
     unsigned long long big_updates;   // vehicle-updates done in big tiles (measurement)
-    int pad[2];
+    int stall_run;    // consecutive stalled steps before this one (gridlock detector)
+    int pad1;
 };
 
 // t_a, t_b, n_act[0], n_act[1] in one 16-byte load (the step number and both
@@ -249,6 +256,7 @@ struct Dev {
     // edges beyond the LDS of a workgroup
     int* big_list;
     int2* big_lane;             // [lane] {step, big tile} of the last step the lane's edge was in a big tile
+    int* moved_at;              // [kMovedSlots] last step in which a workgroup hashed to the slot saw a vehicle move
     unsigned long long* big_defer;   // admission items whose target lane is in a big tile: tile << 32 | item
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
@@ -414,6 +422,15 @@ __device__ inline int wg_sum(int v, int* wsh) {
     for (int w = 0; w < kWaves; ++w) s += wsh[w];
     __syncthreads();
     return s;
+}
+
+// Gridlock detector: a workgroup that saw a vehicle move stamps the step
+// into one of kMovedSlots slots (spread so that thousands of workgroups do
+// not store to one address), from an LDS flag (a register held across the
+// kernel would spill in the tile kernel); call after a barrier that follows
+// every write of the flag.
+__device__ inline void publish_moved(const Dev& d, const int* smoved, int t) {
+    if (threadIdx.x == 0 && *smoved) d.moved_at[blockIdx.x % kMovedSlots] = t;
 }
 
 // per-workgroup counter accumulation, flushed with one atomic per counter
@@ -592,7 +609,8 @@ __device__ inline void finish_pending(const TileBuf& b, int q, int dir, const fl
 // common case carries none of their code)
 template <int NT, bool kSpread>
 __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int n, int t, int par,
-                                    CounterAcc& acc, Scan4* wsh4, const ClassParams* scp, const DrawQ& dq) {
+                                    CounterAcc& acc, Scan4* wsh4, const ClassParams* scp, const DrawQ& dq,
+                                    int* smoved) {
     const Slots S = d.s[par];
     const int tid = threadIdx.x;
     const int dir = (t % 2 == 0) ? -1 : 1;
@@ -989,7 +1007,11 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
     __syncthreads();
 
     // ---- lane fronts (requests) and rears (admission and scatter tables)
+    // (and, for the gridlock detector, whether any vehicle changed position,
+    // x_new against x of slot index r, or lane: the movers' count mpref[n])
+    bool moved = tid == 0 && n > 0 && b.mpref[n] > 0;
     for (int r = tid; r < n; r += NT) {
+        moved = moved || (b.xn[r] != b.x[r]);
         const uint32_t el = b.pel[r];
         const bool front = (r == 0) || (b.pel[r - 1] != el);
         const bool rear = (r == n - 1) || (b.pel[r + 1] != el);
@@ -1040,6 +1062,7 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             }
         }
     }
+    if (__ballot(moved) && (tid & 63) == 0) *smoved = 1;
     __syncthreads();
 }
 
@@ -1086,9 +1109,11 @@ __device__ inline void tile_step(const Dev& d) {
     __shared__ ClassParams scp[16];
     __shared__ uint32_t dtask[kTileDrawTasks];
     __shared__ int dcount[2];
+    __shared__ int smoved;                      // gridlock detector: a vehicle of this workgroup moved
     const DrawQ dq{dtask, dcount, kTileDrawTasks};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
+    if (threadIdx.x == 0) smoved = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     const StepHead sh = step_head(d.ctl);
     const int t = sh.t_a, par = t & 1;
@@ -1121,7 +1146,7 @@ __device__ inline void tile_step(const Dev& d) {
             continue;
         }
         if (cnt <= kTileCapLds) {
-            process_tile<kTileNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq);
+            process_tile<kTileNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq, &smoved);
         } else {
             if (threadIdx.x == 0) {
                 const int q = atomicAdd(&d.ctl->n_big[par], 1);
@@ -1135,6 +1160,7 @@ __device__ inline void tile_step(const Dev& d) {
         }
     }
     flush_counters_lds(d, acc, shc);
+    publish_moved(d, &smoved, t);
 }
 
 // six workgroups per CU: at most 80 VGPRs, which the kernel fits without spills
@@ -1157,9 +1183,11 @@ __device__ __forceinline__ void big_tiles(const Dev& d, int t, int par, int nbig
     __shared__ ClassParams scp[16];
     __shared__ uint32_t dtask[2 * kBigNT];
     __shared__ int dcount[2];
+    __shared__ int smoved;                      // gridlock detector: a vehicle of this workgroup moved
     const DrawQ dq{dtask, dcount, 2 * kBigNT};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
+    if (threadIdx.x == 0) smoved = 0;
     if (threadIdx.x < 16) scp[threadIdx.x] = d.cp[threadIdx.x];
     __syncthreads();
     const int32_t* edge = d.s[par].edge;
@@ -1194,15 +1222,16 @@ __device__ __forceinline__ void big_tiles(const Dev& d, int t, int par, int nbig
             const int cnt = end - pos;
             if (threadIdx.x == 0) atomicAdd(&d.ctl->big_updates, (unsigned long long)cnt);
             if (cnt <= kBigCapLds) {
-                process_tile<kBigNT, true>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp, dq);
+                process_tile<kBigNT, true>(d, carve(lds, kBigCapLds), pos, cnt, t, par, acc, wsh4, scp, dq, &smoved);
             } else {
                 char* mine = d.big + (size_t)blockIdx.x * tile_bytes(d.big_cap);
-                process_tile<kBigNT, true>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp, dq);
+                process_tile<kBigNT, true>(d, carve(mine, d.big_cap), pos, cnt, t, par, acc, wsh4, scp, dq, &smoved);
             }
             pos = end;
         }
     }
     flush_counters_lds(d, acc, shc);
+    publish_moved(d, &smoved, t);
 }
 
 // ---- admission -------------------------------------------------------------
@@ -1429,7 +1458,7 @@ __global__ void __launch_bounds__(kBigNT) k_big_admit(Dev d) {
 // one per lane; kept in LDS and sorted there when an edge has several).
 // Lanes without a request cost three 4-byte stamps and their post-move count.
 __device__ inline void commit_block(const Dev& d, int blk, int t, int par, CounterAcc& acc, Scan4* wsh4,
-                                    uint32_t* xid, double* xtt, uint16_t* xnc) {
+                                    uint32_t* xid, double* xtt, uint16_t* xnc, int* smoved) {
     const Slots S = d.s[par];
     const int e = blk * kEdgeBlock + (int)threadIdx.x;
     uint32_t* myid = xid + threadIdx.x * kCommitLanes;
@@ -1503,6 +1532,7 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
                 acc.c[cTransfers] += won ? 1u : 0u;
                 acc.c[cWaivedExits] += (won && !lane_allowed(m, ob.nxt, l)) ? 1u : 0u;
                 acc.c[cHolds] += exits ? 0u : 1u;
+                if (exits) *smoved = 1;                 // gridlock detector
                 if (exits) {
                     d.exit_stamp[gl] = t;
                     const double tau = ((double)t + (double)ob.phi) * (double)d.dt;
@@ -1555,6 +1585,7 @@ __device__ inline void commit_block(const Dev& d, int blk, int t, int par, Count
                     d.tau_in[vid] = (double)(t + 1) * (double)d.dt;
                     d.ent[gl] = r;
                     acc.c[cDeparted]++;
+                    *smoved = 1;
                 }
             }
             if (transfer_in && !claimed) d.enter_stamp[gl] = t;   // the scatter takes the crossing's record
@@ -1603,13 +1634,16 @@ __global__ void __launch_bounds__(kCommitNT) k_commit(Dev d) {
     __shared__ uint32_t xid[kCommitNT * kCommitLanes];     // exits of each thread's edge
     __shared__ double xtt[kCommitNT * kCommitLanes];
     __shared__ uint16_t xnc[kCommitNT * kCommitLanes];   // new counts of each thread's lanes
+    __shared__ int smoved;                                // gridlock detector: an exit or a departure here
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
+    if (threadIdx.x == 0) smoved = 0;
     __syncthreads();
     const int t = d.ctl->t_b, par = t & 1;
     CounterAcc acc;
     acc.zero();
-    commit_block(d, blockIdx.x, t, par, acc, wsh4, xid, xtt, xnc);
+    commit_block(d, blockIdx.x, t, par, acc, wsh4, xid, xtt, xnc, &smoved);
     flush_commit_counters(d, acc, shc);
+    publish_moved(d, &smoved, t);
 }
 
 // ---- offsets of the edge blocks and the end of the step --------------------
@@ -1673,7 +1707,13 @@ __device__ inline int scan_block_sums_staged(const int* blk_sum, int nb, int* of
 
 // n_act of the next step, refused departures of this one (every due vehicle
 // still waiting asked for a lane and was refused), and the step counter
+// Called by the first wavefront of one workgroup; its lane 0 writes.
 __device__ inline void finish_step(const Dev& d, int t, int par, int total) {
+    const bool moved = __ballot(d.moved_at[threadIdx.x] == t) != 0ull;   // gridlock detector
+    if (threadIdx.x != 0) return;
+    const int run = (d.ctl->n_act[par] > 0 && !moved) ? d.ctl->stall_run + 1 : 0;
+    d.ctl->stall_run = run;
+    if (run >= kGridlockSteps) d.counters[cGridlock * kCounterCopies] += 1ull;
     d.ctl->n_act[par ^ 1] = total;
     const int due_now = d.max_dep < 0 ? 0 : d.due[min(t, d.max_dep)];
     const int departed = d.ctl->n_departed;
@@ -1690,7 +1730,7 @@ __global__ void __launch_bounds__(kBigNT) k_blkscan(Dev d) {
     __shared__ int stage[kScanLdsMax];
     const int t = d.ctl->t_b, par = t & 1;
     const int total = scan_block_sums_staged<kBigNT>(d.blk_sum, d.n_blk, d.blk_off, stage, kScanLdsMax, wsh4, &tot);
-    if (threadIdx.x == 0) finish_step(d, t, par, total);
+    if (threadIdx.x < 64) finish_step(d, t, par, total);
 }
 
 // ---- next layout -----------------------------------------------------------
@@ -1737,7 +1777,7 @@ __device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* 
         // at most kScanLdsMax blocks take this path)
         nnew = scan_block_sums_staged<kNT>(d.blk_sum, d.n_blk, soff, soff, kScanLdsMax, wsh4, totp);
         boff = soff;
-        if (blockIdx.x == 0 && threadIdx.x == 0) finish_step(d, t, par, nnew);
+        if (blockIdx.x == 0 && threadIdx.x < 64) finish_step(d, t, par, nnew);
     } else {
         boff = d.blk_off;
         nnew = d.ctl->n_act[par ^ 1];

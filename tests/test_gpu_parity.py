@@ -275,6 +275,22 @@ def test_edge_means_on_the_device(M, oracle_mod, c1):
     assert np.array_equal(mean, np.where(oc > 0, os_ / np.maximum(oc, 1), 0.0))
 
 
+def test_gridlock_detector(M, oracle_mod):
+    """The stopped ring of the oracle's detector tests (60 vehicles on 400 m,
+    every gap below s0): both sides count a step from the 600th stalled one
+    on, and the run restarts at a written state."""
+    from test_oracle_sim import stopped_ring
+    w, st = stopped_ring()
+    g, o, bitwise = run_pair(M, oracle_mod, w, [599, 600, 700], init=st)
+    assert bitwise and o.counters()["gridlock_steps"] == 101
+    s = g.state()
+    g.write_state(dict(s, counters=None))
+    g.step(599)
+    assert g.counters()["gridlock_steps"] == 101
+    g.step(1)
+    assert g.counters()["gridlock_steps"] == 102
+
+
 def test_determinism_and_resume(M, c1):
     a = M.Sim(c1)
     a.step(2000)

@@ -432,3 +432,68 @@ def test_brute_force_phase1_decisions(oracle_mod):
         assert got == _phase1_brute(oracle_mod, w, pre, step), step
         total += len(got)
     assert total > 20
+
+
+# ------------------------------------------------------------ gridlock detector
+def stopped_ring(n=60, n_nodes=4, edge_len=100.0, offset=0.3, spacing=400.0 / 60):
+    """A one-lane ring of n_nodes x edge_len m with n stopped vehicles
+    `spacing` m apart.  60 on 400 m leave gaps of 1.67 m, below s0 = 2 m, so
+    every vehicle brakes at standstill and none moves again (a gridlock by
+    construction); with gaps above s0 the ring starts to flow.  Returns
+    (workload, state at step 0)."""
+    w = W.ring_road(n, n_nodes=n_nodes, edge_len=edge_len, laps=4)
+    p = offset + np.arange(n) * spacing
+    k = np.floor(p / edge_len).astype(np.int64)                 # ring edge of each vehicle
+    start = np.arange(n) % n_nodes                               # each route starts at its own edge
+    cursor = ((k - start) % n_nodes).astype(np.int32)
+    edge = w.route_edges[w.route_off[:-1] + cursor]
+    st = dict(status=np.ones(n, np.uint8), edge=edge.astype(np.int32), lane=np.zeros(n, np.int32),
+              cursor=cursor, x=(p - k * edge_len).astype(np.float32), v=np.zeros(n, np.float32),
+              held_since=np.full(n, -1, np.int32), mand=np.zeros(n, np.uint8), ww=np.zeros(n, np.int32),
+              tau_in=np.zeros(n), t_arr=np.full(n, -1.0), counters=None, t=0)
+    return w, st
+
+
+def test_gridlock_detector_counts_after_600_stalled_steps(oracle_mod):
+    w, st = stopped_ring()
+    o = oracle_mod.OracleSim(w)
+    o.write_state(0, st)
+    o.step(599)
+    c = o.counters()
+    assert c["gridlock_steps"] == 0 and c["stop_branch"] == 599 * 60 and c["transfers"] == 0, c
+    assert np.array_equal(o.state()["x"], st["x"])               # nobody moved
+    o.step(1)
+    assert o.counters()["gridlock_steps"] == 1                   # the 600th stalled step
+    o.step(100)
+    assert o.counters()["gridlock_steps"] == 101
+
+
+def test_gridlock_detector_restarts_on_a_written_state(oracle_mod):
+    w, st = stopped_ring()
+    o = oracle_mod.OracleSim(w)
+    o.write_state(0, st)
+    o.step(650)
+    assert o.counters()["gridlock_steps"] == 51
+    s = o.state()
+    o.write_state(650, dict(s, t_arr=None))
+    o.step(599)
+    assert o.counters()["gridlock_steps"] == 51                  # the run started again at the written state
+    o.step(1)
+    assert o.counters()["gridlock_steps"] == 52
+
+
+def test_gridlock_detector_quiet_while_anything_moves(oracle_mod):
+    # 30 vehicles with gaps of 8.3 m: the ring flows and never stalls (with 59
+    # at the gridlock spacing the one wide gap closes within 90 steps and the
+    # ring freezes again); an empty network (every trip arrived) is no
+    # gridlock either
+    w, st = stopped_ring(n=30, spacing=400.0 / 30)
+    o = oracle_mod.OracleSim(w)
+    o.write_state(0, st)
+    o.step(1200)
+    c = o.counters()
+    assert c["gridlock_steps"] == 0 and c["transfers"] > 0, c
+    e = oracle_mod.OracleSim(W.ring_road(8, n_nodes=4, laps=1))  # one lap, then the ring is empty
+    e.step(900)
+    c = e.counters()
+    assert c["arrived"] == 8 and c["gridlock_steps"] == 0, c
