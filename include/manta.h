@@ -287,7 +287,9 @@ sim_status sim_destroy(sim_handle *h);
  * destinations, at most 16 GB).  Errors: SIM_EINVAL (bad input, origin ==
  * destination, no route), SIM_EUNSUPPORTED (labels above 16 GB), SIM_ENOMEM,
  * SIM_EDEVICE.
- * Needs no handle; runs on the current device and synchronises it. */
+ * Needs no handle; runs on the current device and synchronises it.  Its
+ * device buffers come from the allocator of sim_set_allocator (hipMalloc
+ * without one) and are returned before the call returns. */
 sim_status sim_shortest_routes(const sim_network *net, const float *edge_cost, int32_t n_queries,
                                const int32_t *origin, const int32_t *dest, int64_t *route_off,
                                int32_t *route_edges, int64_t capacity, int64_t *n_route_edges);

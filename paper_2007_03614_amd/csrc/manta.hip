@@ -1557,18 +1557,23 @@ sim_status sim_probe_draws(uint64_t seed, const int64_t* t, const int64_t* id, f
 
 // ---- routes on travel times ------------------------------------------------
 namespace {
-struct DevBufs {   // device buffers of one routing call, freed on every exit
+// Device buffers of one routing call, from the allocator set by
+// sim_set_allocator (hipMalloc without one), returned on every exit; the call
+// has synchronized the device before it returns them.
+struct DevBufs {
+    Alloc al{g_alloc, g_release, g_ctx};
     std::vector<void*> p;
     size_t left() const { return SIZE_MAX; }
     template <class T>
     T* get(size_t n) {
-        void* q = nullptr;
-        HIP_OK(hipMalloc(&q, std::max<size_t>(n, 1) * sizeof(T)));
+        const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+        void* q = al.get(bytes);
+        if (!q) throw Fail{SIM_ENOMEM, fmt("device allocation of %zu bytes failed", bytes)};
         p.push_back(q);
         return (T*)q;
     }
     ~DevBufs() {
-        for (void* q : p) (void)hipFree(q);
+        for (void* q : p) al.put(q);
     }
 };
 }  // namespace
