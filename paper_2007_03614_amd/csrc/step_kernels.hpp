@@ -383,31 +383,55 @@ __device__ inline Scan4 scan4_op(Scan4 x, Scan4 y) {
     return Scan4{x.s + y.s, max(x.a, y.a), max(x.b, y.b), max(x.c, y.c)};
 }
 
-// exclusive workgroup scan of one Scan4 per thread; wsh: NT/64 Scan4 in LDS
+// Inclusive wavefront scans with DPP moves (register to register, no LDS
+// round trip): Hillis-Steele over row shifts of 1, 2, 4 and 8 lanes within
+// each row of 16, then the last lane of row 0 broadcast into row 1 and of
+// row 2 into row 3 (row_bcast:15), then lane 31 into rows 2 and 3
+// (row_bcast:31).  A lane whose source is outside its row, or whose row is
+// masked off, takes the identity (the `old` operand).
+constexpr int kDppRowShr = 0x110, kDppRowBcast15 = 0x142, kDppRowBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+__device__ inline int wave_incl_sum(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 1, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 2, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 4, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowShr + 8, 0xf, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowBcast15, 0xa, 0xf, false);
+    x += __builtin_amdgcn_update_dpp(0, x, kDppRowBcast31, 0xc, 0xf, false);
+    return x;
+}
+
+// the same for max with identity -1 (the values scanned are indices >= -1)
+__device__ inline int wave_incl_max(int x) {
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, kDppRowShr + 1, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, kDppRowShr + 2, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, kDppRowShr + 4, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, kDppRowShr + 8, 0xf, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, kDppRowBcast15, 0xa, 0xf, false));
+    x = max(x, __builtin_amdgcn_update_dpp(-1, x, kDppRowBcast31, 0xc, 0xf, false));
+    return x;
+}
+
+// exclusive workgroup scan of one Scan4 per thread (all NT threads take
+// part); wsh: NT/64 Scan4 in LDS
 template <int NT = kNT>
 __device__ inline Scan4 wg_exclusive_scan4(Scan4 v, Scan4* wsh) {
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    Scan4 inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        Scan4 o;
-        o.s = __shfl_up(inc.s, d, 64);
-        o.a = __shfl_up(inc.a, d, 64);
-        o.b = __shfl_up(inc.b, d, 64);
-        o.c = __shfl_up(inc.c, d, 64);
-        if (lane >= d) inc = scan4_op(o, inc);
-    }
+    Scan4 inc;
+    inc.s = wave_incl_sum(v.s);
+    inc.a = wave_incl_max(v.a);
+    inc.b = wave_incl_max(v.b);
+    inc.c = wave_incl_max(v.c);
     if (lane == 63) wsh[wave] = inc;
     __syncthreads();
     Scan4 carry{0, -1, -1, -1};
     for (int w = 0; w < wave; ++w) carry = scan4_op(carry, wsh[w]);
     __syncthreads();
     Scan4 exc;
-    exc.s = __shfl_up(inc.s, 1, 64);
-    exc.a = __shfl_up(inc.a, 1, 64);
-    exc.b = __shfl_up(inc.b, 1, 64);
-    exc.c = __shfl_up(inc.c, 1, 64);
-    if (lane == 0) exc = Scan4{0, -1, -1, -1};
+    exc.s = inc.s - v.s;
+    exc.a = __builtin_amdgcn_update_dpp(-1, inc.a, kDppWaveShr1, 0xf, 0xf, false);   // lane 0 gets -1
+    exc.b = __builtin_amdgcn_update_dpp(-1, inc.b, kDppWaveShr1, 0xf, 0xf, false);
+    exc.c = __builtin_amdgcn_update_dpp(-1, inc.c, kDppWaveShr1, 0xf, 0xf, false);
     return scan4_op(carry, exc);
 }
 
