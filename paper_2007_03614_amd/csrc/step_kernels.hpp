@@ -435,19 +435,6 @@ __device__ inline Scan4 wg_exclusive_scan4(Scan4 v, Scan4* wsh) {
     return scan4_op(carry, exc);
 }
 
-__device__ inline int wg_sum(int v, int* wsh) {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    const int wave = threadIdx.x >> 6;
-    __syncthreads();
-    if ((threadIdx.x & 63) == 0) wsh[wave] = v;
-    __syncthreads();
-    int s = 0;
-    for (int w = 0; w < kWaves; ++w) s += wsh[w];
-    __syncthreads();
-    return s;
-}
-
 // Gridlock detector: a workgroup that saw a vehicle move stamps the step
 // into one of kMovedSlots slots (spread so that thousands of workgroups do
 // not store to one address), from an LDS flag (a register held across the
