@@ -83,7 +83,8 @@ struct sim_handle {
     int t = 0;
     int n_veh = 0, n_edges = 0, n_lanes = 0, n_classes = 0;
     int g_tile = 1, g_big = 1, g_scatter = 1, n_blk = 1;
-    int g_big_min = 1, g_big_max = 1, g_scatter_max = 1;
+    size_t scatter_lds = 0;   // dynamic LDS of k_scatter<true>: the block offsets
+    int g_big_min = 1, g_big_max = 1, g_scatter_max = 1, g_scatter_res = 1;
     int n_scen = 1;
     double* tt_mean = nullptr;      // per-edge means (sim_read_edge_means), allocated at first use
     std::vector<int32_t> veh_off;   // ensemble: vehicles of scenario k
@@ -254,7 +255,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
         hipLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, d);
         hipLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, d);
         if (lds_scan) {
-            hipLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, d);
+            hipLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, h->scatter_lds, s, d);
         } else {
             hipLaunchKernelGGL(k_blkscan, dim3(1), dim3(kBigNT), 0, s, d);
             hipLaunchKernelGGL(k_scatter<false>, dim3(h->g_scatter), b, 0, s, d);
@@ -266,7 +267,7 @@ void launch_step(sim_handle* h, hipStream_t s, hipEvent_t* ev = nullptr) {
     hipExtLaunchKernelGGL(k_big_admit, dim3(h->g_big), dim3(kBigNT), 0, s, ev[2], ev[3], 0, d);
     if (lds_scan) {
         hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, ev[4], ev[5], 0, d);
-        hipExtLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, 0, s, ev[6], ev[7], 0, d);
+        hipExtLaunchKernelGGL(k_scatter<true>, dim3(h->g_scatter), b, h->scatter_lds, s, ev[6], ev[7], 0, d);
     } else {   // the block scan is counted with commit
         hipExtLaunchKernelGGL(k_commit, dim3(h->n_blk), dim3(kCommitNT), 0, s, ev[4], nullptr, 0, d);
         hipExtLaunchKernelGGL(k_blkscan, dim3(1), dim3(kBigNT), 0, s, nullptr, ev[5], 0, d);
@@ -406,12 +407,12 @@ namespace {
 // rounded up to 1 KiB: the occupancy query alone has reported one workgroup
 // more than fits for a tile kernel just below a sixth of the CU's LDS, and a
 // persistent grid sized on that runs its surplus workgroups in a second wave.
-int lds_fit(const void* kernel, int dev) {
+int lds_fit(const void* kernel, int dev, size_t dyn = 0) {
     hipFuncAttributes fa;
     HIP_OK(hipFuncGetAttributes(&fa, kernel));
     int lds_cu = 0;
     HIP_OK(hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev));
-    const size_t per = (fa.sharedSizeBytes + 1023) / 1024 * 1024;
+    const size_t per = (fa.sharedSizeBytes + dyn + 1023) / 1024 * 1024;
     if (per == 0 || lds_cu <= 0) return INT_MAX;
     return std::max(1, (int)((size_t)lds_cu / per));
 }
@@ -634,17 +635,24 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
                 h->g_big_min = (int)std::max(1LL, std::min<long long>(h->g_big_max, (items + kBigNT - 1) / kBigNT));
                 h->g_big = h->g_big_min;
             }
+            h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
+            d.n_blk = h->n_blk;
+            h->scatter_lds = h->n_blk <= kScanLdsMax ? sizeof(int) * (size_t)h->n_blk : 0;
             h->g_scatter_max = std::max(1, std::min(4096, (N + kNT - 1) / kNT));
-            {   // k_scatter: the workgroups resident at once, each scanning the block sums once
+            {   // k_scatter: the workgroups resident at once, each scanning the block sums once.
+                // Without the LDS scan (above kScanLdsMax blocks: tens of millions of
+                // vehicles) as many as the LDS scan allows at its largest: more
+                // workgroups were slower there (2,048 against 1,024 on the 4.39M-edge
+                // roofline probe: 1.02 against 0.98 ms), as more scattered stores wait at once
                 int dev = 0, cus = 0, per_cu = 0;
                 HIP_OK(hipGetDevice(&dev));
                 HIP_OK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scatter<true>, kNT, 0));
-                per_cu = std::min(per_cu, lds_fit((const void*)k_scatter<true>, dev));
-                h->g_scatter = std::max(1, std::min(cus * std::max(per_cu, 1), h->g_scatter_max));
+                const size_t dyn = h->scatter_lds ? h->scatter_lds : sizeof(int) * (size_t)kScanLdsMax;
+                HIP_OK(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_scatter<true>, kNT, dyn));
+                per_cu = std::min(per_cu, lds_fit((const void*)k_scatter<true>, dev, dyn));
+                h->g_scatter_res = std::max(1, std::min(cus * std::max(per_cu, 1), h->g_scatter_max));
+                h->g_scatter = h->g_scatter_res;
             }
-            h->n_blk = (E + kEdgeBlock - 1) / kEdgeBlock;
-            d.n_blk = h->n_blk;
             // ---- dynamic state
             const size_t NV = std::max(N, 1);
             for (int b = 0; b < 2; ++b) {
@@ -1432,7 +1440,7 @@ sim_status sim_autotune_steps(sim_handle* h, const char* cache_path, int32_t ste
         for (int w : {0, 64, 128, 256})
             for (int g1 : {std::max(1, h->d.tile_target / 2), h->d.tile_target})
                 for (int g2 : {h->g_big_min, h->g_big_max})
-                    for (int g4 : {1024, 4096}) {
+                    for (int g4 : {h->g_scatter_res, 4096}) {
                         const int g1c = std::max(1, std::min(g1, (N + (w ? w : kTileWindowMin) - 1) /
                                                                      (w ? w : kTileWindowMin)));
                         const int g4c = std::max(1, std::min(g4, h->g_scatter_max));

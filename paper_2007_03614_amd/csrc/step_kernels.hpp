@@ -860,6 +860,14 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
         // the leader is the vehicle before in the same run, the position q.
         const int k0 = b.rk[q];
         const int rs = b.run_st[k0];
+        // the start-of-step rear of the lane it would look into with no leader
+        // on the tile, loaded now so that the round trip overlaps the leader
+        // search: for a lane's first vehicle and for the movers, the vehicles
+        // that most often have none (any other loads it where it is used)
+        const int look_i = lw_base(b.lbf[q]) + min(lam, lw_lanes(b.lbf[q]) - 1);
+        const bool pre = f >= 0 && (mv != 0 || q == rs);
+        LaneRear rp{0.0f, 0.0f, -1, 0u};
+        if (pre) rp = d.rear[look_i];
         int j, newpos, lane_start;
         bool quiet = false;
         if (!mv) {
@@ -941,14 +949,13 @@ __device__ inline void process_tile(const Dev& d, const TileBuf& b, int a0, int 
             s = b.L[q] - xi;
             vl = 0.0f;
         } else {
-            const int lf = min(lam, lw_lanes(b.lbf[q]) - 1);
-            const LaneRear r = d.rear[lw_base(b.lbf[q]) + lf];
+            const LaneRear r = pre ? rp : d.rear[look_i];
             if (r.stamp == t) {
                 kind = kLook;
                 s = (b.L[q] - xi) + r.xm;
                 vl = r.v;
                 partner = (int)r.vid;
-                look_gl = lw_base(b.lbf[q]) + lf;
+                look_gl = look_i;
             } else {
                 kind = kFree;
             }
@@ -1853,7 +1860,9 @@ __device__ inline void scatter_items(const Dev& d, int* soff, Scan4* wsh4, int* 
 
 template <bool kLds>
 __global__ void __launch_bounds__(kNT) k_scatter(Dev d) {
-    __shared__ int soff[kLds ? kScanLdsMax : 1];
+    // kLds: the block offsets, d.n_blk ints of dynamic LDS sized at launch
+    // (so a network with few edge blocks leaves room for more workgroups)
+    extern __shared__ int soff[];
     __shared__ Scan4 wsh4[kWaves];
     __shared__ int tot;
     __shared__ float slen[16];                    // vehicle length per class
