@@ -329,6 +329,8 @@ void load_state(sim_handle* h, const void* src, int t) {
     // big-tile marks of steps at or after t belong to the run being replaced
     HIP_OK(hipMemsetAsync(h->d.big_lane, 0xFF, sizeof(int2) * (size_t)h->n_lanes, h->stream));
     HIP_OK(hipMemsetAsync(h->d.moved_at, 0xFF, sizeof(int) * kMovedSlots, h->stream));
+    // a step at t clears the counters of t + 1: those of t may hold a later step's count
+    HIP_OK(hipMemsetAsync(tile_counters(h->d), 0, sizeof(int) * kTileCtrInts, h->stream));
     h->t = t;
 }
 
@@ -690,7 +692,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             d.counters = h->dev<unsigned long long>(cNumCounters * kCounterCopies);
             d.big_list = h->dev<int>(2 * ((size_t)N / kTileWindowMin + 2));
             d.big_lane = h->dev<int2>(NL);
-            d.moved_at = h->dev<int>(kMovedSlots);
+            d.moved_at = h->dev<int>(kMovedSlots + kTileCtrInts);   // then the tile counters
             d.big_defer = h->dev<unsigned long long>((size_t)NL + (size_t)h->nq);   // each item at most once
             d.big = h->dev<char>(tile_bytes(d.big_cap) * (size_t)h->g_big_max);
             // ---- initial values
@@ -703,6 +705,7 @@ sim_status create_impl(const sim_network* net, const sim_routes* r, const sim_id
             HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * NL));
             HIP_OK(hipMemset(d.big_lane, 0xFF, sizeof(int2) * NL));
             HIP_OK(hipMemset(d.moved_at, 0xFF, sizeof(int) * kMovedSlots));
+            HIP_OK(hipMemset(tile_counters(d), 0, sizeof(int) * kTileCtrInts));
             HIP_OK(hipMemset(d.tt_sum, 0, sizeof(double) * E));
             HIP_OK(hipMemset(d.tt_cnt, 0, sizeof(unsigned long long) * E));
             HIP_OK(hipMemset(d.ctl, 0, sizeof(Ctl)));
@@ -1018,6 +1021,7 @@ sim_status sim_write_state(sim_handle* h, const sim_state* in) {
         HIP_OK(hipMemset(d.enter_stamp, 0xFF, sizeof(int) * h->n_lanes));
         HIP_OK(hipMemset(d.big_lane, 0xFF, sizeof(int2) * h->n_lanes));   // no big-tile marks of other runs
         HIP_OK(hipMemset(d.moved_at, 0xFF, sizeof(int) * kMovedSlots));     // nor movement stamps
+        HIP_OK(hipMemset(tile_counters(d), 0, sizeof(int) * kTileCtrInts));   // nor tile counts
         if (d.imode == 1) {                        // the round-robin restarts
             HIP_OK(hipMemset(d.rr, 0xFF, sizeof(int) * (size_t)d.n_nodes));
             HIP_OK(hipMemset(d.win_node, 0xFF, sizeof(unsigned long long) * (size_t)d.n_nodes));

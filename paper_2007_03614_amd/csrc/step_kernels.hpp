@@ -36,6 +36,10 @@ constexpr int kTileWindowMin = 64;       // tile_window slots (a schedule parame
 constexpr int kTileCapLds = 304;         // tiles up to this size are staged in LDS (6 workgroups per CU)
 constexpr int kTileIndexMax = 32767;     // vehicles of a tile at most (16-bit indices in LDS)
 constexpr int kTileNT = 256;             // threads per tile workgroup
+constexpr int kTileGroups = 8;           // tile counters of k_tile_step (one per group of workgroups)
+constexpr int kTileCtrRounds = 8;        // the counters hand out tiles above this many rounds per step
+constexpr int kTileCtrStride = 32;       // ints between two counters: one 128-byte line each
+constexpr int kTileCtrInts = 2 * kTileGroups * kTileCtrStride;   // [step parity][group] counters
 constexpr int kTileWindowAuto = 192;     // largest window the per-step choice takes
 constexpr int kTileDrawTasks = 384;      // listed Philox blocks per tile round (more are computed in place)
 constexpr int kCommitLanes = 8;         // lanes of an edge at most
@@ -256,7 +260,8 @@ struct Dev {
     // edges beyond the LDS of a workgroup
     int* big_list;
     int2* big_lane;             // [lane] {step, big tile} of the last step the lane's edge was in a big tile
-    int* moved_at;              // [kMovedSlots] last step in which a workgroup hashed to the slot saw a vehicle move
+    int* moved_at;              // [kMovedSlots] last step in which a workgroup hashed to the slot saw a vehicle move,
+                                //   then in the same allocation the tile counters (tile_counters)
     unsigned long long* big_defer;   // admission items whose target lane is in a big tile: tile << 32 | item
     int tile_window;            // slots per tile window, or 0: chosen per step from tile_target
     int tile_target;            // tiles per step that run in one round of resident workgroups
@@ -270,6 +275,10 @@ struct Dev {
     char* big;
     int big_cap;                // vehicles per workgroup region
 };
+
+// k_tile_step's tile counters: after the movement stamps, 128-byte aligned
+// (the stamps take 256 bytes), in the same allocation
+__host__ __device__ inline int* tile_counters(const Dev& d) { return d.moved_at + kMovedSlots; }
 
 // ---- per-tile working set -----------------------------------------------
 struct TileBuf {
@@ -502,6 +511,10 @@ __device__ inline int first_edge_start(const int32_t* edge, int lo, int hi, int*
 // first edge start in [w0, w1) (w1 if none), a1 = the first edge start at or
 // after w1 (n if none).  Windows are at most NT / 2 slots, so the pass also
 // covers NT / 2 slots past w1; a longer edge continues with first_edge_start.
+struct TileSpan {   // a tile's slots [a0, a1) and the end of its window
+    int a0, a1, w1;
+};
+
 template <int NT>
 __device__ inline void tile_bounds(const int32_t* edge, int w0, int w1, int n, int* wsh2, int& a0, int& a1) {
     constexpr int kW = NT / 64;
@@ -1128,6 +1141,7 @@ __device__ inline void tile_step(const Dev& d) {
     __shared__ uint32_t dtask[kTileDrawTasks];
     __shared__ int dcount[2];
     __shared__ int smoved;                      // gridlock detector: a vehicle of this workgroup moved
+    __shared__ int snext;                       // the workgroup's next tile
     const DrawQ dq{dtask, dcount, kTileDrawTasks};
     if (threadIdx.x < cNumCounters) shc[threadIdx.x] = 0;
     if (threadIdx.x < 2) dcount[threadIdx.x] = 0;
@@ -1148,20 +1162,29 @@ __device__ inline void tile_step(const Dev& d) {
         d.ctl->n_defer = 0;
         if (d.trace) d.nact_hist[t % d.trace_period] = n;
     }
+    // the next step's tile counters (this step's were cleared by the previous one)
+    if (blockIdx.x == 0 && threadIdx.x < kTileGroups)
+        tile_counters(d)[((par ^ 1) * kTileGroups + (int)threadIdx.x) * kTileCtrStride] = 0;
     __syncthreads();
     // a tile is the set of edges whose first slot lies in one window
     const int W = tile_window(d, n);
     const int ntile = (n + W - 1) / W;
     const int32_t* edge = d.s[par].edge;
-    for (int k = blockIdx.x; k < ntile; k += gridDim.x) {
+    // A tile is the set of edges whose first slot lies in one window: its
+    // bounds (run_tile), then its phases or its listing as a big tile (do_tile)
+    auto run_tile = [&](int k) {
         const int w0 = k * W, w1 = min(n, w0 + W);
         int a0, a1;
         tile_bounds<kTileNT>(edge, w0, w1, n, wsh, a0, a1);
-        if (a0 >= w1) continue;   // window inside one long edge: handled by an earlier tile
+        return TileSpan{a0, a1, w1};
+    };
+    auto do_tile = [&](const TileSpan& sp) {
+        const int a0 = sp.a0, a1 = sp.a1;
+        if (a0 >= sp.w1) return;   // window inside one long edge: handled by an earlier tile
         const int cnt = a1 - a0;
-        if (cnt > d.big_cap) {   // more vehicles than the edges can physically hold
+        if (cnt > d.big_cap) {     // more vehicles than the edges can physically hold
             if (threadIdx.x == 0) atomicOr(&d.ctl->err, kErrTileTooBig);
-            continue;
+            return;
         }
         if (cnt <= kTileCapLds) {
             process_tile<kTileNT, kSpread>(d, carve(lds, kTileCapLds), a0, cnt, t, par, acc, wsh4, scp, dq, &smoved);
@@ -1176,6 +1199,34 @@ __device__ inline void tile_step(const Dev& d) {
             mark_big_lanes<kTileNT>(d, edge, a0, a1, t, wsh[0]);
             __syncthreads();                        // wsh is reused by the next tile
         }
+    };
+    // A workgroup's first tile is its index.  With few rounds per step each
+    // later one is G further (G the workgroups).  With many, the imbalance of
+    // tile lengths adds up over the rounds, so the later tiles are split into
+    // kTileGroups groups (tile G + g + j * groups), each handed out by a
+    // counter of its own to the workgroups of index g modulo the groups: a
+    // workgroup whose tiles ran short takes the next, and each counter sees
+    // one workgroup in eight.  The counter is read before the bounds probe,
+    // whose loads its round trip overlaps, and the index is shared after the
+    // probe (which begins with a barrier, so every thread has read the
+    // previous one).
+    const int G = (int)gridDim.x;
+    if (ntile > kTileCtrRounds * G) {
+        const int ng = min(kTileGroups, G);
+        const int grp = (int)blockIdx.x % ng;
+        int* const ctr = tile_counters(d) + (par * kTileGroups + grp) * kTileCtrStride;
+        int k = blockIdx.x;
+        while (k < ntile) {
+            int nk = 0;
+            if (threadIdx.x == 0) nk = G + grp + ng * atomicAdd(ctr, 1);
+            const TileSpan sp = run_tile(k);
+            if (threadIdx.x == 0) snext = nk;
+            do_tile(sp);
+            __syncthreads();                        // snext written
+            k = __builtin_amdgcn_readfirstlane(snext);
+        }
+    } else {
+        for (int k = blockIdx.x; k < ntile; k += G) do_tile(run_tile(k));
     }
     flush_counters_lds(d, acc, shc);
     publish_moved(d, &smoved, t);
