@@ -244,6 +244,46 @@ def test_parity_big_tiles_with_transfers(M, oracle_mod, tmp_path, spread_admissi
     assert np.array_equal(gcnt, ocnt) and np.array_equal(gsum, osum)
 
 
+@pytest.mark.parametrize("g1", [16, 5])
+def test_parity_tile_counters(M, oracle_mod, tmp_path, g1):
+    """Few tile workgroups, set through a schedule cache, so that a step has
+    more rounds of tiles than the threshold above which k_tile_step hands
+    out the tiles after each workgroup's first from its counters: full-size
+    config 2 from the state its demand gives at 08:00 (about 60,000 active,
+    20 or 60 rounds), 100 steps bit for bit with the oracle; with 5
+    workgroups, fewer workgroups than counter groups."""
+    w = W.config2()
+    init, _ = W.loaded_state(w, 10_800, speed_frac=0.4)
+    n_act = int((init["status"] == 1).sum())
+    rounds = -(-n_act // (192 * g1))
+    assert rounds > 8, (n_act, rounds)
+    g = M.Sim(w)
+    sch = g.schedule()
+    p = tmp_path / "sched.txt"
+    p.write_text(f"manta-schedule E={w.net.n_edges} L={int(w.net.lanes.sum())} N={w.n_vehicles} S=1 -> "
+                 f"0 {g1} {sch[2]} {sch[3]}\n")
+    assert g.autotune(str(p))[1] == g1
+    o = oracle_mod.OracleSim(w)
+    g.write_state(init)
+    o.write_state(init["t"], init)
+    t = init["t"]
+    oracle_mod.set_threads(0)
+    try:
+        for cp in (t + 1, t + 2, t + 30, t + 100):
+            g.step(cp - t)
+            o.step(cp - t)
+            t = cp
+            gs, os_ = g.state(), o.state()
+            assert compare_states(gs, os_, f"g1 {g1} step {t}")
+            gc = dict(zip(M.COUNTERS, gs["counters"].tolist()))
+            assert gc == o.counters(), f"step {t}: counters {gc} vs {o.counters()}"
+    finally:
+        oracle_mod.set_threads(1)
+    gsum, gcnt = g.edge_stats()
+    osum, ocnt = o.edge_stats()
+    assert np.array_equal(gcnt, ocnt) and np.array_equal(gsum, osum)
+
+
 def test_parity_scaled_config2(M, oracle_mod):
     """Config 2's recipe on a 30x30 grid + ring with 15,000 vehicles, full 3 h."""
     w = W.scaled_config2(n_vehicles=15000, rows=30, cols=30, n_steps=21600)
